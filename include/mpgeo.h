@@ -1,0 +1,196 @@
+/*
+ * mpgeo.h — C ABI of the MI355X (gfx950) mixed-precision Gaussian log-likelihood library.
+ *
+ * The library evaluates, for n locations s_1..s_n in R^2 and data Z (Section IV-A),
+ *   Sigma_ab = C(||s_a - s_b||; theta)                          Matérn, eq. (1)
+ *   Sigma = L L^T   (tile Cholesky, mixed precision)            Section VI, Algorithm 1
+ *   y = L^-1 Z,  logdet = 2 sum log L_ii,  quad = y^T y
+ *   loglik = -n/2 log(2 pi) - logdet/2 - quad/2                 eq. (2)
+ * and, optionally, simple-kriging predictions at new sites from the same factor.
+ *
+ * Precision map (Algorithm 1, with its "diag_thick" = band64 + 1): the matrix is split
+ * into tiles of tile x tile entries; tile (i, j), i >= j, is stored and updated in FP64
+ * when i - j <= band64 and in FP32 otherwise.  An operation runs in the precision of the
+ * tile it writes: FP64 inputs of an FP32 operation are rounded to nearest-even, FP32
+ * inputs of an FP64 operation are promoted exactly.  Diagonal tiles (and so the
+ * log-determinant) are always FP64.  The forward solve accumulates in FP64.
+ *
+ * Conventions for every entry point:
+ *  - Return value: an mpgeo_status code; MPGEO_OK (0) on success.
+ *  - Ownership: the caller owns every pointer it passes and keeps it valid for the call;
+ *    the library owns the device memory inside contexts and datasets and frees it on
+ *    destroy.  Pointer arguments are host memory unless MPGEO_INPUT_DEVICE is set in the
+ *    flags of the call (or of the dataset), in which case they are device pointers on
+ *    the context's device (for example torch's tensor.data_ptr()).
+ *  - Layout: locations are n x 2 row-major float64 (x, y); vectors are float64.
+ *  - Ordering: all calls are ordered on the context's HIP stream and are synchronous at
+ *    return (results filled in).  A context is used by one host thread at a time.
+ *  - Errors: on a non-OK return the outputs are undefined except mpgeo_result.info.
+ *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 != -1, lowp != 0, a
+ *    non-finite or non-positive theta component, a null pointer that is not nullable.
+ *    MPGEO_E_NOT_SPD: a non-positive (or NaN) pivot; info = its 0-based global column in
+ *    the (Morton-ordered) matrix.  MPGEO_E_NOMEM: device allocation failed.
+ *    MPGEO_E_DEVICE: a HIP runtime error.  MPGEO_E_UNSUPPORTED: a feature not built.
+ */
+#ifndef MPGEO_H
+#define MPGEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPGEO_OK = 0,
+    MPGEO_E_ARG = 1,
+    MPGEO_E_NOT_SPD = 2,
+    MPGEO_E_NOMEM = 3,
+    MPGEO_E_DEVICE = 4,
+    MPGEO_E_UNSUPPORTED = 5
+} mpgeo_status;
+
+/* Flags (mpgeo_plan.flags and dataset flags). */
+#define MPGEO_ORDER_MORTON 1u   /* reorder locations (and Z) by Z-order key before tiling */
+#define MPGEO_INPUT_DEVICE 2u   /* pointer arguments are device pointers */
+#define MPGEO_TIMING       4u   /* record HIP events per kernel launch (see mpgeo_ctx_kernel_stats) */
+
+/* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
+ * (smoothness); all must be finite and > 0. */
+typedef struct {
+    double sigma2;
+    double beta;
+    double nu;
+} mpgeo_theta;
+
+/* Tiling and precision plan.
+ *  tile:   tile size nb (1..512); the matrix has p = ceil(n / nb) tile rows.
+ *  band64: b >= 0: tile (i, j) is FP64 iff i - j <= b; -1: every tile FP64.
+ *  band32: must be -1 (FP32 from band64 + 1 to the edge of the matrix).
+ *  lowp:   must be 0 (no third precision tier).
+ *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING. */
+typedef struct {
+    int32_t tile;
+    int32_t band64;
+    int32_t band32;
+    int32_t lowp;
+    uint32_t flags;
+} mpgeo_plan;
+
+/* Result of one evaluation.  loglik, logdet (natural log of det Sigma) and quad
+ * (Z^T Sigma^-1 Z) are those of eq. (2).  info: -1, or the failing global column when
+ * the status is MPGEO_E_NOT_SPD.  Times are seconds measured with HIP events on the
+ * context stream: covariance generation, factorisation (including the fused forward
+ * solve), final reduction, and the whole call. */
+typedef struct {
+    double loglik;
+    double logdet;
+    double quad;
+    int64_t info;
+    double t_covgen;
+    double t_factor;
+    double t_solve;
+    double t_total;
+} mpgeo_result;
+
+/* Per-kernel-class launch statistics accumulated while MPGEO_TIMING is set. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double seconds;     /* sum of HIP-event durations of those launches */
+    double flops;       /* algorithmic flops of those launches */
+    double bytes;       /* algorithmic bytes (read + written) of those launches */
+} mpgeo_kernel_stat;
+
+typedef struct mpgeo_ctx mpgeo_ctx;
+typedef struct mpgeo_dataset mpgeo_dataset;
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t; NULL: the library creates its own stream).  *out receives the handle. */
+int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream);
+
+/* Free a context and its cached device memory.  NULL is accepted. */
+int mpgeo_ctx_destroy(mpgeo_ctx *ctx);
+
+/* Kernel statistics since the last reset: writes up to `max` entries to `out` and the
+ * number of kernel classes to *count.  Reset clears them. */
+int mpgeo_ctx_kernel_stats(mpgeo_ctx *ctx, mpgeo_kernel_stat *out, int max, int *count);
+int mpgeo_ctx_reset_stats(mpgeo_ctx *ctx);
+
+/* One-shot log-likelihood, eq. (2): orders the n locations (MPGEO_ORDER_MORTON), builds
+ * the Matérn tiles, factors them with the plan's precision map, solves, and reduces.
+ * locs: n x 2, z: n (host, or device with MPGEO_INPUT_DEVICE); not modified.  Device
+ * workspace is cached in the context and reused by later calls of the same size. */
+int mpgeo_loglik(mpgeo_ctx *ctx, int64_t n, const double *locs, const double *z,
+                 mpgeo_theta theta, mpgeo_plan plan, mpgeo_result *out);
+
+/* Resident dataset: copies locations and z to the device once, Morton-orders them when
+ * flags has MPGEO_ORDER_MORTON, and keeps tile memory across evaluations (the
+ * maximum-likelihood loop of Section IV-C changes only theta). */
+int mpgeo_dataset_create(mpgeo_ctx *ctx, int64_t n, const double *locs, const double *z,
+                         uint32_t flags, mpgeo_dataset **out);
+int mpgeo_dataset_destroy(mpgeo_dataset *ds);
+
+/* eq. (2) at theta for the resident dataset.  plan.flags may add MPGEO_TIMING; its
+ * ordering and input flags are ignored (fixed at dataset creation). */
+int mpgeo_dataset_loglik(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
+                         mpgeo_result *out);
+
+/* Simple-kriging prediction (Section VIII-D) at m new sites from the factor of the last
+ * successful mpgeo_dataset_loglik call: pred = Sigma(new, S) Sigma^-1 Z, and, when var is
+ * not NULL, var = theta1 - Sigma(new, S) Sigma^-1 Sigma(S, new).  new_locs: m x 2;
+ * pred, var: m entries in the order of new_locs; host or device like the dataset.
+ * MPGEO_E_ARG if no factor is available. */
+int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs,
+                        double *pred, double *var);
+
+/* Inspection (tests): copy to HOST memory
+ *  perm:   n int64, the ordering used (ordered position -> caller index);
+ *  matrix: the n x n lower triangle (column-major, ld >= n) of the tiles as they are now:
+ *          after mpgeo_dataset_covariance the tier-rounded Sigma, after a loglik the
+ *          factor L; FP32 tiles promoted; the strict upper triangle is left untouched;
+ *  y:      the forward-solve vector L^-1 Z (n entries, ordered). */
+int mpgeo_dataset_perm(mpgeo_dataset *ds, int64_t *perm);
+int mpgeo_dataset_covariance(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan);
+int mpgeo_dataset_matrix(mpgeo_dataset *ds, double *out, int64_t ld);
+int mpgeo_dataset_solution(mpgeo_dataset *ds, double *y);
+
+/* Sampled entries of the stored lower triangle (tests at sizes where a dense copy does
+ * not fit): out[q] = M[max(r, c)][min(r, c)] for r = rows[q], c = cols[q] (0-based indices
+ * in the ordered matrix), where M is the tier-rounded Sigma after mpgeo_dataset_covariance
+ * or the factor L after a loglik (pass r >= c for L).  rows, cols, out: count entries in
+ * HOST memory.  MPGEO_E_ARG for an index outside [0, n). */
+int mpgeo_dataset_entries(mpgeo_dataset *ds, int64_t count, const int64_t *rows,
+                          const int64_t *cols, double *out);
+
+/* Maximum-likelihood estimate of theta (Section IV-C: maximise eq. (2)) with a
+ * Nelder-Mead simplex on u = log(theta): reflection 1, expansion 2, contraction 1/2,
+ * shrink 1/2, initial steps of 0.1 in each log-parameter from `start`; theta is clamped
+ * to [0.01, 10] x [0.001, 2] x [0.1, 3]; a point whose matrix is not positive definite
+ * scores -infinity.  Stops when the simplex spans less than xtol (log units, max-norm),
+ * when its log-likelihoods differ by less than ftol * |best|, or after max_evals
+ * evaluations.  Writes the best theta, its log-likelihood, and the evaluation and
+ * iteration counts (any output pointer may be NULL). */
+int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
+                      double ftol, int32_t max_evals, mpgeo_theta *theta_hat,
+                      double *loglik_hat, int32_t *evals, int32_t *iters);
+
+/* Algorithm 1 on a caller-given symmetric positive-definite matrix: A is n x n,
+ * column-major with leading dimension lda >= n, only its lower triangle is read; z
+ * (n entries) is optional (NULL: quad = 0 and loglik uses quad = 0).  No reordering.
+ * Fills logdet, quad and loglik as for eq. (2). */
+int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda,
+                       const double *z, mpgeo_plan plan, mpgeo_result *out);
+
+/* HBM bytes of the lower-triangle tiles for n and plan (admission control). */
+size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan);
+
+/* Static text for a status code. */
+const char *mpgeo_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGEO_H */

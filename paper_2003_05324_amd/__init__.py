@@ -1,0 +1,295 @@
+"""Python binding of libmpgeo, the MI355X mixed-precision Gaussian log-likelihood library.
+
+Argument marshalling only: every step of the computation runs in the HIP library.
+The functions named mpgeo_* mirror the C-ABI of include/mpgeo.h one to one; Context
+and Dataset are small conveniences around them.  Host inputs are numpy float64
+arrays; device inputs are torch tensors on the context's device (their data
+pointers are passed with MPGEO_INPUT_DEVICE).  torch is imported first so that the
+library binds to the same HIP runtime as torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpgeo.so")
+
+MPGEO_OK, MPGEO_E_ARG, MPGEO_E_NOT_SPD, MPGEO_E_NOMEM, MPGEO_E_DEVICE, MPGEO_E_UNSUPPORTED = range(6)
+MPGEO_ORDER_MORTON = 1
+MPGEO_INPUT_DEVICE = 2
+MPGEO_TIMING = 4
+
+EXPORTED = (
+    "mpgeo_ctx_create", "mpgeo_ctx_destroy", "mpgeo_ctx_kernel_stats", "mpgeo_ctx_reset_stats",
+    "mpgeo_loglik", "mpgeo_dataset_create", "mpgeo_dataset_destroy", "mpgeo_dataset_loglik",
+    "mpgeo_dataset_krige", "mpgeo_dataset_perm", "mpgeo_dataset_covariance",
+    "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
+    "mpgeo_footprint_bytes", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
+)
+
+
+class Theta(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_double), ("beta", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("band64", ctypes.c_int32), ("band32", ctypes.c_int32),
+                ("lowp", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("loglik", ctypes.c_double), ("logdet", ctypes.c_double), ("quad", ctypes.c_double),
+                ("info", ctypes.c_int64), ("t_covgen", ctypes.c_double),
+                ("t_factor", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("t_total", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class MpgeoError(RuntimeError):
+    def __init__(self, status: int, what: str, info: int = -1):
+        self.status = status
+        self.info = info
+        super().__init__(f"{what}: {status_string(status)} (status {status}, info {info})")
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2003_05324_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    sig = {
+        "mpgeo_ctx_create": ([ctypes.POINTER(P), ctypes.c_int, P], ctypes.c_int),
+        "mpgeo_ctx_destroy": ([P], ctypes.c_int),
+        "mpgeo_ctx_kernel_stats": ([P, ctypes.POINTER(KernelStat), ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "mpgeo_ctx_reset_stats": ([P], ctypes.c_int),
+        "mpgeo_loglik": ([P, I64, P, P, Theta, Plan, ctypes.POINTER(Result)], ctypes.c_int),
+        "mpgeo_dataset_create": ([P, I64, P, P, U32, ctypes.POINTER(P)], ctypes.c_int),
+        "mpgeo_dataset_destroy": ([P], ctypes.c_int),
+        "mpgeo_dataset_loglik": ([P, Theta, Plan, ctypes.POINTER(Result)], ctypes.c_int),
+        "mpgeo_dataset_krige": ([P, I64, P, P, P], ctypes.c_int),
+        "mpgeo_dataset_perm": ([P, P], ctypes.c_int),
+        "mpgeo_dataset_covariance": ([P, Theta, Plan], ctypes.c_int),
+        "mpgeo_dataset_matrix": ([P, P, I64], ctypes.c_int),
+        "mpgeo_dataset_solution": ([P, P], ctypes.c_int),
+        "mpgeo_factor_dense": ([P, I64, P, I64, P, Plan, ctypes.POINTER(Result)], ctypes.c_int),
+        "mpgeo_footprint_bytes": ([I64, Plan], ctypes.c_size_t),
+        "mpgeo_dataset_entries": ([P, I64, P, P, P], ctypes.c_int),
+        "mpgeo_dataset_mle": ([P, Theta, Plan, D, D, I32, ctypes.POINTER(Theta),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
+                               ctypes.POINTER(I32)], ctypes.c_int),
+        "mpgeo_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    del I32, D
+    return lib
+
+
+LIB = _load()
+
+
+def status_string(status: int) -> str:
+    return LIB.mpgeo_status_string(status).decode()
+
+
+def _check(status: int, what: str, info: int = -1) -> None:
+    if status != MPGEO_OK:
+        raise MpgeoError(status, what, info)
+
+
+def _host_f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def make_plan(tile: int, band64: int, flags: int = 0) -> Plan:
+    return Plan(tile=tile, band64=band64, band32=-1, lowp=0, flags=flags)
+
+
+def mpgeo_footprint_bytes(n: int, tile: int, band64: int) -> int:
+    return int(LIB.mpgeo_footprint_bytes(n, make_plan(tile, band64)))
+
+
+class Context:
+    """A library context on one device, ordered on a HIP stream (default: torch's current)."""
+
+    def __init__(self, device: int = 0, stream: Optional["torch.cuda.Stream"] = None):
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        _check(LIB.mpgeo_ctx_create(ctypes.byref(handle), device, ctypes.c_void_p(stream.cuda_stream)),
+               "mpgeo_ctx_create")
+        self.handle = handle
+
+    def close(self) -> None:
+        if self.handle:
+            LIB.mpgeo_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
+               morton: bool = True, timing: bool = False) -> dict:
+        """One-shot eq. (2): ordering, covariance tiles, factor, solve, reduction."""
+        dev = isinstance(locs, torch.Tensor)
+        if not dev:
+            locs, z = _host_f64(locs), _host_f64(z)
+        flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0) | \
+                (MPGEO_TIMING if timing else 0)
+        res = Result()
+        st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
+                              make_plan(tile, band64, flags), ctypes.byref(res))
+        _check(st, "mpgeo_loglik", res.info)
+        return res.as_dict()
+
+    def factor_dense(self, a: np.ndarray, z, tile: int, band64: int) -> dict:
+        """Algorithm 1 on a given symmetric positive-definite matrix (lower triangle read)."""
+        a = np.asfortranarray(np.asarray(a, dtype=np.float64))
+        n = a.shape[0]
+        zz = None if z is None else _host_f64(z)
+        res = Result()
+        st = LIB.mpgeo_factor_dense(self.handle, n, a.ctypes.data, n, _ptr(zz),
+                                    make_plan(tile, band64), ctypes.byref(res))
+        _check(st, "mpgeo_factor_dense", res.info)
+        return res.as_dict()
+
+    def kernel_stats(self) -> list:
+        arr = (KernelStat * 32)()
+        count = ctypes.c_int()
+        _check(LIB.mpgeo_ctx_kernel_stats(self.handle, arr, 32, ctypes.byref(count)),
+               "mpgeo_ctx_kernel_stats")
+        return [{"name": s.name.decode(), "launches": s.launches, "seconds": s.seconds,
+                 "flops": s.flops, "bytes": s.bytes} for s in arr[:count.value]]
+
+    def reset_stats(self) -> None:
+        _check(LIB.mpgeo_ctx_reset_stats(self.handle), "mpgeo_ctx_reset_stats")
+
+
+class Dataset:
+    """Locations and data resident on the device, Morton-ordered once."""
+
+    def __init__(self, ctx: Context, locs, z=None, morton: bool = True):
+        self.ctx = ctx
+        dev = isinstance(locs, torch.Tensor)
+        if not dev:
+            locs = _host_f64(locs)
+            z = None if z is None else _host_f64(z)
+        self.device_io = dev
+        self.n = int(locs.shape[0])
+        flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0)
+        handle = ctypes.c_void_p()
+        _check(LIB.mpgeo_dataset_create(ctx.handle, self.n, _ptr(locs), _ptr(z), flags,
+                                        ctypes.byref(handle)), "mpgeo_dataset_create")
+        self.handle = handle
+
+    def close(self) -> None:
+        if self.handle:
+            LIB.mpgeo_dataset_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False) -> dict:
+        res = Result()
+        st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
+                                      make_plan(tile, band64, MPGEO_TIMING if timing else 0),
+                                      ctypes.byref(res))
+        _check(st, "mpgeo_dataset_loglik", res.info)
+        return res.as_dict()
+
+    def try_loglik(self, theta: Sequence[float], tile: int, band64: int) -> tuple:
+        """(status, result dict) without raising (for optimisers that meet non-SPD points)."""
+        res = Result()
+        st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta), make_plan(tile, band64),
+                                      ctypes.byref(res))
+        return st, res.as_dict()
+
+    def krige(self, new_locs, variance: bool = False):
+        if self.device_io:
+            m = int(new_locs.shape[0])
+            pred = torch.empty(m, dtype=torch.float64, device=new_locs.device)
+            var = torch.empty(m, dtype=torch.float64, device=new_locs.device) if variance else None
+        else:
+            new_locs = _host_f64(new_locs)
+            m = new_locs.shape[0]
+            pred = np.empty(m)
+            var = np.empty(m) if variance else None
+        _check(LIB.mpgeo_dataset_krige(self.handle, m, _ptr(new_locs), _ptr(pred), _ptr(var)),
+               "mpgeo_dataset_krige")
+        return (pred, var) if variance else pred
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int64)
+        _check(LIB.mpgeo_dataset_perm(self.handle, out.ctypes.data), "mpgeo_dataset_perm")
+        return out
+
+    def covariance(self, theta: Sequence[float], tile: int, band64: int) -> np.ndarray:
+        """Sigma as stored in its tiles (tier-rounded), lower triangle, ordered."""
+        _check(LIB.mpgeo_dataset_covariance(self.handle, Theta(*theta), make_plan(tile, band64)),
+               "mpgeo_dataset_covariance")
+        return self.matrix()
+
+    def matrix(self) -> np.ndarray:
+        out = np.zeros((self.n, self.n), order="F")
+        _check(LIB.mpgeo_dataset_matrix(self.handle, out.ctypes.data, self.n), "mpgeo_dataset_matrix")
+        return out
+
+    def entries(self, rows, cols) -> np.ndarray:
+        """Stored lower-triangle entries M[max(r, c), min(r, c)] at ordered indices."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.empty(rows.shape[0])
+        _check(LIB.mpgeo_dataset_entries(self.handle, rows.shape[0], rows.ctypes.data,
+                                         cols.ctypes.data, out.ctypes.data), "mpgeo_dataset_entries")
+        return out
+
+    def mle(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
+            ftol: float = 1e-9, max_evals: int = 1000) -> dict:
+        """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2))."""
+        th = Theta()
+        ll = ctypes.c_double()
+        ev = ctypes.c_int32()
+        it = ctypes.c_int32()
+        _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), make_plan(tile, band64), xtol, ftol,
+                                     max_evals, ctypes.byref(th), ctypes.byref(ll), ctypes.byref(ev),
+                                     ctypes.byref(it)), "mpgeo_dataset_mle")
+        return {"theta": (th.sigma2, th.beta, th.nu), "loglik": ll.value, "evals": ev.value,
+                "iters": it.value}
+
+    def solution(self) -> np.ndarray:
+        out = np.empty(self.n)
+        _check(LIB.mpgeo_dataset_solution(self.handle, out.ctypes.data), "mpgeo_dataset_solution")
+        return out

@@ -1,0 +1,961 @@
+// C-ABI entry points and the step-ordered tile engine of the mixed-precision
+// log-likelihood (eq. (2) with the tile Cholesky of Algorithm 1).
+//
+// Per evaluation, on the context stream:
+//   order (Z-order keys + sort)  ->  Matérn tiles in their tier precision
+//   for k = 0 .. p-1:
+//     POTRF(k) + L_kk^-1 + y_k                       (FP64, one workgroup)
+//     panel X_i = A_ik L_kk^-T: FP64 band tiles, FP32 far tiles (matrix cores)
+//     r_i -= X_i y_k and X_i back into its storage tile
+//     trailing A_ij -= X_i X_j^T: FP64 launch for band tiles, FP32 launch for far tiles
+//   reduce logdet and quad, assemble eq. (2)
+// Tiles are kept resident in HBM; no host transfer happens inside the loop.
+#include "common.h"
+#include "../../include/mpgeo.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace mpgeo;
+
+namespace {
+
+int status_from(hipError_t e) {
+    if (e == hipSuccess) return MPGEO_OK;
+    return e == hipErrorOutOfMemory ? MPGEO_E_NOMEM : MPGEO_E_DEVICE;
+}
+
+#define MPGEO_HIP(expr)                         \
+    do {                                        \
+        hipError_t _e = (expr);                 \
+        if (_e != hipSuccess) {                 \
+            (void)hipGetLastError();            \
+            return status_from(_e);             \
+        }                                       \
+    } while (0)
+
+#define MPGEO_TRY(expr)                         \
+    do {                                        \
+        int _s = (expr);                        \
+        if (_s != MPGEO_OK) return _s;          \
+    } while (0)
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t b) {
+        if (b <= bytes && ptr) return MPGEO_OK;
+        release();
+        if (b == 0) return MPGEO_OK;
+        hipError_t e = hipMalloc(&ptr, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ptr = nullptr;
+            bytes = 0;
+            return MPGEO_E_NOMEM;
+        }
+        bytes = b;
+        return MPGEO_OK;
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Tiles, precision tiers and per-step work lists for one (n, nb, band).
+struct Layout {
+    int64_t n = 0;
+    int nb = 0, nbp = 0, p = 0, band = -2;
+    std::vector<int64_t> off;
+    std::vector<TileIJ> all, list64, list32;
+    std::vector<int64_t> pre64, pre32;        // entries of each list with j > k (step k)
+    std::vector<double> flops64, flops32;     // algorithmic flops of each step's update
+    std::vector<double> trsm64_flops, trsm32_flops;
+    int64_t n64 = 0, n32 = 0;                 // tiles per tier
+
+    bool same(int64_t n_, int nb_, int band_) const { return n == n_ && nb == nb_ && band == band_; }
+
+    int64_t rows(int i) const { return std::min<int64_t>(nb, n - (int64_t)i * nb); }
+
+    void build(int64_t n_, int nb_, int band64) {
+        n = n_;
+        nb = nb_;
+        nbp = (nb + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
+        p = (int)((n + nb - 1) / nb);
+        band = (band64 < 0 || band64 > p) ? p : band64;
+        const int64_t nt = (int64_t)p * (p + 1) / 2;
+        off.assign(nt, 0);
+        all.clear();
+        list64.clear();
+        list32.clear();
+        n64 = n32 = 0;
+        const int64_t tile_elems = (int64_t)nbp * nbp;
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j <= i; ++j) {
+                all.push_back({i, j});
+                if (i - j <= band) off[tri_index(i, j)] = (n64++) * tile_elems;
+                else off[tri_index(i, j)] = (n32++) * tile_elems;
+            }
+        // update lists: columns j = p-1 down to 1, rows ascending; the prefix with j > k is
+        // exactly the trailing work of step k
+        for (int j = p - 1; j >= 1; --j)
+            for (int i = j; i < p; ++i) {
+                if (i - j <= band) list64.push_back({i, j});
+                else list32.push_back({i, j});
+            }
+        pre64.assign(p, 0);
+        pre32.assign(p, 0);
+        flops64.assign(p, 0.0);
+        flops32.assign(p, 0.0);
+        trsm64_flops.assign(p, 0.0);
+        trsm32_flops.assign(p, 0.0);
+        std::vector<double> col64(p, 0.0), col32(p, 0.0);
+        std::vector<int64_t> cnt64(p, 0), cnt32(p, 0);
+        for (int j = 1; j < p; ++j)
+            for (int i = j; i < p; ++i) {
+                const double f = (i == j) ? (double)rows(j) * (rows(j) + 1) : 2.0 * rows(i) * rows(j);
+                if (i - j <= band) {
+                    col64[j] += f;
+                    cnt64[j]++;
+                } else {
+                    col32[j] += f;
+                    cnt32[j]++;
+                }
+            }
+        double s64 = 0, s32 = 0;
+        int64_t c64 = 0, c32 = 0;
+        for (int k = p - 1; k >= 0; --k) {
+            pre64[k] = c64;
+            pre32[k] = c32;
+            flops64[k] = s64 * rows(k);
+            flops32[k] = s32 * rows(k);
+            s64 += col64[k];
+            s32 += col32[k];
+            c64 += cnt64[k];
+            c32 += cnt32[k];
+        }
+        for (int k = 0; k < p; ++k)
+            for (int i = k + 1; i < p; ++i) {
+                const double f = (double)rows(i) * rows(k) * rows(k);   // triangular solve
+                if (i - k <= band) trsm64_flops[k] += f;
+                else trsm32_flops[k] += f;
+            }
+    }
+};
+
+enum StatClass {
+    kStatCovgen, kStatOrder, kStatPotrf, kStatTrsm64, kStatTrsm32, kStatPanel, kStatUpdate64,
+    kStatUpdate32, kStatFinal, kStatCount
+};
+const char *kStatNames[kStatCount] = {"covgen", "morton_order", "potrf_tile", "trsm_fp64",
+                                      "trsm_fp32", "panel_solve", "update_fp64", "update_fp32",
+                                      "finalize"};
+
+}  // namespace
+
+struct mpgeo_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    struct Pending {
+        int cls;
+        hipEvent_t a, b;
+        double flops, bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+    mpgeo_kernel_stat stats[kStatCount];
+    bool timing = false;
+    mpgeo_dataset *scratch_ds = nullptr;   // workspace of the one-shot calls
+
+    hipEvent_t take_event() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+    // launch wrapper: events around a launch when timing is on
+    template <class F> void timed(int cls, double flops, double bytes, F &&launch) {
+        if (!timing) {
+            launch();
+            return;
+        }
+        hipEvent_t a = take_event(), b = take_event();
+        if (!a || !b) {
+            launch();
+            return;
+        }
+        (void)hipEventRecord(a, stream);
+        launch();
+        (void)hipEventRecord(b, stream);
+        pending.push_back({cls, a, b, flops, bytes});
+    }
+    void collect() {
+        for (auto &pl : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pl.a, pl.b) == hipSuccess) {
+                stats[pl.cls].launches += 1;
+                stats[pl.cls].seconds += ms * 1e-3;
+                stats[pl.cls].flops += pl.flops;
+                stats[pl.cls].bytes += pl.bytes;
+            } else {
+                (void)hipGetLastError();
+            }
+            spare.push_back(pl.a);
+            spare.push_back(pl.b);
+        }
+        pending.clear();
+    }
+    void reset_stats() {
+        for (int c = 0; c < kStatCount; ++c) {
+            std::memset(&stats[c], 0, sizeof(stats[c]));
+            std::strncpy(stats[c].name, kStatNames[c], sizeof(stats[c].name) - 1);
+        }
+    }
+};
+
+struct mpgeo_dataset {
+    mpgeo_ctx *ctx = nullptr;
+    int64_t n = 0;
+    uint32_t flags = 0;
+    Layout layout;
+    // ordered inputs
+    DevBuf locs, z, perm, keys, locs_in, z_in;
+    // tiles and work buffers
+    DevBuf pool64, pool32, off, all, list64, list32;
+    DevBuf p64, p32, linv, linv32;
+    DevBuf r, y, parts, info, result;
+    DevBuf tmp_a, tmp_b, tmp_c;
+    bool has_factor = false;
+    mpgeo_theta theta{};
+};
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_theta(const mpgeo_theta &t) {
+    return (finite_pos(t.sigma2) && finite_pos(t.beta) && finite_pos(t.nu)) ? MPGEO_OK : MPGEO_E_ARG;
+}
+
+int check_plan(const mpgeo_plan &pl) {
+    if (pl.tile < 1 || pl.tile > kMaxTile) return MPGEO_E_ARG;
+    if (pl.band64 < -1) return MPGEO_E_ARG;
+    if (pl.band32 != -1 || pl.lowp != 0) return MPGEO_E_ARG;
+    return MPGEO_OK;
+}
+
+TileMap tile_map(const mpgeo_dataset *ds) {
+    const Layout &L = ds->layout;
+    TileMap m;
+    m.off = ds->off.as<int64_t>();
+    m.pool64 = ds->pool64.as<double>();
+    m.pool32 = ds->pool32.as<float>();
+    m.band = L.band;
+    m.nbp = L.nbp;
+    m.nb = L.nb;
+    m.p = L.p;
+    m.n = L.n;
+    return m;
+}
+
+// Allocate tiles and tables for (n, plan) and upload the tables.
+int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
+    Layout &L = ds->layout;
+    const int band = pl.band64;
+    const int64_t p_new = (ds->n + pl.tile - 1) / pl.tile;
+    const int band_eff = (band < 0 || band > p_new) ? (int)p_new : band;
+    if (L.same(ds->n, pl.tile, band_eff) && ds->off.ptr) return MPGEO_OK;
+    L.build(ds->n, pl.tile, band);
+    ds->has_factor = false;
+    const size_t te = (size_t)L.nbp * L.nbp;
+    MPGEO_TRY(ds->pool64.ensure(std::max<size_t>(1, (size_t)L.n64 * te * sizeof(double))));
+    MPGEO_TRY(ds->pool32.ensure(std::max<size_t>(1, (size_t)L.n32 * te * sizeof(float))));
+    MPGEO_TRY(ds->off.ensure(L.off.size() * sizeof(int64_t)));
+    MPGEO_TRY(ds->all.ensure(std::max<size_t>(1, L.all.size()) * sizeof(TileIJ)));
+    MPGEO_TRY(ds->list64.ensure(std::max<size_t>(1, L.list64.size()) * sizeof(TileIJ)));
+    MPGEO_TRY(ds->list32.ensure(std::max<size_t>(1, L.list32.size()) * sizeof(TileIJ)));
+    MPGEO_TRY(ds->p64.ensure((size_t)L.p * te * sizeof(double)));
+    MPGEO_TRY(ds->p32.ensure((size_t)L.p * te * sizeof(float)));
+    MPGEO_TRY(ds->linv.ensure((size_t)L.p * te * sizeof(double)));
+    MPGEO_TRY(ds->linv32.ensure(te * sizeof(float)));
+    const size_t vec = (size_t)L.p * L.nbp * sizeof(double);
+    MPGEO_TRY(ds->r.ensure(vec));
+    MPGEO_TRY(ds->y.ensure(vec));
+    MPGEO_TRY(ds->parts.ensure(2 * (size_t)L.p * sizeof(double)));
+    MPGEO_TRY(ds->info.ensure(sizeof(unsigned long long)));
+    MPGEO_TRY(ds->result.ensure(4 * sizeof(double)));
+    hipStream_t s = ds->ctx->stream;
+    MPGEO_HIP(hipMemcpyAsync(ds->off.ptr, L.off.data(), L.off.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
+    MPGEO_HIP(hipMemcpyAsync(ds->all.ptr, L.all.data(), L.all.size() * sizeof(TileIJ),
+                             hipMemcpyHostToDevice, s));
+    if (!L.list64.empty())
+        MPGEO_HIP(hipMemcpyAsync(ds->list64.ptr, L.list64.data(), L.list64.size() * sizeof(TileIJ),
+                                 hipMemcpyHostToDevice, s));
+    if (!L.list32.empty())
+        MPGEO_HIP(hipMemcpyAsync(ds->list32.ptr, L.list32.data(), L.list32.size() * sizeof(TileIJ),
+                                 hipMemcpyHostToDevice, s));
+    MPGEO_HIP(hipStreamSynchronize(s));   // host vectors may change with the next build
+    return MPGEO_OK;
+}
+
+// Copy caller inputs to the device (if on the host), order them, keep perm.
+int load_inputs(mpgeo_dataset *ds, const double *locs, const double *z, uint32_t flags) {
+    mpgeo_ctx *ctx = ds->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t n = ds->n;
+    MPGEO_TRY(ds->locs.ensure((size_t)n * 2 * sizeof(double)));
+    MPGEO_TRY(ds->z.ensure((size_t)n * sizeof(double)));
+    MPGEO_TRY(ds->perm.ensure((size_t)n * sizeof(int64_t)));
+    const double *dl = locs;
+    const double *dz = z;
+    if (!(flags & MPGEO_INPUT_DEVICE)) {
+        MPGEO_TRY(ds->locs_in.ensure((size_t)n * 2 * sizeof(double)));
+        MPGEO_HIP(hipMemcpyAsync(ds->locs_in.ptr, locs, (size_t)n * 2 * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+        dl = ds->locs_in.as<double>();
+        if (z) {
+            MPGEO_TRY(ds->z_in.ensure((size_t)n * sizeof(double)));
+            MPGEO_HIP(hipMemcpyAsync(ds->z_in.ptr, z, (size_t)n * sizeof(double),
+                                     hipMemcpyHostToDevice, s));
+            dz = ds->z_in.as<double>();
+        }
+    }
+    if (flags & MPGEO_ORDER_MORTON) {
+        int64_t n2 = 1024;
+        while (n2 < n) n2 *= 2;
+        MPGEO_TRY(ds->keys.ensure((size_t)n2 * sizeof(uint64_t)));
+        ctx->timed(kStatOrder, 0.0, (double)n * 40.0, [&] {
+            launch_morton_order(dl, dz, n, ds->keys.as<uint64_t>(), n2, ds->locs.as<double>(),
+                                dz ? ds->z.as<double>() : nullptr, ds->perm.as<int64_t>(), s);
+        });
+        MPGEO_HIP(hipGetLastError());
+    } else {
+        MPGEO_HIP(hipMemcpyAsync(ds->locs.ptr, dl, (size_t)n * 2 * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+        if (dz)
+            MPGEO_HIP(hipMemcpyAsync(ds->z.ptr, dz, (size_t)n * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s));
+        std::vector<int64_t> id(n);
+        for (int64_t i = 0; i < n; ++i) id[i] = i;
+        MPGEO_HIP(hipMemcpyAsync(ds->perm.ptr, id.data(), (size_t)n * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipStreamSynchronize(s));
+    }
+    if (!z) MPGEO_HIP(hipMemsetAsync(ds->z.ptr, 0, (size_t)n * sizeof(double), s));
+    return MPGEO_OK;
+}
+
+int run_covgen(mpgeo_dataset *ds, const mpgeo_theta &th) {
+    mpgeo_ctx *ctx = ds->ctx;
+    const Layout &L = ds->layout;
+    const MaternParams mp = make_matern_params(th.sigma2, th.beta, th.nu);
+    const TileMap map = tile_map(ds);
+    const double evals = (double)L.n * (L.n + 1) / 2.0;
+    const double bytes = (double)L.n64 * L.nb * L.nb * 8.0 + (double)L.n32 * L.nb * L.nb * 4.0;
+    ctx->timed(kStatCovgen, evals, bytes, [&] {
+        launch_covgen(map, ds->locs.as<double>(), ds->all.as<TileIJ>(), (int64_t)L.all.size(), mp,
+                      ctx->stream);
+    });
+    MPGEO_HIP(hipGetLastError());
+    return MPGEO_OK;
+}
+
+// Factor the resident tiles, fused with the forward solve of z, then reduce.
+int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
+    mpgeo_ctx *ctx = ds->ctx;
+    hipStream_t s = ctx->stream;
+    const Layout &L = ds->layout;
+    const TileMap map = tile_map(ds);
+    const int nbp = L.nbp, p = L.p;
+    const size_t te = (size_t)nbp * nbp;
+    double *r = ds->r.as<double>();
+    double *y = ds->y.as<double>();
+    double *logdet_part = ds->parts.as<double>();
+    double *quad_part = logdet_part + p;
+    unsigned long long *info = ds->info.as<unsigned long long>();
+    MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s));
+    launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s);
+    double *p64 = ds->p64.as<double>();
+    float *p32 = ds->p32.as<float>();
+    const double nbd = L.nb;
+    for (int k = 0; k < p; ++k) {
+        PotrfArgs pa;
+        pa.a = ds->pool64.as<double>() + L.off[tri_index(k, k)];
+        pa.linv = ds->linv.as<double>() + (int64_t)k * te;
+        pa.linv32 = ds->linv32.as<float>();
+        pa.r = r + (int64_t)k * nbp;
+        pa.y = y + (int64_t)k * nbp;
+        pa.logdet_part = logdet_part + k;
+        pa.quad_part = quad_part + k;
+        pa.info = info;
+        pa.col_base = (int64_t)k * L.nb;
+        pa.nb = L.nb;
+        pa.nbp = nbp;
+        const double rk = (double)L.rows(k);
+        ctx->timed(kStatPotrf, rk * rk * rk / 3.0, rk * rk * 8.0 * 3.0,
+                   [&] { launch_potrf(pa, s); });
+        if (k + 1 < p) {
+            const int n64 = std::min(L.band, p - 1 - k);
+            const int first32 = k + L.band + 1;
+            const int n32 = first32 < p ? p - first32 : 0;
+            if (n64 > 0)
+                ctx->timed(kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
+                    launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, s);
+                });
+            if (n32 > 0)
+                ctx->timed(kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
+                    launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, s);
+                });
+            ctx->timed(kStatPanel, 2.0 * (p - 1 - k) * nbd * nbd, (double)(p - 1 - k) * nbd * nbd * 16.0,
+                       [&] { launch_panel_solve(map, k, p64, pa.y, r, s); });
+            const int64_t c64 = L.pre64[k], c32 = L.pre32[k];
+            if (c64 > 0)
+                ctx->timed(kStatUpdate64, L.flops64[k], (double)c64 * nbd * nbd * 8.0 * 2.0, [&] {
+                    launch_update(map, ds->list64.as<TileIJ>(), c64, true, p64, p32, s);
+                });
+            if (c32 > 0)
+                ctx->timed(kStatUpdate32, L.flops32[k], (double)c32 * nbd * nbd * 4.0 * 2.0, [&] {
+                    launch_update(map, ds->list32.as<TileIJ>(), c32, false, p64, p32, s);
+                });
+        }
+        MPGEO_HIP(hipGetLastError());
+    }
+    if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s));
+    ctx->timed(kStatFinal, 2.0 * p, 16.0 * p, [&] {
+        launch_finalize(logdet_part, quad_part, p, L.n, ds->result.as<double>(), s);
+    });
+    MPGEO_HIP(hipGetLastError());
+    return MPGEO_OK;
+}
+
+// Read back {loglik, logdet, quad} and info into *out.
+int read_result(mpgeo_dataset *ds, mpgeo_result *out) {
+    hipStream_t s = ds->ctx->stream;
+    double res[3];
+    unsigned long long info = 0;
+    MPGEO_HIP(hipMemcpyAsync(res, ds->result.ptr, sizeof(res), hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipMemcpyAsync(&info, ds->info.ptr, sizeof(info), hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    out->loglik = res[0];
+    out->logdet = res[1];
+    out->quad = res[2];
+    out->info = (info == ~0ull) ? -1 : (int64_t)info;
+    return out->info >= 0 ? MPGEO_E_NOT_SPD : MPGEO_OK;
+}
+
+struct EventSet {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ok = true;
+    EventSet() {
+        for (auto &x : e)
+            if (hipEventCreate(&x) != hipSuccess) {
+                (void)hipGetLastError();
+                x = nullptr;
+                ok = false;
+            }
+    }
+    ~EventSet() {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    double secs(int a, int b) const {
+        float ms = 0.f;
+        if (!ok || hipEventElapsedTime(&ms, e[a], e[b]) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0.0;
+        }
+        return ms * 1e-3;
+    }
+};
+
+// covgen + factor + reduce for a dataset whose ordered inputs are resident.
+int evaluate(mpgeo_dataset *ds, const mpgeo_theta &th, const mpgeo_plan &pl, mpgeo_result *out,
+             hipEvent_t ev_start_outer) {
+    mpgeo_ctx *ctx = ds->ctx;
+    hipStream_t s = ctx->stream;
+    MPGEO_TRY(prepare_layout(ds, pl));
+    EventSet ev;
+    if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[0], s));
+    MPGEO_TRY(run_covgen(ds, th));
+    if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[1], s));
+    MPGEO_TRY(run_factor(ds, ev.ok ? ev.e[2] : nullptr));
+    if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[3], s));
+    const int st = read_result(ds, out);
+    out->t_covgen = ev.secs(0, 1);
+    out->t_factor = ev.secs(1, 2);
+    out->t_solve = ev.secs(2, 3);
+    if (ev_start_outer) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev_start_outer, ev.e[3]) == hipSuccess) out->t_total = ms * 1e-3;
+        else (void)hipGetLastError();
+    } else {
+        out->t_total = ev.secs(0, 3);
+    }
+    ctx->collect();
+    ds->has_factor = (st == MPGEO_OK);
+    ds->theta = th;
+    return st;
+}
+
+struct Device {
+    explicit Device(int d) { ok = hipSetDevice(d) == hipSuccess; }
+    bool ok;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *mpgeo_status_string(int status) {
+    switch (status) {
+        case MPGEO_OK: return "ok";
+        case MPGEO_E_ARG: return "invalid argument";
+        case MPGEO_E_NOT_SPD: return "matrix is not positive definite";
+        case MPGEO_E_NOMEM: return "device memory allocation failed";
+        case MPGEO_E_DEVICE: return "HIP runtime error";
+        case MPGEO_E_UNSUPPORTED: return "unsupported feature";
+        default: return "unknown status";
+    }
+}
+
+size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
+    if (n < 1 || check_plan(plan) != MPGEO_OK) return 0;
+    Layout L;
+    L.build(n, plan.tile, plan.band64);
+    const size_t te = (size_t)L.nbp * L.nbp;
+    return (size_t)L.n64 * te * sizeof(double) + (size_t)L.n32 * te * sizeof(float);
+}
+
+int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {
+    if (!out) return MPGEO_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) {
+        (void)hipGetLastError();
+        return MPGEO_E_DEVICE;
+    }
+    if (device < 0 || device >= count) return MPGEO_E_ARG;
+    MPGEO_HIP(hipSetDevice(device));
+    mpgeo_ctx *c = new mpgeo_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        hipError_t e = hipStreamCreate(&c->stream);   // blocking: ordered after the null stream
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete c;
+            return MPGEO_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    c->reset_stats();
+    *out = c;
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_destroy(mpgeo_dataset *ds);
+
+int mpgeo_ctx_destroy(mpgeo_ctx *ctx) {
+    if (!ctx) return MPGEO_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->scratch_ds) mpgeo_dataset_destroy(ctx->scratch_ds);
+    ctx->collect();
+    for (auto e : ctx->spare) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return MPGEO_OK;
+}
+
+int mpgeo_ctx_kernel_stats(mpgeo_ctx *ctx, mpgeo_kernel_stat *out, int max, int *count) {
+    if (!ctx || !count || (max > 0 && !out)) return MPGEO_E_ARG;
+    *count = kStatCount;
+    for (int c = 0; c < kStatCount && c < max; ++c) out[c] = ctx->stats[c];
+    return MPGEO_OK;
+}
+
+int mpgeo_ctx_reset_stats(mpgeo_ctx *ctx) {
+    if (!ctx) return MPGEO_E_ARG;
+    ctx->reset_stats();
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_create(mpgeo_ctx *ctx, int64_t n, const double *locs, const double *z,
+                         uint32_t flags, mpgeo_dataset **out) {
+    if (!ctx || !out || !locs || n < 1 || n > (int64_t)0xFFFFFFFF) return MPGEO_E_ARG;
+    *out = nullptr;
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    mpgeo_dataset *ds = new mpgeo_dataset();
+    ds->ctx = ctx;
+    ds->n = n;
+    ds->flags = flags;
+    const int st = load_inputs(ds, locs, z, flags);
+    if (st != MPGEO_OK) {
+        mpgeo_dataset_destroy(ds);
+        return st;
+    }
+    *out = ds;
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
+    if (!ds) return MPGEO_OK;
+    (void)hipSetDevice(ds->ctx->device);
+    (void)hipStreamSynchronize(ds->ctx->stream);
+    for (DevBuf *b : {&ds->locs, &ds->z, &ds->perm, &ds->keys, &ds->locs_in, &ds->z_in,
+                      &ds->pool64, &ds->pool32, &ds->off, &ds->all, &ds->list64, &ds->list32,
+                      &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
+                      &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c})
+        b->release();
+    delete ds;
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_loglik(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan, mpgeo_result *out) {
+    if (!ds || !out) return MPGEO_E_ARG;
+    out->info = -1;
+    MPGEO_TRY(check_theta(theta));
+    MPGEO_TRY(check_plan(plan));
+    Device dev(ds->ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    ds->ctx->timing = (plan.flags & MPGEO_TIMING) != 0;
+    const int st = evaluate(ds, theta, plan, out, nullptr);
+    ds->ctx->timing = false;
+    return st;
+}
+
+int mpgeo_loglik(mpgeo_ctx *ctx, int64_t n, const double *locs, const double *z, mpgeo_theta theta,
+                 mpgeo_plan plan, mpgeo_result *out) {
+    if (!ctx || !out || !locs || !z || n < 1 || n > (int64_t)0xFFFFFFFF) return MPGEO_E_ARG;
+    out->info = -1;
+    MPGEO_TRY(check_theta(theta));
+    MPGEO_TRY(check_plan(plan));
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    if (ctx->scratch_ds && ctx->scratch_ds->n != n) {
+        // keep the large tile pools if the size matches; otherwise start over
+        mpgeo_dataset_destroy(ctx->scratch_ds);
+        ctx->scratch_ds = nullptr;
+    }
+    if (!ctx->scratch_ds) {
+        ctx->scratch_ds = new mpgeo_dataset();
+        ctx->scratch_ds->ctx = ctx;
+        ctx->scratch_ds->n = n;
+    }
+    mpgeo_dataset *ds = ctx->scratch_ds;
+    ds->flags = plan.flags;
+    ctx->timing = (plan.flags & MPGEO_TIMING) != 0;
+    EventSet ev;
+    if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[0], ctx->stream));
+    int st = load_inputs(ds, locs, z, plan.flags);
+    if (st == MPGEO_OK) st = evaluate(ds, theta, plan, out, ev.ok ? ev.e[0] : nullptr);
+    ctx->timing = false;
+    return st;
+}
+
+int mpgeo_dataset_perm(mpgeo_dataset *ds, int64_t *perm) {
+    if (!ds || !perm) return MPGEO_E_ARG;
+    Device dev(ds->ctx->device);
+    MPGEO_HIP(hipMemcpy(perm, ds->perm.ptr, (size_t)ds->n * sizeof(int64_t), hipMemcpyDeviceToHost));
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_covariance(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan) {
+    if (!ds) return MPGEO_E_ARG;
+    MPGEO_TRY(check_theta(theta));
+    MPGEO_TRY(check_plan(plan));
+    Device dev(ds->ctx->device);
+    MPGEO_TRY(prepare_layout(ds, plan));
+    MPGEO_TRY(run_covgen(ds, theta));
+    ds->has_factor = false;
+    MPGEO_HIP(hipStreamSynchronize(ds->ctx->stream));
+    ds->ctx->collect();
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_matrix(mpgeo_dataset *ds, double *out, int64_t ld) {
+    if (!ds || !out || ld < ds->n || !ds->off.ptr) return MPGEO_E_ARG;
+    Device dev(ds->ctx->device);
+    const int64_t n = ds->n;
+    hipStream_t s = ds->ctx->stream;
+    MPGEO_TRY(ds->tmp_a.ensure((size_t)n * n * sizeof(double)));
+    MPGEO_HIP(hipMemsetAsync(ds->tmp_a.ptr, 0, (size_t)n * n * sizeof(double), s));
+    launch_export_dense(tile_map(ds), ds->tmp_a.as<double>(), n, ds->all.as<TileIJ>(),
+                        (int64_t)ds->layout.all.size(), s);
+    MPGEO_HIP(hipGetLastError());
+    std::vector<double> host((size_t)n * n);
+    MPGEO_HIP(hipMemcpyAsync(host.data(), ds->tmp_a.ptr, host.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = c; r < n; ++r) out[r + c * ld] = host[r + c * n];
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_solution(mpgeo_dataset *ds, double *y) {
+    if (!ds || !y || !ds->has_factor) return MPGEO_E_ARG;
+    Device dev(ds->ctx->device);
+    const Layout &L = ds->layout;
+    hipStream_t s = ds->ctx->stream;
+    MPGEO_TRY(ds->tmp_b.ensure((size_t)ds->n * sizeof(double)));
+    launch_unpad_vector(ds->y.as<double>(), ds->tmp_b.as<double>(), L.n, L.nb, L.nbp, s);
+    MPGEO_HIP(hipGetLastError());
+    MPGEO_HIP(hipMemcpyAsync(y, ds->tmp_b.ptr, (size_t)ds->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs, double *pred,
+                        double *var) {
+    if (!ds || m < 0 || (m > 0 && (!new_locs || !pred))) return MPGEO_E_ARG;
+    if (!ds->has_factor) return MPGEO_E_ARG;
+    if (var && m > 65535) return MPGEO_E_ARG;
+    if (m == 0) return MPGEO_OK;
+    Device dev(ds->ctx->device);
+    const Layout &L = ds->layout;
+    hipStream_t s = ds->ctx->stream;
+    const bool on_dev = (ds->flags & MPGEO_INPUT_DEVICE) != 0;
+    const size_t vec = (size_t)L.p * L.nbp;
+    MPGEO_TRY(ds->tmp_a.ensure(2 * vec * sizeof(double)));
+    double *t = ds->tmp_a.as<double>();
+    double *w = t + vec;
+    launch_backward_solve(tile_map(ds), ds->linv.as<double>(), ds->y.as<double>(), t, w, s);
+    MPGEO_HIP(hipGetLastError());
+    // new sites and outputs on the device
+    const size_t need = (size_t)m * 2 * sizeof(double) + 2 * (size_t)m * sizeof(double);
+    MPGEO_TRY(ds->tmp_b.ensure(need));
+    double *dnew = ds->tmp_b.as<double>();
+    double *dpred = dnew + 2 * m;
+    double *dvar = dpred + m;
+    if (on_dev) MPGEO_HIP(hipMemcpyAsync(dnew, new_locs, (size_t)m * 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else MPGEO_HIP(hipMemcpyAsync(dnew, new_locs, (size_t)m * 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    const MaternParams mp = make_matern_params(ds->theta.sigma2, ds->theta.beta, ds->theta.nu);
+    launch_krige_predict(ds->locs.as<double>(), L.n, L.nb, L.nbp, dnew, m, w, mp, dpred, s);
+    MPGEO_HIP(hipGetLastError());
+    if (var) {
+        const int64_t ldc = (int64_t)vec;
+        MPGEO_TRY(ds->tmp_c.ensure((size_t)ldc * m * sizeof(double) + (size_t)L.nbp * m * sizeof(double)));
+        double *c = ds->tmp_c.as<double>();
+        double *tmp = c + (size_t)ldc * m;
+        launch_cross_cov(ds->locs.as<double>(), L.n, L.nb, L.nbp, L.p, dnew, m, mp, c, ldc, s);
+        launch_forward_multi(tile_map(ds), ds->linv.as<double>(), c, ldc, m, tmp, s);
+        launch_column_var(c, ldc, ldc, m, ds->theta.sigma2, dvar, s);
+        MPGEO_HIP(hipGetLastError());
+    }
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    MPGEO_HIP(hipMemcpyAsync(pred, dpred, (size_t)m * sizeof(double), kind, s));
+    if (var) MPGEO_HIP(hipMemcpyAsync(var, dvar, (size_t)m * sizeof(double), kind, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_entries(mpgeo_dataset *ds, int64_t count, const int64_t *rows,
+                          const int64_t *cols, double *out) {
+    if (!ds || count < 0 || (count > 0 && (!rows || !cols || !out)) || !ds->off.ptr)
+        return MPGEO_E_ARG;
+    if (count == 0) return MPGEO_OK;
+    for (int64_t q = 0; q < count; ++q)
+        if (rows[q] < 0 || rows[q] >= ds->n || cols[q] < 0 || cols[q] >= ds->n) return MPGEO_E_ARG;
+    Device dev(ds->ctx->device);
+    hipStream_t s = ds->ctx->stream;
+    const size_t ib = (size_t)count * sizeof(int64_t);
+    MPGEO_TRY(ds->tmp_b.ensure(2 * ib + (size_t)count * sizeof(double)));
+    char *base = ds->tmp_b.as<char>();
+    int64_t *drows = reinterpret_cast<int64_t *>(base);
+    int64_t *dcols = reinterpret_cast<int64_t *>(base + ib);
+    double *dout = reinterpret_cast<double *>(base + 2 * ib);
+    MPGEO_HIP(hipMemcpyAsync(drows, rows, ib, hipMemcpyHostToDevice, s));
+    MPGEO_HIP(hipMemcpyAsync(dcols, cols, ib, hipMemcpyHostToDevice, s));
+    launch_entries(tile_map(ds), count, drows, dcols, dout, s);
+    MPGEO_HIP(hipGetLastError());
+    MPGEO_HIP(hipMemcpyAsync(out, dout, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    return MPGEO_OK;
+}
+
+int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
+                      double ftol, int32_t max_evals, mpgeo_theta *theta_hat, double *loglik_hat,
+                      int32_t *evals_out, int32_t *iters_out) {
+    if (!ds || max_evals < 4 || !(xtol >= 0.0) || !(ftol >= 0.0)) return MPGEO_E_ARG;
+    MPGEO_TRY(check_theta(start));
+    MPGEO_TRY(check_plan(plan));
+    Device dev(ds->ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    static const double lo[3] = {0.01, 0.001, 0.1};
+    static const double hi[3] = {10.0, 2.0, 3.0};
+    auto to_theta = [&](const double *u) {
+        double t[3];
+        for (int q = 0; q < 3; ++q) t[q] = std::min(std::max(std::exp(u[q]), lo[q]), hi[q]);
+        return mpgeo_theta{t[0], t[1], t[2]};
+    };
+    int hard_error = MPGEO_OK;
+    // objective: -loglik; a non-positive-definite point scores +infinity
+    auto f = [&](const double *u) -> double {
+        mpgeo_result r{};
+        const int st = evaluate(ds, to_theta(u), plan, &r, nullptr);
+        if (st == MPGEO_OK) return -r.loglik;
+        if (st != MPGEO_E_NOT_SPD && hard_error == MPGEO_OK) hard_error = st;
+        return INFINITY;
+    };
+    double x[4][3];
+    double fv[4];
+    const double u0[3] = {std::log(start.sigma2), std::log(start.beta), std::log(start.nu)};
+    for (int v = 0; v < 4; ++v)
+        for (int q = 0; q < 3; ++q) x[v][q] = u0[q] + ((v > 0 && q == v - 1) ? 0.1 : 0.0);
+    int evals = 0, iters = 0;
+    for (int v = 0; v < 4; ++v) {
+        fv[v] = f(x[v]);
+        ++evals;
+    }
+    while (evals < max_evals && hard_error == MPGEO_OK) {
+        int order[4] = {0, 1, 2, 3};
+        std::stable_sort(order, order + 4, [&](int a, int b) { return fv[a] < fv[b]; });
+        double xs[4][3], fs[4];
+        for (int v = 0; v < 4; ++v) {
+            fs[v] = fv[order[v]];
+            for (int q = 0; q < 3; ++q) xs[v][q] = x[order[v]][q];
+        }
+        std::memcpy(x, xs, sizeof(x));
+        std::memcpy(fv, fs, sizeof(fv));
+        double span = 0.0;
+        for (int v = 1; v < 4; ++v)
+            for (int q = 0; q < 3; ++q) span = std::max(span, std::fabs(x[v][q] - x[0][q]));
+        if (span < xtol || std::fabs(fv[3] - fv[0]) <= ftol * std::fabs(fv[0])) break;
+        ++iters;
+        double c[3], xr[3], xe[3], xc[3];
+        for (int q = 0; q < 3; ++q) c[q] = (x[0][q] + x[1][q] + x[2][q]) / 3.0;
+        for (int q = 0; q < 3; ++q) xr[q] = c[q] + (c[q] - x[3][q]);
+        const double fr = f(xr);
+        ++evals;
+        if (fr < fv[0]) {
+            for (int q = 0; q < 3; ++q) xe[q] = c[q] + 2.0 * (c[q] - x[3][q]);
+            const double fe = f(xe);
+            ++evals;
+            if (fe < fr) {
+                std::memcpy(x[3], xe, sizeof(xe));
+                fv[3] = fe;
+            } else {
+                std::memcpy(x[3], xr, sizeof(xr));
+                fv[3] = fr;
+            }
+            continue;
+        }
+        if (fr < fv[2]) {
+            std::memcpy(x[3], xr, sizeof(xr));
+            fv[3] = fr;
+            continue;
+        }
+        if (fr < fv[3]) {
+            for (int q = 0; q < 3; ++q) xc[q] = c[q] + 0.5 * (xr[q] - c[q]);   // outside
+            const double fc = f(xc);
+            ++evals;
+            if (fc <= fr) {
+                std::memcpy(x[3], xc, sizeof(xc));
+                fv[3] = fc;
+                continue;
+            }
+        } else {
+            for (int q = 0; q < 3; ++q) xc[q] = c[q] + 0.5 * (x[3][q] - c[q]);   // inside
+            const double fc = f(xc);
+            ++evals;
+            if (fc < fv[3]) {
+                std::memcpy(x[3], xc, sizeof(xc));
+                fv[3] = fc;
+                continue;
+            }
+        }
+        for (int v = 1; v < 4; ++v) {   // shrink towards the best vertex
+            for (int q = 0; q < 3; ++q) x[v][q] = x[0][q] + 0.5 * (x[v][q] - x[0][q]);
+            fv[v] = f(x[v]);
+            ++evals;
+        }
+    }
+    if (hard_error != MPGEO_OK) return hard_error;
+    int best = 0;
+    for (int v = 1; v < 4; ++v)
+        if (fv[v] < fv[best]) best = v;
+    if (!std::isfinite(fv[best])) return MPGEO_E_NOT_SPD;
+    const mpgeo_theta th = to_theta(x[best]);
+    mpgeo_result r{};
+    MPGEO_TRY(evaluate(ds, th, plan, &r, nullptr));   // leave the factor of theta_hat resident
+    if (theta_hat) *theta_hat = th;
+    if (loglik_hat) *loglik_hat = r.loglik;
+    if (evals_out) *evals_out = evals;
+    if (iters_out) *iters_out = iters;
+    return MPGEO_OK;
+}
+
+int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, const double *z,
+                       mpgeo_plan plan, mpgeo_result *out) {
+    if (!ctx || !out || !a || n < 1 || lda < n) return MPGEO_E_ARG;
+    out->info = -1;
+    MPGEO_TRY(check_plan(plan));
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    mpgeo_dataset ds;
+    ds.ctx = ctx;
+    ds.n = n;
+    hipStream_t s = ctx->stream;
+    const bool on_dev = (plan.flags & MPGEO_INPUT_DEVICE) != 0;
+    int st = prepare_layout(&ds, plan);
+    const double *da = a;
+    if (st == MPGEO_OK && !on_dev) {
+        st = ds.tmp_a.ensure((size_t)lda * n * sizeof(double));
+        if (st == MPGEO_OK && hipMemcpyAsync(ds.tmp_a.ptr, a, (size_t)lda * n * sizeof(double),
+                                             hipMemcpyHostToDevice, s) != hipSuccess)
+            st = MPGEO_E_DEVICE;
+        da = ds.tmp_a.as<double>();
+    }
+    if (st == MPGEO_OK) st = ds.z.ensure((size_t)n * sizeof(double));
+    if (st == MPGEO_OK) {
+        hipError_t e;
+        if (!z) e = hipMemsetAsync(ds.z.ptr, 0, (size_t)n * sizeof(double), s);
+        else e = hipMemcpyAsync(ds.z.ptr, z, (size_t)n * sizeof(double),
+                                on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = MPGEO_E_DEVICE;
+    }
+    if (st == MPGEO_OK) {
+        ctx->timing = (plan.flags & MPGEO_TIMING) != 0;
+        EventSet ev;
+        if (ev.ok) (void)hipEventRecord(ev.e[0], s);
+        launch_import_dense(tile_map(&ds), da, lda, ds.all.as<TileIJ>(), (int64_t)ds.layout.all.size(), s);
+        if (ev.ok) (void)hipEventRecord(ev.e[1], s);
+        st = status_from(hipGetLastError());
+        if (st == MPGEO_OK) st = run_factor(&ds, ev.ok ? ev.e[2] : nullptr);
+        if (ev.ok) (void)hipEventRecord(ev.e[3], s);
+        if (st == MPGEO_OK) {
+            st = read_result(&ds, out);
+            out->t_covgen = ev.secs(0, 1);
+            out->t_factor = ev.secs(1, 2);
+            out->t_solve = ev.secs(2, 3);
+            out->t_total = ev.secs(0, 3);
+        }
+        ctx->collect();
+        ctx->timing = false;
+    }
+    (void)hipStreamSynchronize(s);
+    for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.p64,
+                      &ds.p32, &ds.linv, &ds.linv32, &ds.r, &ds.y, &ds.parts, &ds.info, &ds.result,
+                      &ds.tmp_a, &ds.z})
+        b->release();
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP sources of libmpgeo (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+namespace mpgeo {
+
+// Physical tiles are padded to a multiple of kTileQuantum rows/columns; the padding
+// rows and columns hold an identity block (unit diagonal, zero elsewhere) and a zero
+// right-hand side.  Because those rows are decoupled from the rest, the Cholesky
+// factor, log-determinant and quadratic form of the padded matrix equal those of the
+// true matrix exactly.
+constexpr int kTileQuantum = 32;
+constexpr int kMaxTile = 512;
+
+struct TileIJ {
+    int32_t i;
+    int32_t j;
+};
+
+// Index of lower tile (i, j), i >= j, in row-major packed lower-triangular order.
+__host__ __device__ inline int64_t tri_index(int64_t i, int64_t j) {
+    return i * (i + 1) / 2 + j;
+}
+
+// Where the tiles live: one pool per precision; off[tri_index(i, j)] is the element
+// offset of tile (i, j) inside the pool of its precision (FP64 iff i - j <= band).
+struct TileMap {
+    const int64_t *off;
+    double *pool64;
+    float *pool32;
+    int band;   // FP64 iff i - j <= band (band >= p - 1 means every tile is FP64)
+    int nbp;    // physical tile size (multiple of kTileQuantum)
+    int nb;     // logical tile size
+    int p;      // tiles per side
+    int64_t n;  // logical matrix order
+};
+
+__host__ __device__ inline bool tile_is_fp64(const TileMap &m, int i, int j) {
+    return (i - j) <= m.band;
+}
+
+// ---- launchers (host functions; every kernel is enqueued on `stream`) -------------
+
+// Matérn covariance of eq. (1) for every lower tile, written in the tile's precision.
+struct MaternParams {
+    double sigma2, beta, nu;
+    double pref;   // sigma2 / (2^(nu-1) Gamma(nu))
+    int nl;        // nu = mu + nl with mu in [-1/2, 1/2)
+    double mu;
+    int mode;      // 0 general nu, 1: nu = 1/2, 2: nu = 3/2, 3: nu = 5/2
+};
+MaternParams make_matern_params(double sigma2, double beta, double nu);
+
+void launch_covgen(const TileMap &map, const double *locs, const TileIJ *tiles,
+                   int64_t ntiles, const MaternParams &mp, hipStream_t stream);
+
+// Caller matrix (device, column-major, ld) -> tiles in their precision (identity padding).
+void launch_import_dense(const TileMap &map, const double *a, int64_t lda,
+                         const TileIJ *tiles, int64_t ntiles, hipStream_t stream);
+
+// Tiles -> dense lower triangle (device, column-major, ld), FP32 promoted.
+void launch_export_dense(const TileMap &map, double *out, int64_t ld, const TileIJ *tiles,
+                         int64_t ntiles, hipStream_t stream);
+
+// Sampled entries of the stored lower triangle (host-side indices copied in by the caller).
+void launch_entries(const TileMap &map, int64_t count, const int64_t *rows, const int64_t *cols,
+                    double *out, hipStream_t stream);
+
+// Logical vector (n) -> physical padded vector (p * nbp), zero in padding rows.
+void launch_pad_vector(const double *src, double *dst, int64_t n, int nb, int nbp, int p,
+                       hipStream_t stream);
+void launch_unpad_vector(const double *src, double *dst, int64_t n, int nb, int nbp,
+                         hipStream_t stream);
+
+// Z-order keys, sort, and gather of locations and data.
+void launch_morton_order(const double *locs_in, const double *z_in, int64_t n,
+                         uint64_t *keys, int64_t n2, double *locs_out, double *z_out,
+                         int64_t *perm_out, hipStream_t stream);
+
+// FP64 factorisation of diagonal tile k in place, its inverse (FP64 and FP32 copies),
+// the forward-solve block y_k = L_kk^-1 r_k, and the step's log-det / quad parts.
+struct PotrfArgs {
+    double *a;         // tile (k, k), nbp x nbp column-major
+    double *linv;      // out: L_kk^-1, nbp x nbp
+    float *linv32;     // out: FP32 copy of L_kk^-1
+    const double *r;   // residual block r_k (nbp)
+    double *y;         // out: y_k (nbp)
+    double *logdet_part;
+    double *quad_part;
+    unsigned long long *info;   // atomic min of the failing global column
+    int64_t col_base;  // global logical column of the tile's first column
+    int nb;            // logical tile size (columns >= nb are padding)
+    int nbp;
+};
+void launch_potrf(const PotrfArgs &a, hipStream_t stream);
+
+// Panel TRSM of step k through the explicit inverse: X_i = A_ik L_kk^-T for
+// i in [i_begin, i_begin + count); writes the staging panels P64[i], P32[i].
+void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64,
+                 const double *linv, const float *linv32, double *p64, float *p32,
+                 hipStream_t stream);
+
+// Trailing update of step k: A_ij -= P_i P_j^T over list[0, count) (tiles all of one
+// precision), with P the staging panel of that precision.
+void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool fp64,
+                   const double *p64, const float *p32, hipStream_t stream);
+
+// Panel step of the fused forward solve: r_i -= P64_i y_k for i in (k, p), and copy the
+// finished panel tile (i, k) from staging into its storage precision.
+void launch_panel_solve(const TileMap &map, int k, const double *p64, const double *yk,
+                        double *r, hipStream_t stream);
+
+// Reduction of the per-step parts into {loglik, logdet, quad} (device double[3]).
+void launch_finalize(const double *logdet_part, const double *quad_part, int p, int64_t n,
+                     double *result, hipStream_t stream);
+
+// Backward solve w = L^-T y over the tiles (uses the stored diagonal inverses).
+void launch_backward_solve(const TileMap &map, const double *linv_all, const double *y,
+                           double *t, double *w, hipStream_t stream);
+
+// Kriging: pred_j = sum_a C(||s0_j - s_a||) w_a (physical padded w), j < m.
+void launch_krige_predict(const double *locs, int64_t n, int nb, int nbp,
+                          const double *new_locs, int64_t m, const double *w,
+                          const MaternParams &mp, double *pred, hipStream_t stream);
+
+// Cross-covariance columns for the kriging variance: c[(a phys) + j * ldc] = C(s0_j, s_a).
+void launch_cross_cov(const double *locs, int64_t n, int nb, int nbp, int p,
+                      const double *new_locs, int64_t m, const MaternParams &mp, double *c,
+                      int64_t ldc, hipStream_t stream);
+
+// Forward solve of many right-hand sides and their column norms: var_j = sigma2 - |L^-1 c_j|^2.
+void launch_forward_multi(const TileMap &map, const double *linv_all, double *c, int64_t ldc,
+                          int64_t m, double *tmp, hipStream_t stream);
+void launch_column_var(const double *c, int64_t ldc, int64_t rows, int64_t m, double sigma2,
+                       double *var, hipStream_t stream);
+
+}  // namespace mpgeo

@@ -1,0 +1,48 @@
+"""Writes the stored expected values under tests/golden/ using only the oracle.
+
+    python tests/golden/make_golden.py mle_small
+
+mle_small.json: maximum-likelihood fit (Nelder-Mead of the oracle) for the n = 1,600
+jittered-grid workload (theta_0 = (1, 0.1, 0.5)), with z = L eps drawn by the oracle.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from synthetic import SMALL  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def mle_small():
+    w = SMALL
+    locs = w.locations()
+    z = oracle.simulate_field(locs, w.theta, w.eps())
+    t0 = time.time()
+    fit = oracle.fit_mle(locs, z, w.theta)
+    out = {
+        "workload": w.name,
+        "n": w.n,
+        "theta_true": list(w.theta),
+        "theta_hat": list(fit["theta"]),
+        "loglik_hat": fit["loglik"],
+        "evals": fit["evals"],
+        "iters": fit["iters"],
+        "seconds": time.time() - t0,
+        "source": "oracle.fit_mle (Nelder-Mead on eq. (2)); z = oracle.simulate_field",
+    }
+    with open(os.path.join(HERE, "mle_small.json"), "w") as f:
+        json.dump(out, f, indent=2)
+    print(json.dumps(out, indent=2))
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["mle_small"]:
+        globals()[name]()

@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances:
+  * all-FP64 path:       |dl| / |l| <= 1e-10 (also logdet and quad);
+  * FP64/FP32 band path: |dl| / max(|l|, n) <= 1e-5;
+  * Morton permutation:  bit-exact;
+  * covariance entries:  FP64 tiles within 1e-13 relative of the oracle for nu = 1/2 (both
+    sides elementary) and 5e-13 for general nu (the oracle's Bessel routine itself is good
+    to about 1e-13 near x = 2); FP32 tiles within one FP32 ulp of the oracle value.
+"""
+import functools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from synthetic import SMALL, jittered_grid, line_grid, normals, perturbed_thetas
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@functools.lru_cache(maxsize=None)
+def small_case():
+    locs = SMALL.locations()
+    z = oracle.simulate_field(locs, SMALL.theta, SMALL.eps())
+    return locs, z
+
+
+@functools.lru_cache(maxsize=None)
+def small_oracle(theta):
+    locs, z = small_case()
+    out = oracle.loglik(locs, z, theta)
+    return {k: out[k] for k in ("loglik", "logdet", "quad")}
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def small_ds(lib, ctx):
+    locs, z = small_case()
+    ds = lib.Dataset(ctx, locs, z)
+    yield ds
+    ds.close()
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def test_morton_permutation_is_bit_exact(small_ds):
+    locs, _ = small_case()
+    assert np.array_equal(small_ds.perm(), oracle.morton_order(locs))
+
+
+@pytest.mark.parametrize("theta,band", [((1.0, 0.1, 0.5), 2), ((1.3, 0.2, 0.73), 1),
+                                        ((0.9, 0.05, 1.0), 0), ((1.0, 0.1, 1.5), -1)])
+def test_covariance_entries(small_ds, theta, band):
+    locs, _ = small_case()
+    tile = SMALL.tile
+    got = small_ds.covariance(theta, tile, band)
+    want = oracle.matern_matrix(locs[small_ds.perm()], theta)
+    n = want.shape[0]
+    ti = np.arange(n) // tile
+    dist = ti[:, None] - ti[None, :]
+    lower = np.tril(np.ones((n, n), dtype=bool))
+    fp64 = lower & ((dist <= band) if band >= 0 else True)
+    fp32 = lower & ~fp64
+    tol = 1e-13 if theta[2] in (0.5, 1.5, 2.5) else 5e-13
+    err64 = np.abs(got[fp64] - want[fp64]) / np.maximum(np.abs(want[fp64]), 1e-300)
+    assert err64.max() <= tol
+    if fp32.any():
+        w32 = want[fp32].astype(np.float32)
+        ulp = np.spacing(np.abs(w32)).astype(np.float64)
+        assert np.all(np.abs(got[fp32] - w32.astype(np.float64)) <= ulp)
+        assert np.all(got[fp32] == got[fp32].astype(np.float32))   # stored as FP32
+
+
+@pytest.mark.parametrize("theta", [SMALL.theta] + perturbed_thetas(SMALL.theta))
+def test_fp64_path_matches_oracle(small_ds, theta):
+    want = small_oracle(tuple(theta))
+    got = small_ds.loglik(theta, SMALL.tile, -1)
+    assert rel(got["loglik"], want["loglik"]) <= 1e-10
+    assert rel(got["logdet"], want["logdet"]) <= 1e-10
+    assert rel(got["quad"], want["quad"]) <= 1e-10
+
+
+@pytest.mark.parametrize("band", [2, 1, 0])
+@pytest.mark.parametrize("theta", [SMALL.theta] + perturbed_thetas(SMALL.theta)[::3])
+def test_band_path_matches_oracle(small_ds, theta, band):
+    want = small_oracle(tuple(theta))
+    got = small_ds.loglik(theta, SMALL.tile, band)
+    n = SMALL.n
+    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), n) <= 1e-5
+
+
+def test_one_shot_equals_resident_dataset(lib, ctx, small_ds):
+    locs, z = small_case()
+    a = ctx.loglik(locs, z, SMALL.theta, SMALL.tile, SMALL.band64)
+    b = small_ds.loglik(SMALL.theta, SMALL.tile, SMALL.band64)
+    assert a["loglik"] == b["loglik"] and a["logdet"] == b["logdet"]
+
+
+def test_device_inputs(lib, ctx, small_ds):
+    import torch
+    locs, z = small_case()
+    dl = torch.from_numpy(locs).to("cuda:0")
+    dz = torch.from_numpy(z).to("cuda:0")
+    a = ctx.loglik(dl, dz, SMALL.theta, SMALL.tile, SMALL.band64)
+    b = small_ds.loglik(SMALL.theta, SMALL.tile, SMALL.band64)
+    assert a["loglik"] == b["loglik"]
+
+
+def test_factor_and_forward_solve_entries(small_ds):
+    locs, z = small_case()
+    theta = (1.0, 0.1, 1.0)
+    small_ds.loglik(theta, SMALL.tile, -1)
+    perm = small_ds.perm()
+    s = oracle.matern_matrix(locs[perm], theta)
+    low = oracle.cholesky_lower(s)
+    got = small_ds.matrix()
+    assert np.max(np.abs(np.tril(got) - low)) <= 1e-11 * np.max(np.abs(low))
+    y = sla.solve_triangular(low, z[perm], lower=True)
+    np.testing.assert_allclose(small_ds.solution(), y, rtol=0, atol=1e-10 * np.max(np.abs(y)))
+
+
+@pytest.mark.parametrize("n,tile", [(50, 7), (50, 16), (77, 32), (77, 50), (64, 64), (130, 33)])
+@pytest.mark.parametrize("band", [-1, 0, 1])
+def test_ar1_closed_form_ragged_tiles(lib, ctx, n, tile, band):
+    h, sigma2, beta = 0.007, 1.6, 0.05
+    locs = line_grid(n, h)
+    z = normals(n, 3 + n)
+    rho = math.exp(-h / beta)
+    logdet = n * math.log(sigma2) + (n - 1) * math.log(1 - rho * rho)
+    quad = z[0] ** 2 / sigma2 + sum((z[i] - rho * z[i - 1]) ** 2 for i in range(1, n)) / (
+        sigma2 * (1 - rho * rho))
+    got = ctx.loglik(locs, z, (sigma2, beta, 0.5), tile, band)
+    if band < 0 or band >= (n + tile - 1) // tile - 1:      # every tile FP64
+        assert rel(got["logdet"], logdet) <= 1e-11
+        assert rel(got["quad"], quad) <= 1e-11
+    else:
+        want = -0.5 * n * math.log(2 * math.pi) - 0.5 * logdet - 0.5 * quad
+        assert abs(got["loglik"] - want) / max(abs(want), n) <= 1e-5
+
+
+def _exact_loglik(a, z):
+    from fractions import Fraction
+    n = len(z)
+    m = [[Fraction(float(a[i, j])) for j in range(n)] + [Fraction(float(z[i]))] for i in range(n)]
+    det = Fraction(1)
+    for c in range(n):
+        det *= m[c][c]
+        for r in range(c + 1, n):
+            f = m[r][c] / m[c][c]
+            for k in range(c, n + 1):
+                m[r][k] -= f * m[c][k]
+    x = [Fraction(0)] * n
+    for r in range(n - 1, -1, -1):
+        x[r] = (m[r][n] - sum(m[r][k] * x[k] for k in range(r + 1, n))) / m[r][r]
+    quad = float(sum(Fraction(float(z[i])) * x[i] for i in range(n)))
+    logdet = math.log(det)
+    return -0.5 * n * math.log(2 * math.pi) - 0.5 * logdet - 0.5 * quad
+
+
+@pytest.mark.parametrize("n", [5, 9, 12])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+def test_tiny_problems_every_band(lib, ctx, n, tile):
+    rng = np.random.default_rng(100 * n + tile)
+    locs = rng.uniform(0, 1, size=(n, 2))
+    z = normals(n, n + tile)
+    theta = (1.2, 0.3, 0.8)
+    perm = oracle.morton_order(locs)
+    want = _exact_loglik(oracle.matern_matrix(locs[perm], theta), z[perm])
+    p = (n + tile - 1) // tile
+    for band in list(range(p)) + [-1]:
+        got = ctx.loglik(locs, z, theta, tile, band)["loglik"]
+        if band < 0 or band >= p - 1:
+            assert rel(got, want) <= 1e-10, (band, got, want)
+        else:
+            assert abs(got - want) / max(abs(want), n) <= 1e-5, (band, got, want)
+
+
+def _block_banded_spd(n, tile, width, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n, n))
+    a = (a + a.T) / 2
+    ti = np.arange(n) // tile
+    a[np.abs(ti[:, None] - ti[None, :]) > width] = 0.0
+    a += np.eye(n) * (np.abs(a).sum(axis=1).max() + 1.0)    # diagonally dominant -> SPD
+    return a
+
+
+def test_block_banded_matrix_is_exact_for_every_wider_band(lib, ctx):
+    n, tile, width = 200, 32, 2
+    a = _block_banded_spd(n, tile, width, 5)
+    z = normals(n, 6)
+    want = oracle.likelihood.loglik_parts(a, z)
+    results = [ctx.factor_dense(a, z, tile, band) for band in (width, width + 1, 5, -1)]
+    for r in results:
+        assert r["loglik"] == results[0]["loglik"]
+        assert r["logdet"] == results[0]["logdet"]
+    assert rel(results[0]["logdet"], want["logdet"]) <= 1e-12
+    assert rel(results[0]["quad"], want["quad"]) <= 1e-12
+
+
+def test_factor_dense_matches_oracle_on_random_spd(lib, ctx):
+    from synthetic import random_spd
+    a = random_spd(300, 9)
+    z = normals(300, 10)
+    want = oracle.likelihood.loglik_parts(a, z)
+    got = ctx.factor_dense(a, z, 64, -1)
+    assert rel(got["loglik"], want["loglik"]) <= 1e-10
+    got = ctx.factor_dense(a, z, 64, 0)
+    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), 300) <= 1e-5
+
+
+@pytest.mark.parametrize("col", [0, 37, 63])
+def test_not_positive_definite_reports_failing_column(lib, ctx, col):
+    n = 64
+    a = np.eye(n) * 2.0
+    a[col, col] = -1.0
+    with pytest.raises(lib.MpgeoError) as exc:
+        ctx.factor_dense(a, None, 16, -1)
+    assert exc.value.status == lib.MPGEO_E_NOT_SPD
+    assert exc.value.info == col
+
+
+def test_permutation_invariance_of_fp64_path(lib, ctx):
+    locs, z = small_case()
+    perm = np.random.default_rng(1).permutation(len(z))
+    a = ctx.loglik(locs, z, SMALL.theta, SMALL.tile, -1, morton=False)
+    b = ctx.loglik(locs[perm], z[perm], SMALL.theta, SMALL.tile, -1, morton=False)
+    assert rel(a["loglik"], b["loglik"]) <= 1e-12
+
+
+@pytest.mark.parametrize("band", [-1, 2])
+def test_kriging_matches_oracle(lib, ctx, band):
+    locs = jittered_grid(24, 41)
+    theta = (1.0, 0.1, 0.5)
+    z = oracle.simulate_field(locs, theta, normals(len(locs), 42))
+    new = np.random.default_rng(43).uniform(0, 1, size=(40, 2))
+    want = oracle.krige(locs, z, theta, new)
+    ds = lib.Dataset(ctx, locs, z)
+    ds.loglik(theta, 96, band)
+    pred, var = ds.krige(new, variance=True)
+    tol = 1e-9 if band < 0 else 1e-4
+    assert np.max(np.abs(pred - want["pred"])) <= tol * np.max(np.abs(want["pred"]))
+    assert np.max(np.abs(var - want["var"])) <= tol * theta[0]
+    # interpolation at observed sites (FP64 path)
+    if band < 0:
+        at = ds.krige(locs[[3, 100, 500]])
+        np.testing.assert_allclose(at, z[[3, 100, 500]], atol=1e-8)
+    ds.close()
+
+
+def test_argument_validation(lib, ctx, small_ds):
+    with pytest.raises(lib.MpgeoError) as e:
+        small_ds.loglik((1.0, -0.1, 0.5), 160, 2)
+    assert e.value.status == lib.MPGEO_E_ARG
+    with pytest.raises(lib.MpgeoError) as e:
+        small_ds.loglik((1.0, 0.1, float("nan")), 160, 2)
+    assert e.value.status == lib.MPGEO_E_ARG
+    with pytest.raises(lib.MpgeoError) as e:
+        small_ds.loglik((1.0, 0.1, 0.5), 1024, 2)
+    assert e.value.status == lib.MPGEO_E_ARG
+    with pytest.raises(lib.MpgeoError) as e:
+        small_ds.loglik((1.0, 0.1, 0.5), 160, -2)
+    assert e.value.status == lib.MPGEO_E_ARG
+
+
+@pytest.mark.parametrize("band", [2, -1])
+def test_mle_matches_oracle(lib, small_ds, band):
+    gold = json.load(open(os.path.join(HERE, "golden", "mle_small.json")))
+    start = [min(max(t * s, lo), hi) for t, s, lo, hi in
+             zip(SMALL.theta, oracle.mle.START_SCALE, oracle.mle.LOWER, oracle.mle.UPPER)]
+    fit = small_ds.mle(start, SMALL.tile, band)
+    for got, want in zip(fit["theta"], gold["theta_hat"]):
+        assert abs(got - want) / abs(want) <= 1e-3, (fit, gold)
