@@ -156,6 +156,15 @@ int mpgeo_dataset_covariance(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan pl
 int mpgeo_dataset_matrix(mpgeo_dataset *ds, double *out, int64_t ld);
 int mpgeo_dataset_solution(mpgeo_dataset *ds, double *y);
 
+/* Synthetic data (Section VIII-B.1: measurements drawn from a parameter vector theta_0):
+ * factors Sigma(theta) of the dataset's locations with the plan and writes
+ * z = P^T L P eps, a draw of the zero-mean Gaussian field with covariance Sigma(theta),
+ * where P is the dataset's ordering.  eps (n standard normal values) and z_out are in
+ * the caller's order, host or device like the dataset.  The dataset's own data vector is
+ * not changed; the factor stays resident as after a loglik call. */
+int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
+                           const double *eps, double *z_out);
+
 /* Sampled entries of the stored lower triangle (tests at sizes where a dense copy does
  * not fit): out[q] = M[max(r, c)][min(r, c)] for r = rows[q], c = cols[q] (0-based indices
  * in the ordered matrix), where M is the tier-rounded Sigma after mpgeo_dataset_covariance

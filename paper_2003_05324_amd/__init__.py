@@ -30,6 +30,7 @@ EXPORTED = (
     "mpgeo_dataset_krige", "mpgeo_dataset_perm", "mpgeo_dataset_covariance",
     "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
     "mpgeo_footprint_bytes", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
+    "mpgeo_dataset_simulate",
 )
 
 
@@ -67,7 +68,7 @@ class MpgeoError(RuntimeError):
 
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2003_05324_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2003_05324_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
     sig = {
@@ -88,6 +89,7 @@ def _load() -> ctypes.CDLL:
         "mpgeo_factor_dense": ([P, I64, P, I64, P, Plan, ctypes.POINTER(Result)], ctypes.c_int),
         "mpgeo_footprint_bytes": ([I64, Plan], ctypes.c_size_t),
         "mpgeo_dataset_entries": ([P, I64, P, P, P], ctypes.c_int),
+        "mpgeo_dataset_simulate": ([P, Theta, Plan, P, P], ctypes.c_int),
         "mpgeo_dataset_mle": ([P, Theta, Plan, D, D, I32, ctypes.POINTER(Theta),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
                                ctypes.POINTER(I32)], ctypes.c_int),
@@ -250,6 +252,17 @@ class Dataset:
         _check(LIB.mpgeo_dataset_krige(self.handle, m, _ptr(new_locs), _ptr(pred), _ptr(var)),
                "mpgeo_dataset_krige")
         return (pred, var) if variance else pred
+
+    def simulate(self, theta: Sequence[float], eps, tile: int, band64: int = -1):
+        """A draw z = P^T L P eps of the Matérn field at the dataset's locations (caller order)."""
+        if self.device_io:
+            z = torch.empty_like(eps)
+        else:
+            eps = _host_f64(eps)
+            z = np.empty(self.n)
+        _check(LIB.mpgeo_dataset_simulate(self.handle, Theta(*theta), make_plan(tile, band64),
+                                          _ptr(eps), _ptr(z)), "mpgeo_dataset_simulate")
+        return z
 
     def perm(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.int64)

@@ -1,7 +1,7 @@
 """Build libmpgeo.so (HIP, gfx950) in-tree with hipcc.
 
 Every HIP source under csrc/ is compiled to an object in parallel and linked into
-paper_2003_05324_amd/libmpgeo.so.  Run:  python -m paper_2003_05324_amd.build
+paper_2003_05324_amd/libmpgeo.so.  Run:  python paper_2003_05324_amd/build.py   (a plain script: the package itself loads the library)
 """
 from __future__ import annotations
 

@@ -902,6 +902,52 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
     return MPGEO_OK;
 }
 
+int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
+                           const double *eps, double *z_out) {
+    if (!ds || !eps || !z_out) return MPGEO_E_ARG;
+    MPGEO_TRY(check_theta(theta));
+    MPGEO_TRY(check_plan(plan));
+    Device dev(ds->ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    hipStream_t s = ds->ctx->stream;
+    const int64_t n = ds->n;
+    const bool on_dev = (ds->flags & MPGEO_INPUT_DEVICE) != 0;
+    // factor Sigma(theta) with a zero data vector (the dataset's z is kept aside)
+    DevBuf saved_z;
+    MPGEO_TRY(saved_z.ensure((size_t)n * sizeof(double)));
+    MPGEO_HIP(hipMemcpyAsync(saved_z.ptr, ds->z.ptr, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MPGEO_HIP(hipMemsetAsync(ds->z.ptr, 0, (size_t)n * sizeof(double), s));
+    mpgeo_result r{};
+    int st = evaluate(ds, theta, plan, &r, nullptr);
+    (void)hipMemcpyAsync(ds->z.ptr, saved_z.ptr, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (st != MPGEO_OK) {
+        (void)hipStreamSynchronize(s);
+        saved_z.release();
+        ds->has_factor = false;
+        return st;
+    }
+    const Layout &L = ds->layout;
+    const size_t vec = (size_t)L.p * L.nbp;
+    MPGEO_TRY(ds->tmp_a.ensure(2 * vec * sizeof(double) + 2 * (size_t)n * sizeof(double)));
+    double *eps_phys = ds->tmp_a.as<double>();
+    double *z_phys = eps_phys + vec;
+    double *lin_a = z_phys + vec;
+    double *lin_b = lin_a + n;
+    MPGEO_HIP(hipMemcpyAsync(lin_a, eps, (size_t)n * sizeof(double),
+                             on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    launch_permute(lin_a, lin_b, ds->perm.as<int64_t>(), n, false, s);        // ordered eps
+    launch_pad_vector(lin_b, eps_phys, n, L.nb, L.nbp, L.p, s);
+    launch_trmv(tile_map(ds), eps_phys, z_phys, s);
+    launch_unpad_vector(z_phys, lin_b, n, L.nb, L.nbp, s);
+    launch_permute(lin_b, lin_a, ds->perm.as<int64_t>(), n, true, s);         // caller order
+    MPGEO_HIP(hipGetLastError());
+    MPGEO_HIP(hipMemcpyAsync(z_out, lin_a, (size_t)n * sizeof(double),
+                             on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    saved_z.release();
+    return MPGEO_OK;
+}
+
 int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, const double *z,
                        mpgeo_plan plan, mpgeo_result *out) {
     if (!ctx || !out || !a || n < 1 || lda < n) return MPGEO_E_ARG;

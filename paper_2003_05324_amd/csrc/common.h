@@ -114,6 +114,12 @@ void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool f
 void launch_panel_solve(const TileMap &map, int k, const double *p64, const double *yk,
                         double *r, hipStream_t stream);
 
+// z = L eps over the tiles (physical padded vectors), lower triangle of diagonal tiles only.
+void launch_trmv(const TileMap &map, const double *eps, double *z, hipStream_t stream);
+// dst[perm[a]] = src[a] (to_caller) or dst[a] = src[perm[a]] (!to_caller), a < n.
+void launch_permute(const double *src, double *dst, const int64_t *perm, int64_t n, bool to_caller,
+                    hipStream_t stream);
+
 // Reduction of the per-step parts into {loglik, logdet, quad} (device double[3]).
 void launch_finalize(const double *logdet_part, const double *quad_part, int p, int64_t n,
                      double *result, hipStream_t stream);

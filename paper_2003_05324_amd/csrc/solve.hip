@@ -135,7 +135,50 @@ __global__ void column_var_kernel(const double *c, int64_t ldc, int64_t rows, in
     var[j] = sigma2 - s;
 }
 
+// z_i = sum_{j <= i} L_ij eps_j: one workgroup per (tile row i, 256-row block).
+__global__ __launch_bounds__(256) void trmv_kernel(TileMap map, const double *eps, double *z) {
+    __shared__ double es[kMaxTile];
+    const int nbp = map.nbp;
+    const int i = blockIdx.x;
+    const int row = blockIdx.y * 256 + threadIdx.x;
+    double s = 0.0;
+    for (int j = 0; j <= i; ++j) {
+        __syncthreads();
+        for (int c = threadIdx.x; c < nbp; c += 256) es[c] = eps[(int64_t)j * nbp + c];
+        __syncthreads();
+        if (row >= nbp) continue;
+        const bool f64 = tile_is_fp64(map, i, j);
+        const int64_t off = map.off[tri_index(i, j)];
+        const int cend = (j == i) ? row + 1 : nbp;   // only the lower triangle of L_ii
+        for (int c = 0; c < cend; ++c) {
+            const int64_t e = off + row + (int64_t)c * nbp;
+            const double lv = f64 ? map.pool64[e] : (double)map.pool32[e];
+            s += lv * es[c];
+        }
+    }
+    if (row < nbp) z[(int64_t)i * nbp + row] = s;
+}
+
+__global__ void permute_kernel(const double *src, double *dst, const int64_t *perm, int64_t n,
+                               bool to_caller) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    if (to_caller) dst[perm[a]] = src[a];
+    else dst[a] = src[perm[a]];
+}
+
 }  // namespace
+
+void launch_trmv(const TileMap &map, const double *eps, double *z, hipStream_t stream) {
+    dim3 grid((unsigned)map.p, (unsigned)((map.nbp + 255) / 256));
+    hipLaunchKernelGGL(trmv_kernel, grid, dim3(256), 0, stream, map, eps, z);
+}
+
+void launch_permute(const double *src, double *dst, const int64_t *perm, int64_t n, bool to_caller,
+                    hipStream_t stream) {
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src,
+                       dst, perm, n, to_caller);
+}
 
 void launch_panel_solve(const TileMap &map, int k, const double *p64, const double *yk, double *r,
                         hipStream_t stream) {

@@ -19,7 +19,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libmpgeo.so is not built (python -m paper_2003_05324_amd.build)")
+        pytest.fail("libmpgeo.so is not built (python paper_2003_05324_amd/build.py)")
     import torch  # noqa: F401  (same HIP runtime as the binding)
     return ctypes.CDLL(LIB)
 
