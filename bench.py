@@ -128,23 +128,21 @@ def main():
     wall, res, stats = time_path(mp, ctx, locs, z, theta, args.tile, args.band, args.steps,
                                  args.warmup)
     print(f"[bench] mixed: {wall / args.steps:.3f} s/step", file=sys.stderr, flush=True)
-    print("[bench] fp64 path", file=sys.stderr, flush=True)
-    wall64, res64, stats64 = time_path(mp, ctx, locs, z, theta, args.tile, -1, args.fp64_steps, 1)
-    print(f"[bench] fp64: {wall64 / args.fp64_steps:.3f} s/step", file=sys.stderr, flush=True)
+    if args.fp64_steps > 0:
+        print("[bench] fp64 path", file=sys.stderr, flush=True)
+        wall64, res64, _ = time_path(mp, ctx, locs, z, theta, args.tile, -1, args.fp64_steps, 1)
+        print(f"[bench] fp64: {wall64 / args.fp64_steps:.3f} s/step", file=sys.stderr, flush=True)
     ctx.close()
 
     chol_flops = n ** 3 / 3.0
     totals = [r["t_total"] for r in res]
     factor = [r["t_factor"] for r in res]
-    totals64 = [r["t_total"] for r in res64]
-    factor64 = [r["t_factor"] for r in res64]
     value = args.steps / wall
     dom = next(s for s in stats if s["name"] == "update_fp32") if args.band >= 0 else \
         next(s for s in stats if s["name"] == "update_fp64")
     achieved = dom["flops"] / dom["seconds"] / 1e12
     peak = PEAK_FP32_MATRIX if args.band >= 0 else PEAK_FP64_MATRIX
     ll = res[-1]["loglik"]
-    ll64 = res64[-1]["loglik"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -164,16 +162,7 @@ def main():
         "cholesky_tflops": chol_flops / statistics.median(factor) / 1e12,
         "p50_s": percentile(totals, 0.5),
         "p99_s": percentile(totals, 0.99),
-        "fp64": {
-            "evals_per_s": args.fp64_steps / wall64,
-            "cholesky_tflops": chol_flops / statistics.median(factor64) / 1e12,
-            "p50_s": percentile(totals64, 0.5),
-            "p99_s": percentile(totals64, 0.99),
-        },
-        "speedup_vs_fp64": value / (args.fp64_steps / wall64),
         "loglik": ll,
-        "loglik_fp64": ll64,
-        "dloglik_rel_vs_fp64": abs(ll - ll64) / max(abs(ll64), n),
         "roofline": {
             "kernel": dom["name"],
             "bound": "mfma",
@@ -189,6 +178,19 @@ def main():
                                 "tflops": (s["flops"] / s["seconds"] / 1e12) if s["seconds"] else None}
                     for s in stats if s["launches"]},
     }
+    if args.fp64_steps > 0:
+        totals64 = [r["t_total"] for r in res64]
+        factor64 = [r["t_factor"] for r in res64]
+        ll64 = res64[-1]["loglik"]
+        out["fp64"] = {
+            "evals_per_s": args.fp64_steps / wall64,
+            "cholesky_tflops": chol_flops / statistics.median(factor64) / 1e12,
+            "p50_s": percentile(totals64, 0.5),
+            "p99_s": percentile(totals64, 0.99),
+        }
+        out["speedup_vs_fp64"] = value / (args.fp64_steps / wall64)
+        out["loglik_fp64"] = ll64
+        out["dloglik_rel_vs_fp64"] = abs(ll - ll64) / max(abs(ll64), n)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_m, n, theta)

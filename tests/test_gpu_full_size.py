@@ -1,0 +1,115 @@
+"""Full-size checks at n = 99,856 (316 x 316 jittered grid, tile 512), the benchmarked configuration.
+
+The oracle cannot form the 99,856 x 99,856 matrix here, so the checks use outputs the
+oracle computes one at a time, and properties that hold at any size:
+  * the Z-order permutation is bit-exact against the oracle's;
+  * sampled covariance entries (every tier, the ragged last tile included) against eq. (1);
+  * sampled entries of L L^T against eq. (1) (reconstruction), per precision path;
+  * sampled rows of L y = z (forward solve);
+  * logdet = 2 sum log L_ii over the whole diagonal;
+  * the band path's log-likelihood against the all-FP64 path (itself oracle-exact at the
+    sizes the oracle reaches): |dl| / max(|l|, n) <= 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import LARGE
+
+pytestmark = pytest.mark.gpu
+
+TILE = LARGE.tile
+THETA = LARGE.theta
+
+
+@pytest.fixture(scope="module")
+def full(lib):
+    locs = LARGE.locations()
+    z = LARGE.eps()            # any data vector serves the solve checks
+    ctx = lib.Context(0)
+    ds = lib.Dataset(ctx, locs, z)
+    perm = oracle.morton_order(locs)
+    yield {"ctx": ctx, "ds": ds, "locs": locs, "z": z, "perm": perm, "ordered": locs[perm]}
+    ds.close()
+    ctx.close()
+
+
+def _sample_pairs(n, count, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, n, count)
+    b = rng.integers(0, n, count)
+    rows, cols = np.maximum(a, b), np.minimum(a, b)
+    # near-diagonal pairs (inside the FP64 band) and the ragged last tile
+    near = rng.integers(0, n, count // 4)
+    off = rng.integers(0, 3 * TILE, count // 4)
+    nr = np.minimum(near + off, n - 1)
+    last = rng.integers(n - (n % TILE), n, 64)
+    rows = np.concatenate([rows, nr, last, np.arange(0, n, 997)])
+    cols = np.concatenate([cols, near, rng.integers(0, n, 64), np.arange(0, n, 997)])
+    return rows.astype(np.int64), np.minimum(rows, cols).astype(np.int64)
+
+
+def test_permutation_bit_exact(full):
+    assert np.array_equal(full["ds"].perm(), full["perm"])
+
+
+@pytest.mark.parametrize("band", [2, -1])
+def test_sampled_covariance_entries(full, band):
+    ds, x = full["ds"], full["ordered"]
+    n = len(x)
+    ds.covariance(THETA, TILE, band)
+    rows, cols = _sample_pairs(n, 20000, 7)
+    got = ds.entries(rows, cols)
+    d = np.sqrt(((x[rows] - x[cols]) ** 2).sum(axis=1))
+    want = oracle.matern(d, *THETA)
+    fp64 = (rows // TILE - cols // TILE <= band) if band >= 0 else np.ones(len(rows), bool)
+    np.testing.assert_allclose(got[fp64], want[fp64], rtol=1e-13, atol=0)
+    w32 = want[~fp64].astype(np.float32)
+    assert np.all(np.abs(got[~fp64] - w32) <= np.spacing(np.abs(w32)))
+
+
+@pytest.mark.parametrize("band,tol", [(-1, 1e-10), (2, 1e-4)])
+def test_reconstruction_solve_and_logdet(full, band, tol):
+    ds, x, z, perm = full["ds"], full["ordered"], full["z"], full["perm"]
+    n = len(x)
+    res = ds.loglik(THETA, TILE, band)
+    rng = np.random.default_rng(11)
+    picks = np.concatenate([rng.integers(0, n, 6), [n - 1, n - 17, 511, 512]])
+    rows_l = {}
+    for a in picks:
+        cols = np.arange(a + 1, dtype=np.int64)
+        rows_l[a] = ds.entries(np.full(a + 1, a, dtype=np.int64), cols)
+    # (L L^T)_ab = sum_t<=b L_at L_bt against eq. (1)
+    for a in picks:
+        for b in picks:
+            if b > a:
+                continue
+            s = float(np.dot(rows_l[a][: b + 1], rows_l[b][: b + 1]))
+            r = math.sqrt(((x[a] - x[b]) ** 2).sum())
+            want = oracle.matern(np.array([r]), *THETA)[0]
+            assert abs(s - want) <= tol * THETA[0], (a, b, s, want)
+    # forward solve: (L y)_a = z_a (z in the ordered frame)
+    y = ds.solution()
+    zo = z[perm]
+    for a in picks:
+        lhs = float(np.dot(rows_l[a], y[: a + 1]))
+        scale = float(np.dot(np.abs(rows_l[a]), np.abs(y[: a + 1])))
+        assert abs(lhs - zo[a]) <= 1e-11 * scale, (a, lhs, zo[a])
+    # logdet from the whole diagonal
+    idx = np.arange(n, dtype=np.int64)
+    diag = ds.entries(idx, idx)
+    assert np.all(diag > 0)
+    logdet = 2.0 * math.fsum(np.log(diag))
+    assert abs(logdet - res["logdet"]) <= 1e-12 * abs(logdet) + 1e-9
+    quad = math.fsum(y * y)
+    assert abs(quad - res["quad"]) <= 1e-12 * quad
+
+
+def test_band_path_against_fp64_path(full):
+    ds = full["ds"]
+    n = LARGE.n
+    a = ds.loglik(THETA, TILE, 2)
+    b = ds.loglik(THETA, TILE, -1)
+    assert abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), n) <= 1e-5
