@@ -178,8 +178,8 @@ int mpgeo_dataset_entries(mpgeo_dataset *ds, int64_t count, const int64_t *rows,
  * shrink 1/2, initial steps of 0.1 in each log-parameter from `start`; theta is clamped
  * to [0.01, 10] x [0.001, 2] x [0.1, 3]; a point whose matrix is not positive definite
  * scores -infinity.  Stops when the simplex spans less than xtol (log units, max-norm),
- * when its log-likelihoods differ by less than ftol * |best|, or after max_evals
- * evaluations.  Writes the best theta, its log-likelihood, and the evaluation and
+ * when ftol > 0 and its log-likelihoods differ by less than ftol * |best|, or after
+ * max_evals evaluations.  Writes the best theta, its log-likelihood, and the evaluation and
  * iteration counts (any output pointer may be NULL). */
 int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
                       double ftol, int32_t max_evals, mpgeo_theta *theta_hat,

@@ -6,8 +6,10 @@ name the algorithm.  The reading used here is a plain Nelder-Mead simplex
 search (reflection 1, expansion 2, contraction 1/2, shrink 1/2) on
 u = log(theta), with theta clamped to box bounds, started at
 theta0 * (1.5, 0.5, 1.2) with initial simplex steps of 0.1 in log units, and
-stopped when the simplex spans less than xtol (log units, max-norm) or its
-function values differ by less than ftol * |f_best|, or after max_evals.
+stopped when the simplex spans less than xtol (log units, max-norm), or after
+max_evals.  (A stop on small differences of the function values, ftol > 0, is
+available but off: along the flat sigma2-range ridge of the Matérn likelihood it
+ends the search while theta is still far from the maximum.)
 """
 from __future__ import annotations
 
@@ -24,7 +26,7 @@ START_SCALE = (1.5, 0.5, 1.2)
 
 
 def nelder_mead(f: Callable[[np.ndarray], float], x0: Sequence[float], step: float = 0.1,
-                xtol: float = 1e-6, ftol: float = 1e-9, max_evals: int = 1000) -> dict:
+                xtol: float = 1e-6, ftol: float = 0.0, max_evals: int = 1000) -> dict:
     """Minimise f from x0 with the standard Nelder-Mead moves; returns x, f, evals, iters."""
     x0 = np.asarray(x0, dtype=np.float64)
     d = x0.size
@@ -41,7 +43,7 @@ def nelder_mead(f: Callable[[np.ndarray], float], x0: Sequence[float], step: flo
         simplex = [simplex[i] for i in order]
         fv = [fv[i] for i in order]
         span = max(np.max(np.abs(v - simplex[0])) for v in simplex[1:])
-        if span < xtol or abs(fv[-1] - fv[0]) <= ftol * abs(fv[0]):
+        if span < xtol or (ftol > 0 and abs(fv[-1] - fv[0]) <= ftol * abs(fv[0])):
             break
         iters += 1
         centroid = np.mean(simplex[:-1], axis=0)

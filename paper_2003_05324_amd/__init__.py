@@ -290,7 +290,7 @@ class Dataset:
         return out
 
     def mle(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
-            ftol: float = 1e-9, max_evals: int = 1000) -> dict:
+            ftol: float = 0.0, max_evals: int = 1000) -> dict:
         """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2))."""
         th = Theta()
         ll = ctypes.c_double()

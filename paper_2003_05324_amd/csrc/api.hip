@@ -76,6 +76,7 @@ struct Layout {
     std::vector<TileIJ> all, list64, list32;
     std::vector<int64_t> pre64, pre32;        // entries of each list with j > k (step k)
     std::vector<double> flops64, flops32;     // algorithmic flops of each step's update
+    std::vector<double> colf64, colf32;       // per tile column j (without the K = rows(k) factor)
     std::vector<double> trsm64_flops, trsm32_flops;
     int64_t n64 = 0, n32 = 0;                 // tiles per tier
 
@@ -128,6 +129,8 @@ struct Layout {
                     cnt32[j]++;
                 }
             }
+        colf64 = col64;
+        colf32 = col32;
         double s64 = 0, s32 = 0;
         int64_t c64 = 0, c32 = 0;
         for (int k = p - 1; k >= 0; --k) {
@@ -163,6 +166,21 @@ struct mpgeo_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;            // lookahead stream (next panel's critical path)
+    std::vector<hipEvent_t> sync_events;   // dependency events between the two streams
+
+    // at least `count` timing-free events for stream dependencies
+    bool ensure_sync_events(size_t count) {
+        while (sync_events.size() < count) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+            sync_events.push_back(e);
+        }
+        return true;
+    }
     struct Pending {
         int cls;
         hipEvent_t a, b;
@@ -189,6 +207,9 @@ struct mpgeo_ctx {
     }
     // launch wrapper: events around a launch when timing is on
     template <class F> void timed(int cls, double flops, double bytes, F &&launch) {
+        timed_on(stream, cls, flops, bytes, launch);
+    }
+    template <class F> void timed_on(hipStream_t st, int cls, double flops, double bytes, F &&launch) {
         if (!timing) {
             launch();
             return;
@@ -198,9 +219,9 @@ struct mpgeo_ctx {
             launch();
             return;
         }
-        (void)hipEventRecord(a, stream);
+        (void)hipEventRecord(a, st);
         launch();
-        (void)hipEventRecord(b, stream);
+        (void)hipEventRecord(b, st);
         pending.push_back({cls, a, b, flops, bytes});
     }
     void collect() {
@@ -288,8 +309,8 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     MPGEO_TRY(ds->all.ensure(std::max<size_t>(1, L.all.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list64.ensure(std::max<size_t>(1, L.list64.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list32.ensure(std::max<size_t>(1, L.list32.size()) * sizeof(TileIJ)));
-    MPGEO_TRY(ds->p64.ensure((size_t)L.p * te * sizeof(double)));
-    MPGEO_TRY(ds->p32.ensure((size_t)L.p * te * sizeof(float)));
+    MPGEO_TRY(ds->p64.ensure(2 * (size_t)L.p * te * sizeof(double)));   // two steps in flight
+    MPGEO_TRY(ds->p32.ensure(2 * (size_t)L.p * te * sizeof(float)));
     MPGEO_TRY(ds->linv.ensure((size_t)L.p * te * sizeof(double)));
     MPGEO_TRY(ds->linv32.ensure(te * sizeof(float)));
     const size_t vec = (size_t)L.p * L.nbp * sizeof(double);
@@ -376,9 +397,19 @@ int run_covgen(mpgeo_dataset *ds, const mpgeo_theta &th) {
 }
 
 // Factor the resident tiles, fused with the forward solve of z, then reduce.
+//
+// Two streams: the context stream runs the bulk of each step's trailing update (tile
+// columns j >= k+2); the side stream runs the critical path one step ahead: the update of
+// column k+1, then POTRF, panel solve and forward-solve step of k+1 (lookahead of depth 1).
+// Staging panels alternate between two buffers so step k+1's panel can be written while
+// step k's bulk update still reads step k's.  Dependencies:
+//   F(k)        = POTRF + TRSM + panel solve of step k            (side stream)
+//   U_col(k)    = update of column k+1 with panel k               (side; after U_bulk(k-1))
+//   U_bulk(k)   = update of columns >= k+2 with panel k           (main; after F(k))
 int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     mpgeo_ctx *ctx = ds->ctx;
-    hipStream_t s = ctx->stream;
+    hipStream_t s0 = ctx->stream;
+    hipStream_t s1 = ctx->side;
     const Layout &L = ds->layout;
     const TileMap map = tile_map(ds);
     const int nbp = L.nbp, p = L.p;
@@ -388,12 +419,23 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     double *logdet_part = ds->parts.as<double>();
     double *quad_part = logdet_part + p;
     unsigned long long *info = ds->info.as<unsigned long long>();
-    MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s));
-    launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s);
-    double *p64 = ds->p64.as<double>();
-    float *p32 = ds->p32.as<float>();
+    if (!ctx->ensure_sync_events(2 * (size_t)p + 1)) return MPGEO_E_DEVICE;
+    hipEvent_t ev_start = ctx->sync_events[0];
+    hipEvent_t *ev_f = ctx->sync_events.data() + 1;       // F(k) done
+    hipEvent_t *ev_bulk = ev_f + p;                        // U_bulk(k) done
+    MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s0));
+    launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
+    MPGEO_HIP(hipEventRecord(ev_start, s0));
+    MPGEO_HIP(hipStreamWaitEvent(s1, ev_start, 0));
     const double nbd = L.nb;
-    for (int k = 0; k < p; ++k) {
+    const TileIJ *l64 = ds->list64.as<TileIJ>();
+    const TileIJ *l32 = ds->list32.as<TileIJ>();
+
+    auto panel64 = [&](int k) { return ds->p64.as<double>() + (size_t)(k & 1) * p * te; };
+    auto panel32 = [&](int k) { return ds->p32.as<float>() + (size_t)(k & 1) * p * te; };
+
+    // F(k): POTRF, TRSM of the panel into staging (k & 1), panel solve of the forward solve
+    auto factor_step = [&](int k) {
         PotrfArgs pa;
         pa.a = ds->pool64.as<double>() + L.off[tri_index(k, k)];
         pa.linv = ds->linv.as<double>() + (int64_t)k * te;
@@ -407,37 +449,65 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         pa.nb = L.nb;
         pa.nbp = nbp;
         const double rk = (double)L.rows(k);
-        ctx->timed(kStatPotrf, rk * rk * rk / 3.0, rk * rk * 8.0 * 3.0,
-                   [&] { launch_potrf(pa, s); });
+        ctx->timed_on(s1, kStatPotrf, rk * rk * rk / 3.0, rk * rk * 8.0 * 3.0,
+                      [&] { launch_potrf(pa, s1); });
+        if (k + 1 >= p) return;
+        const int n64 = std::min(L.band, p - 1 - k);
+        const int first32 = k + L.band + 1;
+        const int n32 = first32 < p ? p - first32 : 0;
+        double *p64 = panel64(k);
+        float *p32 = panel32(k);
+        if (n64 > 0)
+            ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
+                launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, s1);
+            });
+        if (n32 > 0)
+            ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
+                launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, s1);
+            });
+        ctx->timed_on(s1, kStatPanel, 2.0 * (p - 1 - k) * nbd * nbd,
+                      (double)(p - 1 - k) * nbd * nbd * 16.0,
+                      [&] { launch_panel_solve(map, k, p64, pa.y, r, s1); });
+    };
+    // update of list entries [b, e) of both tiers with panel k on stream st
+    auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, double f64,
+                            double f32, hipStream_t st) {
+        if (e64 > b64)
+            ctx->timed_on(st, kStatUpdate64, f64, (double)(e64 - b64) * nbd * nbd * 8.0 * 2.0, [&] {
+                launch_update(map, l64 + b64, e64 - b64, true, panel64(k), panel32(k), st);
+            });
+        if (e32 > b32)
+            ctx->timed_on(st, kStatUpdate32, f32, (double)(e32 - b32) * nbd * nbd * 4.0 * 2.0, [&] {
+                launch_update(map, l32 + b32, e32 - b32, false, panel64(k), panel32(k), st);
+            });
+    };
+
+    factor_step(0);
+    MPGEO_HIP(hipEventRecord(ev_f[0], s1));
+    for (int k = 0; k < p; ++k) {
+        const double rk = (double)L.rows(k);
+        // bulk: columns >= k+2 (list prefix [0, pre[k+1]))
+        MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[k], 0));
         if (k + 1 < p) {
-            const int n64 = std::min(L.band, p - 1 - k);
-            const int first32 = k + L.band + 1;
-            const int n32 = first32 < p ? p - first32 : 0;
-            if (n64 > 0)
-                ctx->timed(kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
-                    launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, s);
-                });
-            if (n32 > 0)
-                ctx->timed(kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
-                    launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, s);
-                });
-            ctx->timed(kStatPanel, 2.0 * (p - 1 - k) * nbd * nbd, (double)(p - 1 - k) * nbd * nbd * 16.0,
-                       [&] { launch_panel_solve(map, k, p64, pa.y, r, s); });
-            const int64_t c64 = L.pre64[k], c32 = L.pre32[k];
-            if (c64 > 0)
-                ctx->timed(kStatUpdate64, L.flops64[k], (double)c64 * nbd * nbd * 8.0 * 2.0, [&] {
-                    launch_update(map, ds->list64.as<TileIJ>(), c64, true, p64, p32, s);
-                });
-            if (c32 > 0)
-                ctx->timed(kStatUpdate32, L.flops32[k], (double)c32 * nbd * nbd * 4.0 * 2.0, [&] {
-                    launch_update(map, ds->list32.as<TileIJ>(), c32, false, p64, p32, s);
-                });
+            const double c64 = L.colf64[k + 1] * rk, c32 = L.colf32[k + 1] * rk;
+            update_range(k, 0, L.pre64[k + 1], 0, L.pre32[k + 1], L.flops64[k] - c64,
+                         L.flops32[k] - c32, s0);
+        }
+        MPGEO_HIP(hipEventRecord(ev_bulk[k], s0));
+        if (k + 1 < p) {
+            // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
+            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
+            update_range(k, L.pre64[k + 1], L.pre64[k], L.pre32[k + 1], L.pre32[k],
+                         L.colf64[k + 1] * rk, L.colf32[k + 1] * rk, s1);
+            factor_step(k + 1);
+            MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
         MPGEO_HIP(hipGetLastError());
     }
-    if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s));
+    MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[p - 1], 0));
+    if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s0));
     ctx->timed(kStatFinal, 2.0 * p, 16.0 * p, [&] {
-        launch_finalize(logdet_part, quad_part, p, L.n, ds->result.as<double>(), s);
+        launch_finalize(logdet_part, quad_part, p, L.n, ds->result.as<double>(), s0);
     });
     MPGEO_HIP(hipGetLastError());
     return MPGEO_OK;
@@ -564,6 +634,12 @@ int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return MPGEO_E_DEVICE;
+    }
     c->reset_stats();
     *out = c;
     return MPGEO_OK;
@@ -578,6 +654,9 @@ int mpgeo_ctx_destroy(mpgeo_ctx *ctx) {
     if (ctx->scratch_ds) mpgeo_dataset_destroy(ctx->scratch_ds);
     ctx->collect();
     for (auto e : ctx->spare) (void)hipEventDestroy(e);
+    for (auto e : ctx->sync_events) (void)hipEventDestroy(e);
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return MPGEO_OK;
@@ -837,7 +916,7 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
         double span = 0.0;
         for (int v = 1; v < 4; ++v)
             for (int q = 0; q < 3; ++q) span = std::max(span, std::fabs(x[v][q] - x[0][q]));
-        if (span < xtol || std::fabs(fv[3] - fv[0]) <= ftol * std::fabs(fv[0])) break;
+        if (span < xtol || (ftol > 0.0 && std::fabs(fv[3] - fv[0]) <= ftol * std::fabs(fv[0]))) break;
         ++iters;
         double c[3], xr[3], xe[3], xc[3];
         for (int q = 0; q < 3; ++q) c[q] = (x[0][q] + x[1][q] + x[2][q]) / 3.0;

@@ -36,7 +36,7 @@ template <> struct Mfma<float> {
 };
 template <> struct Mfma<double> {
     using acc_t = f64x4;
-    static constexpr int kKC = 8;
+    static constexpr int kKC = 16;
     __device__ static acc_t mac(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -45,11 +45,13 @@ template <> struct Mfma<double> {
 };
 
 constexpr int kThreads = 256;
+constexpr int kXcds = 8;
 
 enum Epilogue { kUpdate = 0, kTrsm = 1 };
 
 struct GemmArgs {
     TileMap map;
+    int64_t ntiles;       // output tiles in this launch
     const TileIJ *list;   // update: output tiles (i, j)
     int k;                // step (trsm: panel column; output rows i = i_begin + tile)
     int i_begin;
@@ -76,8 +78,15 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
 
     const int nbp = g.map.nbp;
     const int per_side = nbp / MT;
-    const int macro = blockIdx.x % (per_side * per_side);
-    const int tile = blockIdx.x / (per_side * per_side);
+    const int per_tile = per_side * per_side;
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Map
+    // them so that all macro blocks of one output tile run on the same XCD: its row and
+    // column panel slices are then re-read from that XCD's L2.
+    const int xcd = blockIdx.x % kXcds;
+    const int local = blockIdx.x / kXcds;
+    const int macro = local % per_tile;
+    const int tile = (local / per_tile) * kXcds + xcd;
+    if (tile >= g.ntiles) return;
     const int mr = macro % per_side;   // row block
     const int mc = macro / per_side;   // column block
 
@@ -111,13 +120,36 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
     const int wr = wave & 1;    // wave row half
     const int wc = wave >> 1;   // wave column half
 
+    const int lrow = lane & 15;      // position inside a 16-block
+    const int lk = lane >> 4;        // k within the 4-step
+
+    // FP64 update: the accumulators start from the C block itself (its loads overlap the
+    // first chunk's) and take -R Q^T; the epilogue is then a plain store.  FP32 update: the
+    // product is accumulated from zero and subtracted from C once at the end, so partial sums
+    // are rounded at the scale of the product rather than of C (as a BLAS sgemm with beta = 1
+    // would).  TRSM starts from 0.
+    constexpr bool kPreload = (EPI == kUpdate) && (sizeof(T) == 8);
+    T *C = nullptr;
+    if (EPI == kUpdate) {
+        const int64_t off = g.map.off[tri_index(ti, tj)];
+        C = (sizeof(T) == 8) ? reinterpret_cast<T *>(g.map.pool64 + off)
+                             : reinterpret_cast<T *>(g.map.pool32 + off);
+    }
     acc_t acc[NB16][NB16];      // [col block][row block]
 #pragma unroll
     for (int a = 0; a < NB16; ++a)
 #pragma unroll
         for (int b = 0; b < NB16; ++b)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[a][b][q] = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (kPreload) {
+                    const int row = row0 + wr * WT + b * 16 + lrow;
+                    const int col = col0 + wc * WT + a * 16 + M::m_index(lk, q);
+                    acc[a][b][q] = C[row + (int64_t)col * nbp];
+                } else {
+                    acc[a][b][q] = 0;
+                }
+            }
 
     vec_t regQ[VPT], regR[VPT];
     auto load_chunk = [&](int k0) {
@@ -146,12 +178,12 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
         }
     };
 
-    const int nchunks = nbp / KC;
+    // TRSM: Q = L_kk^-1 is lower triangular (Q[col][t] = 0 for t > col), so K stops after
+    // this block's last column
+    const int nchunks = (EPI == kTrsm) ? (col0 + MT) / KC : nbp / KC;
     load_chunk(0);
     store_chunk(0);
     __syncthreads();
-    const int lrow = lane & 15;      // position inside a 16-block
-    const int lk = lane >> 4;        // k within the 4-step
     for (int c = 0; c < nchunks; ++c) {
         const int buf = c & 1;
         if (c + 1 < nchunks) load_chunk((c + 1) * KC);
@@ -162,7 +194,10 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
             const int t = 4 * s + lk;
             T qa[NB16], rb[NB16];
 #pragma unroll
-            for (int a = 0; a < NB16; ++a) qa[a] = sq[t * LDS_LD + wc * WT + a * 16 + lrow];
+            for (int a = 0; a < NB16; ++a) {
+                qa[a] = sq[t * LDS_LD + wc * WT + a * 16 + lrow];
+                if (EPI == kUpdate) qa[a] = -qa[a];
+            }
 #pragma unroll
             for (int b = 0; b < NB16; ++b) rb[b] = sr[t * LDS_LD + wr * WT + b * 16 + lrow];
 #pragma unroll
@@ -176,10 +211,6 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
 
     // acc[a][b][q] holds output (row = b-block row lrow, col = a-block col m_index(lk, q))
     if (EPI == kUpdate) {
-        T *C;
-        const int64_t off = g.map.off[tri_index(ti, tj)];
-        C = (sizeof(T) == 8) ? reinterpret_cast<T *>(g.map.pool64 + off)
-                             : reinterpret_cast<T *>(g.map.pool32 + off);
 #pragma unroll
         for (int a = 0; a < NB16; ++a)
 #pragma unroll
@@ -188,8 +219,9 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
                 for (int q = 0; q < 4; ++q) {
                     const int row = row0 + wr * WT + b * 16 + lrow;
                     const int col = col0 + wc * WT + a * 16 + M::m_index(lk, q);
-                    T *p = C + row + (int64_t)col * nbp;
-                    *p = *p - acc[a][b][q];
+                    T *pc = C + row + (int64_t)col * nbp;
+                    if (kPreload) *pc = acc[a][b][q];
+                    else *pc = *pc + acc[a][b][q];
                 }
     } else {
         double *o64 = g.p64 + (int64_t)ti * nbp * nbp;
@@ -215,18 +247,21 @@ void launch_gemm(const GemmArgs &g, int64_t ntiles, bool diag_skip_free, hipStre
     (void)diag_skip_free;
     const int nbp = g.map.nbp;
     if (ntiles <= 0) return;
+    GemmArgs ga = g;
+    ga.ntiles = ntiles;
+    const int64_t slots = (ntiles + kXcds - 1) / kXcds * kXcds;   // whole tiles per XCD
     if (nbp % 128 == 0) {
-        const int64_t blocks = ntiles * (nbp / 128) * (nbp / 128);
+        const int64_t blocks = slots * (nbp / 128) * (nbp / 128);
         hipLaunchKernelGGL((tile_gemm_kernel<T, 128, EPI>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                           stream, g);
+                           stream, ga);
     } else if (nbp % 64 == 0) {
-        const int64_t blocks = ntiles * (nbp / 64) * (nbp / 64);
+        const int64_t blocks = slots * (nbp / 64) * (nbp / 64);
         hipLaunchKernelGGL((tile_gemm_kernel<T, 64, EPI>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                           stream, g);
+                           stream, ga);
     } else {
-        const int64_t blocks = ntiles * (nbp / 32) * (nbp / 32);
+        const int64_t blocks = slots * (nbp / 32) * (nbp / 32);
         hipLaunchKernelGGL((tile_gemm_kernel<T, 32, EPI>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                           stream, g);
+                           stream, ga);
     }
 }
 

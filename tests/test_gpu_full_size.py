@@ -107,9 +107,19 @@ def test_reconstruction_solve_and_logdet(full, band, tol):
     assert abs(quad - res["quad"]) <= 1e-12 * quad
 
 
-def test_band_path_against_fp64_path(full):
-    ds = full["ds"]
+def test_band_path_against_fp64_path(lib, full):
+    # data drawn from the field itself (as in the benchmark): z = P^T L P eps with the FP64
+    # factor (the sampler is checked against the oracle at small n).  White noise as data
+    # would put most of quad on the smallest eigenvalues, where FP32 far tiles are amplified
+    # by the condition number; that is not the regime the method is meant for.
+    ctx, locs = full["ctx"], full["locs"]
+    gen = lib.Dataset(ctx, locs, None)
+    z = gen.simulate(THETA, LARGE.eps(), TILE, -1)
+    gen.close()
+    ds = lib.Dataset(ctx, locs, z)
     n = LARGE.n
     a = ds.loglik(THETA, TILE, 2)
     b = ds.loglik(THETA, TILE, -1)
+    ds.close()
     assert abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), n) <= 1e-5
+    assert abs(a["logdet"] - b["logdet"]) / abs(b["logdet"]) <= 1e-6

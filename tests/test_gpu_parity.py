@@ -263,6 +263,22 @@ def test_kriging_matches_oracle(lib, ctx, band):
     ds.close()
 
 
+@pytest.mark.parametrize("band", [-1, 2])
+def test_field_sampler_matches_oracle(lib, ctx, band):
+    # z = P^T L P eps: the oracle draws the same field in the ordered frame
+    locs = jittered_grid(30, 51)
+    eps = normals(len(locs), 52)
+    theta = (1.1, 0.08, 0.5)
+    ds = lib.Dataset(ctx, locs, None)
+    z = ds.simulate(theta, eps, 128, band)
+    perm = ds.perm()
+    ds.close()
+    want = np.empty(len(locs))
+    want[perm] = oracle.simulate_field(locs[perm], theta, eps[perm])
+    tol = 1e-11 if band < 0 else 1e-5
+    assert np.max(np.abs(z - want)) <= tol * np.max(np.abs(want))
+
+
 def test_argument_validation(lib, ctx, small_ds):
     with pytest.raises(lib.MpgeoError) as e:
         small_ds.loglik((1.0, -0.1, 0.5), 160, 2)

@@ -71,3 +71,21 @@ def test_nelder_mead_finds_known_minima():
 
     res = nelder_mead(rosen, [-1.0, 1.5, 0.5], step=0.5, xtol=1e-10, ftol=0, max_evals=20000)
     np.testing.assert_allclose(res["x"], [1, 1, 1], atol=1e-6)
+
+
+def test_stored_mle_is_a_profile_maximum():
+    # For fixed (range, smoothness) eq. (2) is maximised over the variance by
+    # sigma2 = Z^T Sigma~^-1 Z / n (Sigma~ at unit variance).  The stored oracle fit must
+    # satisfy this closed form to the optimiser's tolerance.
+    import json
+    import os
+
+    from oracle import loglik, simulate_field
+    from synthetic import SMALL
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mle_small.json")))
+    s2, beta, nu = gold["theta_hat"]
+    locs = SMALL.locations()
+    z = simulate_field(locs, SMALL.theta, SMALL.eps())
+    q = loglik(locs, z, (1.0, beta, nu))["quad"]
+    assert abs(s2 - q / len(z)) / s2 <= 1e-4
+    assert abs(loglik(locs, z, (s2, beta, nu))["loglik"] - gold["loglik_hat"]) <= 1e-8 * abs(gold["loglik_hat"])
