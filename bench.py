@@ -29,6 +29,25 @@ sys.path.insert(0, ROOT)
 METRIC = "log-lik evals/sec + Cholesky TFLOP/s at n=100k (mixed vs FP64); p50/p99 latency"
 PEAK_FP32_MATRIX = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MATRIX = 78.6    # TFLOP/s, MI355X dense FP64 matrix
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "update_fp32_hbm_traffic_matern-n99856-nb512-band2.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2003_05324_amd", "csrc", "gemm.hip")
+
+
+def measured_traffic(n, tile, band):
+    """HBM bytes per launch of the FP32 update kernel from the committed rocprofv3 counter
+    summary, or None when the workload differs or the kernel source changed since."""
+    import hashlib
+    import re
+    if (n, tile, band) != (99856, 512, 2) or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    sha = re.search(r"gemm.hip sha256 at measurement: ([0-9a-f]+)", text)
+    val = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+    if not sha or not val:
+        return None
+    if hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest() != sha.group(1):
+        return None
+    return float(val.group(1))
 
 
 def parse():
@@ -170,7 +189,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(n, args.tile, args.band) if args.band >= 0 else None,
             "avg_launch_ms": 1e3 * dom["seconds"] / dom["launches"],
             "launches": dom["launches"],
         },

@@ -5,8 +5,8 @@
 // C[rows, cols] (+)= sum_t R[row, t] Q[col, t] over square nbp x nbp column-major tiles,
 // where R supplies the rows of the output and Q its columns.
 //
-// A workgroup of 256 threads (4 waves, 2 x 2) computes an MT x MT block of one output
-// tile; each wave owns an (MT/2) x (MT/2) sub-block made of 16 x 16 MFMA blocks
+// A workgroup of 64 * WM * WN threads computes a BM x BN block of one output tile; wave
+// (wr, wc) owns a (BM/WM) x (BN/WN) sub-block made of 16 x 16 MFMA blocks
 // (v_mfma_f64_16x16x4_f64 for FP64 tiles, v_mfma_f32_16x16x4_f32 for FP32 tiles).
 // K is walked in chunks of KC columns staged through LDS as [t][row] (rows contiguous,
 // like the tiles), double-buffered, with the next chunk prefetched into registers while
@@ -27,7 +27,6 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
     using acc_t = f32x4;
-    static constexpr int kKC = 16;
     __device__ static acc_t mac(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -36,7 +35,6 @@ template <> struct Mfma<float> {
 };
 template <> struct Mfma<double> {
     using acc_t = f64x4;
-    static constexpr int kKC = 16;
     __device__ static acc_t mac(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -44,7 +42,6 @@ template <> struct Mfma<double> {
     __device__ static int m_index(int g, int q) { return g + 4 * q; }
 };
 
-constexpr int kThreads = 256;
 constexpr int kXcds = 8;
 
 enum Epilogue { kUpdate = 0, kTrsm = 1 };
@@ -61,34 +58,46 @@ struct GemmArgs {
     float *p32;
 };
 
-template <typename T, int MT, int EPI>
-__global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
+// Block shape: BM output rows x BN output columns per workgroup, WM x WN waves, K chunk KC.
+template <int BM_, int BN_, int WM_, int WN_, int KC_> struct Shape {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_;
+    static constexpr int kThreads = 64 * WM * WN;
+};
+
+template <typename T, typename S, int EPI>
+__global__ __launch_bounds__(S::kThreads) void tile_gemm_kernel(GemmArgs g) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
-    constexpr int KC = M::kKC;
-    constexpr int WT = MT / 2;          // wave sub-block
-    constexpr int NB16 = WT / 16;       // 16 x 16 blocks per wave side
-    constexpr int LDS_LD = MT + 16;     // padded LDS row (spreads the 4 k-rows over banks)
-    constexpr int VEC = 16 / sizeof(T); // elements per 16-byte load
-    constexpr int NVEC = KC * MT / VEC; // 16-byte vectors per operand chunk
-    constexpr int VPT = (NVEC + kThreads - 1) / kThreads;
+    constexpr int BM = S::BM, BN = S::BN, KC = S::KC, NT = S::kThreads;
+    constexpr int NBR = BM / S::WM / 16;   // 16-row blocks per wave
+    constexpr int NBC = BN / S::WN / 16;   // 16-column blocks per wave
+    constexpr int LDQ = BN + 16;           // padded LDS rows (spread the 4 k-rows over banks)
+    constexpr int LDR = BM + 16;
+    constexpr int VEC = 16 / sizeof(T);    // elements per 16-byte load
+    constexpr int NVQ = KC * BN / VEC;     // 16-byte vectors per chunk of Q
+    constexpr int NVR = KC * BM / VEC;
+    constexpr int VPQ = (NVQ + NT - 1) / NT;
+    constexpr int VPR = (NVR + NT - 1) / NT;
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
 
-    __shared__ T lds[2][2][KC * LDS_LD];   // [buffer][operand: 0 = Q, 1 = R]
+    __shared__ T ldsq[2][KC * LDQ];
+    __shared__ T ldsr[2][KC * LDR];
 
     const int nbp = g.map.nbp;
-    const int per_side = nbp / MT;
-    const int per_tile = per_side * per_side;
+    const int rows_per = nbp / BM, cols_per = nbp / BN;
+    const int per_tile = rows_per * cols_per;
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Map
-    // them so that all macro blocks of one output tile run on the same XCD: its row and
-    // column panel slices are then re-read from that XCD's L2.
+    // them so that all blocks of one output tile run on the same XCD: its row and column
+    // panel slices are then re-read from that XCD's L2.
     const int xcd = blockIdx.x % kXcds;
     const int local = blockIdx.x / kXcds;
     const int macro = local % per_tile;
     const int tile = (local / per_tile) * kXcds + xcd;
     if (tile >= g.ntiles) return;
-    const int mr = macro % per_side;   // row block
-    const int mc = macro / per_side;   // column block
+    const int mr = macro % rows_per;   // row block
+    const int mc = macro / rows_per;   // column block
+    const int row0 = mr * BM;
+    const int col0 = mc * BN;
 
     const T *R;
     const T *Q;
@@ -97,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
         const TileIJ t = g.list[tile];
         ti = t.i;
         tj = t.j;
-        if (ti == tj && mc > mr) return;   // strictly upper part of a diagonal tile
+        if (ti == tj && col0 >= row0 + BM) return;   // strictly upper part of a diagonal tile
         const T *panel = static_cast<const T *>(g.panel);
         R = panel + (int64_t)ti * nbp * nbp;
         Q = panel + (int64_t)tj * nbp * nbp;
@@ -109,17 +118,16 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
                              : reinterpret_cast<const T *>(g.map.pool32 + off);
         Q = static_cast<const T *>(g.linv);
     }
-    const int row0 = mr * MT;
-    const int col0 = mc * MT;
     R += row0;
     Q += col0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wr = wave & 1;    // wave row half
-    const int wc = wave >> 1;   // wave column half
-
+    const int wr = wave % S::WM;
+    const int wc = wave / S::WM;
+    const int wrow = wr * (BM / S::WM);
+    const int wcol = wc * (BN / S::WN);
     const int lrow = lane & 15;      // position inside a 16-block
     const int lk = lane >> 4;        // k within the 4-step
 
@@ -135,75 +143,86 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
         C = (sizeof(T) == 8) ? reinterpret_cast<T *>(g.map.pool64 + off)
                              : reinterpret_cast<T *>(g.map.pool32 + off);
     }
-    acc_t acc[NB16][NB16];      // [col block][row block]
+    acc_t acc[NBC][NBR];      // [column block][row block]
 #pragma unroll
-    for (int a = 0; a < NB16; ++a)
+    for (int a = 0; a < NBC; ++a)
 #pragma unroll
-        for (int b = 0; b < NB16; ++b)
+        for (int b = 0; b < NBR; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (kPreload) {
-                    const int row = row0 + wr * WT + b * 16 + lrow;
-                    const int col = col0 + wc * WT + a * 16 + M::m_index(lk, q);
+                    const int row = row0 + wrow + b * 16 + lrow;
+                    const int col = col0 + wcol + a * 16 + M::m_index(lk, q);
                     acc[a][b][q] = C[row + (int64_t)col * nbp];
                 } else {
                     acc[a][b][q] = 0;
                 }
             }
 
-    vec_t regQ[VPT], regR[VPT];
+    vec_t regQ[VPQ], regR[VPR];
     auto load_chunk = [&](int k0) {
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int idx = v * kThreads + tid;
-            if (idx < NVEC) {
-                const int t = idx / (MT / VEC);
-                const int rv = idx % (MT / VEC);
-                const int64_t e = (int64_t)(k0 + t) * nbp + rv * VEC;
-                regQ[v] = *reinterpret_cast<const vec_t *>(Q + e);
-                regR[v] = *reinterpret_cast<const vec_t *>(R + e);
+        for (int v = 0; v < VPQ; ++v) {
+            const int idx = v * NT + tid;
+            if (NVQ % NT == 0 || idx < NVQ) {
+                const int t = idx / (BN / VEC), rv = idx % (BN / VEC);
+                regQ[v] = *reinterpret_cast<const vec_t *>(Q + (int64_t)(k0 + t) * nbp + rv * VEC);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VPR; ++v) {
+            const int idx = v * NT + tid;
+            if (NVR % NT == 0 || idx < NVR) {
+                const int t = idx / (BM / VEC), rv = idx % (BM / VEC);
+                regR[v] = *reinterpret_cast<const vec_t *>(R + (int64_t)(k0 + t) * nbp + rv * VEC);
             }
         }
     };
     auto store_chunk = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < VPT; ++v) {
-            const int idx = v * kThreads + tid;
-            if (idx < NVEC) {
-                const int t = idx / (MT / VEC);
-                const int rv = idx % (MT / VEC);
-                *reinterpret_cast<vec_t *>(&lds[buf][0][t * LDS_LD + rv * VEC]) = regQ[v];
-                *reinterpret_cast<vec_t *>(&lds[buf][1][t * LDS_LD + rv * VEC]) = regR[v];
+        for (int v = 0; v < VPQ; ++v) {
+            const int idx = v * NT + tid;
+            if (NVQ % NT == 0 || idx < NVQ) {
+                const int t = idx / (BN / VEC), rv = idx % (BN / VEC);
+                *reinterpret_cast<vec_t *>(&ldsq[buf][t * LDQ + rv * VEC]) = regQ[v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VPR; ++v) {
+            const int idx = v * NT + tid;
+            if (NVR % NT == 0 || idx < NVR) {
+                const int t = idx / (BM / VEC), rv = idx % (BM / VEC);
+                *reinterpret_cast<vec_t *>(&ldsr[buf][t * LDR + rv * VEC]) = regR[v];
             }
         }
     };
 
     // TRSM: Q = L_kk^-1 is lower triangular (Q[col][t] = 0 for t > col), so K stops after
     // this block's last column
-    const int nchunks = (EPI == kTrsm) ? (col0 + MT) / KC : nbp / KC;
+    const int nchunks = (EPI == kTrsm) ? (col0 + BN) / KC : nbp / KC;
     load_chunk(0);
     store_chunk(0);
     __syncthreads();
     for (int c = 0; c < nchunks; ++c) {
         const int buf = c & 1;
         if (c + 1 < nchunks) load_chunk((c + 1) * KC);
-        const T *sq = lds[buf][0];
-        const T *sr = lds[buf][1];
+        const T *sq = ldsq[buf];
+        const T *sr = ldsr[buf];
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
             const int t = 4 * s + lk;
-            T qa[NB16], rb[NB16];
+            T qa[NBC], rb[NBR];
 #pragma unroll
-            for (int a = 0; a < NB16; ++a) {
-                qa[a] = sq[t * LDS_LD + wc * WT + a * 16 + lrow];
+            for (int a = 0; a < NBC; ++a) {
+                qa[a] = sq[t * LDQ + wcol + a * 16 + lrow];
                 if (EPI == kUpdate) qa[a] = -qa[a];
             }
 #pragma unroll
-            for (int b = 0; b < NB16; ++b) rb[b] = sr[t * LDS_LD + wr * WT + b * 16 + lrow];
+            for (int b = 0; b < NBR; ++b) rb[b] = sr[t * LDR + wrow + b * 16 + lrow];
 #pragma unroll
-            for (int a = 0; a < NB16; ++a)
+            for (int a = 0; a < NBC; ++a)
 #pragma unroll
-                for (int b = 0; b < NB16; ++b) acc[a][b] = M::mac(qa[a], rb[b], acc[a][b]);
+                for (int b = 0; b < NBR; ++b) acc[a][b] = M::mac(qa[a], rb[b], acc[a][b]);
         }
         if (c + 1 < nchunks) store_chunk(buf ^ 1);
         __syncthreads();
@@ -212,13 +231,13 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
     // acc[a][b][q] holds output (row = b-block row lrow, col = a-block col m_index(lk, q))
     if (EPI == kUpdate) {
 #pragma unroll
-        for (int a = 0; a < NB16; ++a)
+        for (int a = 0; a < NBC; ++a)
 #pragma unroll
-            for (int b = 0; b < NB16; ++b)
+            for (int b = 0; b < NBR; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row = row0 + wr * WT + b * 16 + lrow;
-                    const int col = col0 + wc * WT + a * 16 + M::m_index(lk, q);
+                    const int row = row0 + wrow + b * 16 + lrow;
+                    const int col = col0 + wcol + a * 16 + M::m_index(lk, q);
                     T *pc = C + row + (int64_t)col * nbp;
                     if (kPreload) *pc = acc[a][b][q];
                     else *pc = *pc + acc[a][b][q];
@@ -227,13 +246,13 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
         double *o64 = g.p64 + (int64_t)ti * nbp * nbp;
         float *o32 = g.p32 + (int64_t)ti * nbp * nbp;
 #pragma unroll
-        for (int a = 0; a < NB16; ++a)
+        for (int a = 0; a < NBC; ++a)
 #pragma unroll
-            for (int b = 0; b < NB16; ++b)
+            for (int b = 0; b < NBR; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row = row0 + wr * WT + b * 16 + lrow;
-                    const int col = col0 + wc * WT + a * 16 + M::m_index(lk, q);
+                    const int row = row0 + wrow + b * 16 + lrow;
+                    const int col = col0 + wcol + a * 16 + M::m_index(lk, q);
                     const int64_t e = row + (int64_t)col * nbp;
                     const T v = acc[a][b][q];
                     o64[e] = (double)v;
@@ -242,27 +261,26 @@ __global__ __launch_bounds__(kThreads) void tile_gemm_kernel(GemmArgs g) {
     }
 }
 
-template <typename T, int EPI>
-void launch_gemm(const GemmArgs &g, int64_t ntiles, bool diag_skip_free, hipStream_t stream) {
-    (void)diag_skip_free;
-    const int nbp = g.map.nbp;
-    if (ntiles <= 0) return;
+template <typename T, typename S, int EPI>
+void launch_shape(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
     GemmArgs ga = g;
     ga.ntiles = ntiles;
+    const int nbp = g.map.nbp;
     const int64_t slots = (ntiles + kXcds - 1) / kXcds * kXcds;   // whole tiles per XCD
-    if (nbp % 128 == 0) {
-        const int64_t blocks = slots * (nbp / 128) * (nbp / 128);
-        hipLaunchKernelGGL((tile_gemm_kernel<T, 128, EPI>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                           stream, ga);
-    } else if (nbp % 64 == 0) {
-        const int64_t blocks = slots * (nbp / 64) * (nbp / 64);
-        hipLaunchKernelGGL((tile_gemm_kernel<T, 64, EPI>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                           stream, ga);
-    } else {
-        const int64_t blocks = slots * (nbp / 32) * (nbp / 32);
-        hipLaunchKernelGGL((tile_gemm_kernel<T, 32, EPI>), dim3((unsigned)blocks), dim3(kThreads), 0,
-                           stream, ga);
-    }
+    const int64_t blocks = slots * (nbp / S::BM) * (nbp / S::BN);
+    hipLaunchKernelGGL((tile_gemm_kernel<T, S, EPI>), dim3((unsigned)blocks), dim3(S::kThreads), 0,
+                       stream, ga);
+}
+
+// Production shapes: 128 x 128 blocks of 4 waves when the tile allows, else 64 or 32;
+// K chunks of 16 columns.
+template <typename T, int EPI>
+void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
+    const int nbp = g.map.nbp;
+    if (ntiles <= 0) return;
+    if (nbp % 128 == 0) launch_shape<T, Shape<128, 128, 2, 2, 16>, EPI>(g, ntiles, stream);
+    else if (nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 16>, EPI>(g, ntiles, stream);
+    else launch_shape<T, Shape<32, 32, 2, 2, 16>, EPI>(g, ntiles, stream);
 }
 
 }  // namespace
@@ -278,10 +296,10 @@ void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, c
     g.p32 = p32;
     if (fp64) {
         g.linv = linv;
-        launch_gemm<double, kTrsm>(g, count, false, stream);
+        launch_gemm<double, kTrsm>(g, count, stream);
     } else {
         g.linv = linv32;
-        launch_gemm<float, kTrsm>(g, count, false, stream);
+        launch_gemm<float, kTrsm>(g, count, stream);
     }
 }
 
@@ -293,10 +311,10 @@ void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool f
     g.list = list;
     if (fp64) {
         g.panel = p64;
-        launch_gemm<double, kUpdate>(g, count, false, stream);
+        launch_gemm<double, kUpdate>(g, count, stream);
     } else {
         g.panel = p32;
-        launch_gemm<float, kUpdate>(g, count, false, stream);
+        launch_gemm<float, kUpdate>(g, count, stream);
     }
 }
 
