@@ -2,9 +2,13 @@
 
 One step = one whole evaluation of eq. (2) through the C-ABI one-shot entry point with the
 inputs resident in HBM: Z-order ordering of the locations, Matérn covariance tiles, the
-mixed-precision tile Cholesky (FP64 within 2 tiles of the diagonal, FP32 beyond, tile 512)
-with the fused forward solve, log-determinant and reduction.  The all-FP64 path is timed
-beside it on the same inputs.
+mixed-precision tile Cholesky with the fused forward solve, log-determinant and reduction.
+
+The timed (headline) path is the three-precision-tier plan of the n ~ 1e5 workload: FP64
+within 2 tiles of the diagonal, FP32 for the next 8 tiles, FP16 operands (power-of-two
+scaled per tile, FP32 accumulation) beyond, tile 512.  The two-tier band path (FP64 band 2,
+FP32 beyond) and the all-FP64 path are timed beside it on the same inputs, and the
+log-likelihood error of each mixed path against the FP64 path is reported.
 
 Inputs: a jittered 316 x 316 grid in ]0,1[^2 (n = 99,856), theta = (1, 0.1, 0.5), and z a
 draw of the Matérn field at theta (z = L eps with L the library's FP64 factor, drawn once
@@ -27,8 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "log-lik evals/sec + Cholesky TFLOP/s at n=100k (mixed vs FP64); p50/p99 latency"
+PEAK_FP16_MATRIX = 2516.6  # TFLOP/s, MI355X dense FP16 / BF16 matrix
 PEAK_FP32_MATRIX = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MATRIX = 78.6    # TFLOP/s, MI355X dense FP64 matrix
+PEAKS = {"update_lowp": PEAK_FP16_MATRIX, "update_fp32": PEAK_FP32_MATRIX,
+         "update_fp64": PEAK_FP64_MATRIX}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "update_fp32_hbm_traffic_matern-n99856-nb512-band2.md")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2003_05324_amd", "csrc", "gemm.hip")
 
@@ -56,6 +63,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--two-tier-steps", type=int, default=2)
+    ap.add_argument("--band32", type=int, default=8)
+    ap.add_argument("--lowp", default="fp16", choices=["fp16", "bf16", "none"])
     ap.add_argument("--m", type=int, default=316, help="grid side (n = m*m)")
     ap.add_argument("--tile", type=int, default=512)
     ap.add_argument("--band", type=int, default=2)
@@ -74,18 +84,35 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (pos - lo)
 
 
-def time_path(mp, ctx, locs, z, theta, tile, band, steps, warmup):
+def time_path(mp, ctx, locs, z, theta, tile, band, steps, warmup, band32=-1, lowp=None):
     """warmup + timed steps of the one-shot evaluation; returns wall time and per-step results."""
     import torch
     for _ in range(warmup):
-        ctx.loglik(locs, z, theta, tile, band)
+        ctx.loglik(locs, z, theta, tile, band, band32=band32, lowp=lowp)
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = [ctx.loglik(locs, z, theta, tile, band, timing=True) for _ in range(steps)]
+    results = [ctx.loglik(locs, z, theta, tile, band, timing=True, band32=band32, lowp=lowp)
+               for _ in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, results, ctx.kernel_stats()
+
+
+def leg_summary(wall, res, steps, n, ll_ref=None):
+    chol_flops = n ** 3 / 3.0
+    out = {
+        "evals_per_s": steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "cholesky_tflops": chol_flops / statistics.median([r["t_factor"] for r in res]) / 1e12,
+        "p50_s": percentile([r["t_total"] for r in res], 0.5),
+        "p99_s": percentile([r["t_total"] for r in res], 0.99),
+        "loglik": res[-1]["loglik"],
+        "logdet": res[-1]["logdet"],
+    }
+    if ll_ref is not None:
+        out["dloglik_rel_vs_fp64"] = abs(res[-1]["loglik"] - ll_ref) / max(abs(ll_ref), n)
+    return out
 
 
 def cpu_baseline(m_sample, n_full, theta):
@@ -143,25 +170,35 @@ def main():
     del gen
     torch.cuda.synchronize()
 
-    print("[bench] mixed path", file=sys.stderr, flush=True)
+    lowp = None if args.lowp == "none" else args.lowp
+    band32 = args.band32 if lowp else -1
+    label = (f"three-tier b={args.band} c={band32} {lowp}" if lowp else f"two-tier b={args.band}")
+    print(f"[bench] {label} path", file=sys.stderr, flush=True)
     wall, res, stats = time_path(mp, ctx, locs, z, theta, args.tile, args.band, args.steps,
-                                 args.warmup)
-    print(f"[bench] mixed: {wall / args.steps:.3f} s/step", file=sys.stderr, flush=True)
+                                 args.warmup, band32, lowp)
+    print(f"[bench] {label}: {wall / args.steps:.3f} s/step", file=sys.stderr, flush=True)
+    legs = {}
+    if lowp and args.two_tier_steps > 0:
+        print("[bench] two-tier path", file=sys.stderr, flush=True)
+        w2, r2, _ = time_path(mp, ctx, locs, z, theta, args.tile, args.band, args.two_tier_steps, 1)
+        print(f"[bench] two-tier: {w2 / args.two_tier_steps:.3f} s/step", file=sys.stderr, flush=True)
+        legs["two_tier"] = (w2, r2, args.two_tier_steps)
     if args.fp64_steps > 0:
         print("[bench] fp64 path", file=sys.stderr, flush=True)
-        wall64, res64, _ = time_path(mp, ctx, locs, z, theta, args.tile, -1, args.fp64_steps, 1)
-        print(f"[bench] fp64: {wall64 / args.fp64_steps:.3f} s/step", file=sys.stderr, flush=True)
+        w64, r64, _ = time_path(mp, ctx, locs, z, theta, args.tile, -1, args.fp64_steps, 1)
+        print(f"[bench] fp64: {w64 / args.fp64_steps:.3f} s/step", file=sys.stderr, flush=True)
+        legs["fp64"] = (w64, r64, args.fp64_steps)
     ctx.close()
 
-    chol_flops = n ** 3 / 3.0
-    totals = [r["t_total"] for r in res]
-    factor = [r["t_factor"] for r in res]
-    value = args.steps / wall
-    dom = next(s for s in stats if s["name"] == "update_fp32") if args.band >= 0 else \
-        next(s for s in stats if s["name"] == "update_fp64")
+    ll64 = legs["fp64"][1][-1]["loglik"] if "fp64" in legs else None
+    main_leg = leg_summary(wall, res, args.steps, n, ll64)
+    value = main_leg["evals_per_s"]
+    # dominant kernel: the update class with the largest share of kernel time
+    updates = [s for s in stats if s["name"] in PEAKS and s["launches"]]
+    dom = max(updates, key=lambda s: s["seconds"])
     achieved = dom["flops"] / dom["seconds"] / 1e12
-    peak = PEAK_FP32_MATRIX if args.band >= 0 else PEAK_FP64_MATRIX
-    ll = res[-1]["loglik"]
+    peak = PEAKS[dom["name"]]
+    dtype = "f64+f32+" + lowp.replace("fp", "f") if lowp else "f64+f32"
     out = {
         "metric": METRIC,
         "value": value,
@@ -169,19 +206,20 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"matern-n{n}-nb{args.tile}-band{args.band}", "n": n,
-                   "grid": f"{m}x{m} jittered", "theta": list(theta), "tile": args.tile,
-                   "band64": args.band, "band32": -1},
-        "cholesky_tflops": chol_flops / statistics.median(factor) / 1e12,
-        "p50_s": percentile(totals, 0.5),
-        "p99_s": percentile(totals, 0.99),
-        "loglik": ll,
+        "config": {"workload": f"matern-n{n}-nb{args.tile}-band{args.band}"
+                               + (f"-band32_{band32}-{lowp}" if lowp else ""),
+                   "n": n, "grid": f"{m}x{m} jittered", "theta": list(theta), "tile": args.tile,
+                   "band64": args.band, "band32": band32, "lowp": lowp},
+        "cholesky_tflops": main_leg["cholesky_tflops"],
+        "p50_s": main_leg["p50_s"],
+        "p99_s": main_leg["p99_s"],
+        "loglik": main_leg["loglik"],
         "roofline": {
             "kernel": dom["name"],
             "bound": "mfma",
@@ -189,7 +227,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic(n, args.tile, args.band) if args.band >= 0 else None,
+            "traffic": (measured_traffic(n, args.tile, args.band)
+                        if dom["name"] == "update_fp32" and not lowp else None),
             "avg_launch_ms": 1e3 * dom["seconds"] / dom["launches"],
             "launches": dom["launches"],
         },
@@ -197,19 +236,11 @@ def main():
                                 "tflops": (s["flops"] / s["seconds"] / 1e12) if s["seconds"] else None}
                     for s in stats if s["launches"]},
     }
-    if args.fp64_steps > 0:
-        totals64 = [r["t_total"] for r in res64]
-        factor64 = [r["t_factor"] for r in res64]
-        ll64 = res64[-1]["loglik"]
-        out["fp64"] = {
-            "evals_per_s": args.fp64_steps / wall64,
-            "cholesky_tflops": chol_flops / statistics.median(factor64) / 1e12,
-            "p50_s": percentile(totals64, 0.5),
-            "p99_s": percentile(totals64, 0.99),
-        }
-        out["speedup_vs_fp64"] = value / (args.fp64_steps / wall64)
-        out["loglik_fp64"] = ll64
-        out["dloglik_rel_vs_fp64"] = abs(ll - ll64) / max(abs(ll64), n)
+    if ll64 is not None:
+        out["dloglik_rel_vs_fp64"] = main_leg["dloglik_rel_vs_fp64"]
+    for name, (w, r, st) in legs.items():
+        out[name] = leg_summary(w, r, st, n, ll64 if name != "fp64" else None)
+        out["speedup_vs_" + name] = value / out[name]["evals_per_s"]
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_m, n, theta)

@@ -14,6 +14,11 @@
  * tile it writes: FP64 inputs of an FP32 operation are rounded to nearest-even, FP32
  * inputs of an FP64 operation are promoted exactly.  Diagonal tiles (and so the
  * log-determinant) are always FP64.  The forward solve accumulates in FP64.
+ * Optional third tier (more precision layers, the paper's future work in Section IX):
+ * with band32 = c >= 0 and lowp = 1 (FP16) or 2 (BF16), tiles with i - j > band64 + c stay
+ * FP32-stored but their trailing updates take 16-bit operands: each finished panel tile
+ * L_ik is scaled by s_i = 2^ceil(log2 max|L_ik|) and rounded to nearest-even once, and
+ * A_ij -= s_i s_j (Q_i Q_j^T) runs on the matrix cores with FP32 accumulation.
  *
  * Conventions for every entry point:
  *  - Return value: an mpgeo_status code; MPGEO_OK (0) on success.
@@ -26,8 +31,9 @@
  *  - Ordering: all calls are ordered on the context's HIP stream and are synchronous at
  *    return (results filled in).  A context is used by one host thread at a time.
  *  - Errors: on a non-OK return the outputs are undefined except mpgeo_result.info.
- *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 != -1, lowp != 0, a
- *    non-finite or non-positive theta component, a null pointer that is not nullable.
+ *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 < -1, lowp outside 0..2,
+ *    band32 >= 0 without a lowp format or lowp without band32 >= 0, a non-finite or
+ *    non-positive theta component, a null pointer that is not nullable.
  *    MPGEO_E_NOT_SPD: a non-positive (or NaN) pivot; info = its 0-based global column in
  *    the (Morton-ordered) matrix.  MPGEO_E_NOMEM: device allocation failed.
  *    MPGEO_E_DEVICE: a HIP runtime error.  MPGEO_E_UNSUPPORTED: a feature not built.
@@ -67,8 +73,9 @@ typedef struct {
 /* Tiling and precision plan.
  *  tile:   tile size nb (1..512); the matrix has p = ceil(n / nb) tile rows.
  *  band64: b >= 0: tile (i, j) is FP64 iff i - j <= b; -1: every tile FP64.
- *  band32: must be -1 (FP32 from band64 + 1 to the edge of the matrix).
- *  lowp:   must be 0 (no third precision tier).
+ *  band32: c >= 0: FP32 operands for band64 < i - j <= band64 + c, 16-bit operands beyond;
+ *          -1: FP32 from band64 + 1 to the edge of the matrix (two tiers).
+ *  lowp:   0 with band32 = -1; 1 (FP16) or 2 (BF16) with band32 >= 0.
  *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING. */
 typedef struct {
     int32_t tile;

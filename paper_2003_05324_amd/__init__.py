@@ -127,12 +127,17 @@ def _ptr(a) -> Optional[int]:
     return a.ctypes.data
 
 
-def make_plan(tile: int, band64: int, flags: int = 0) -> Plan:
-    return Plan(tile=tile, band64=band64, band32=-1, lowp=0, flags=flags)
+LOWP = {None: 0, "fp16": 1, "bf16": 2}
 
 
-def mpgeo_footprint_bytes(n: int, tile: int, band64: int) -> int:
-    return int(LIB.mpgeo_footprint_bytes(n, make_plan(tile, band64)))
+def make_plan(tile: int, band64: int, flags: int = 0, band32: int = -1, lowp=None) -> Plan:
+    """Plan: FP64 within band64 tiles of the diagonal, FP32 beyond; with band32 >= 0 and
+    lowp in {"fp16", "bf16"}, 16-bit operands for tiles farther than band64 + band32."""
+    return Plan(tile=tile, band64=band64, band32=band32, lowp=LOWP[lowp], flags=flags)
+
+
+def mpgeo_footprint_bytes(n: int, tile: int, band64: int, band32: int = -1, lowp=None) -> int:
+    return int(LIB.mpgeo_footprint_bytes(n, make_plan(tile, band64, 0, band32, lowp)))
 
 
 class Context:
@@ -160,7 +165,7 @@ class Context:
             pass
 
     def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
-               morton: bool = True, timing: bool = False) -> dict:
+               morton: bool = True, timing: bool = False, band32: int = -1, lowp=None) -> dict:
         """One-shot eq. (2): ordering, covariance tiles, factor, solve, reduction."""
         dev = isinstance(locs, torch.Tensor)
         if not dev:
@@ -169,18 +174,19 @@ class Context:
                 (MPGEO_TIMING if timing else 0)
         res = Result()
         st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
-                              make_plan(tile, band64, flags), ctypes.byref(res))
+                              make_plan(tile, band64, flags, band32, lowp), ctypes.byref(res))
         _check(st, "mpgeo_loglik", res.info)
         return res.as_dict()
 
-    def factor_dense(self, a: np.ndarray, z, tile: int, band64: int) -> dict:
+    def factor_dense(self, a: np.ndarray, z, tile: int, band64: int, band32: int = -1,
+                     lowp=None) -> dict:
         """Algorithm 1 on a given symmetric positive-definite matrix (lower triangle read)."""
         a = np.asfortranarray(np.asarray(a, dtype=np.float64))
         n = a.shape[0]
         zz = None if z is None else _host_f64(z)
         res = Result()
         st = LIB.mpgeo_factor_dense(self.handle, n, a.ctypes.data, n, _ptr(zz),
-                                    make_plan(tile, band64), ctypes.byref(res))
+                                    make_plan(tile, band64, 0, band32, lowp), ctypes.byref(res))
         _check(st, "mpgeo_factor_dense", res.info)
         return res.as_dict()
 
@@ -224,10 +230,12 @@ class Dataset:
         except Exception:
             pass
 
-    def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False) -> dict:
+    def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False,
+               band32: int = -1, lowp=None) -> dict:
         res = Result()
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
-                                      make_plan(tile, band64, MPGEO_TIMING if timing else 0),
+                                      make_plan(tile, band64, MPGEO_TIMING if timing else 0,
+                                                band32, lowp),
                                       ctypes.byref(res))
         _check(st, "mpgeo_dataset_loglik", res.info)
         return res.as_dict()
@@ -290,13 +298,13 @@ class Dataset:
         return out
 
     def mle(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
-            ftol: float = 0.0, max_evals: int = 1000) -> dict:
+            ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None) -> dict:
         """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2))."""
         th = Theta()
         ll = ctypes.c_double()
         ev = ctypes.c_int32()
         it = ctypes.c_int32()
-        _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), make_plan(tile, band64), xtol, ftol,
+        _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), make_plan(tile, band64, 0, band32, lowp), xtol, ftol,
                                      max_evals, ctypes.byref(th), ctypes.byref(ll), ctypes.byref(ev),
                                      ctypes.byref(it)), "mpgeo_dataset_mle")
         return {"theta": (th.sigma2, th.beta, th.nu), "loglik": ll.value, "evals": ev.value,

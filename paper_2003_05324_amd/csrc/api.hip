@@ -72,29 +72,44 @@ struct DevBuf {
 struct Layout {
     int64_t n = 0;
     int nb = 0, nbp = 0, p = 0, band = -2;
+    int edge = 0;                             // low tier (16-bit operands) iff i - j > edge
+    int lowp = 0;                             // 0: none, 1: FP16, 2: BF16
     std::vector<int64_t> off;
-    std::vector<TileIJ> all, list64, list32;
-    std::vector<int64_t> pre64, pre32;        // entries of each list with j > k (step k)
-    std::vector<double> flops64, flops32;     // algorithmic flops of each step's update
-    std::vector<double> colf64, colf32;       // per tile column j (without the K = rows(k) factor)
+    std::vector<TileIJ> all, list64, list32, list16;
+    std::vector<int64_t> pre64, pre32, pre16; // entries of each list with j > k (step k)
+    std::vector<double> flops64, flops32, flops16;   // algorithmic flops of each step's update
+    std::vector<double> colf64, colf32, colf16;      // per tile column j (without K = rows(k))
     std::vector<double> trsm64_flops, trsm32_flops;
-    int64_t n64 = 0, n32 = 0;                 // tiles per tier
+    int64_t n64 = 0, n32 = 0;                 // tiles per storage precision (FP32 holds tier 16)
 
-    bool same(int64_t n_, int nb_, int band_) const { return n == n_ && nb == nb_ && band == band_; }
+    bool same(int64_t n_, int nb_, int band_, int edge_, int lowp_) const {
+        return n == n_ && nb == nb_ && band == band_ && edge == edge_ && lowp == lowp_;
+    }
+    // tier of tile (i, j): 64, 32 or 16
+    int tier(int i, int j) const { return (i - j <= band) ? 64 : (i - j <= edge ? 32 : 16); }
 
     int64_t rows(int i) const { return std::min<int64_t>(nb, n - (int64_t)i * nb); }
 
-    void build(int64_t n_, int nb_, int band64) {
+    static int effective_band(int64_t p_, int band64) { return (band64 < 0 || band64 > p_) ? (int)p_ : band64; }
+    static int effective_edge(int64_t p_, int band64, int band32) {
+        const int b = effective_band(p_, band64);
+        return (band32 < 0 || (int64_t)b + band32 > p_) ? (int)p_ : b + band32;
+    }
+
+    void build(int64_t n_, int nb_, int band64, int band32 = -1, int lowp_ = 0) {
         n = n_;
         nb = nb_;
         nbp = (nb + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
         p = (int)((n + nb - 1) / nb);
-        band = (band64 < 0 || band64 > p) ? p : band64;
+        band = effective_band(p, band64);
+        edge = effective_edge(p, band64, band32);
+        lowp = (edge < p) ? lowp_ : 0;
         const int64_t nt = (int64_t)p * (p + 1) / 2;
         off.assign(nt, 0);
         all.clear();
         list64.clear();
         list32.clear();
+        list16.clear();
         n64 = n32 = 0;
         const int64_t tile_elems = (int64_t)nbp * nbp;
         for (int i = 0; i < p; ++i)
@@ -107,41 +122,44 @@ struct Layout {
         // exactly the trailing work of step k
         for (int j = p - 1; j >= 1; --j)
             for (int i = j; i < p; ++i) {
-                if (i - j <= band) list64.push_back({i, j});
-                else list32.push_back({i, j});
+                const int t = tier(i, j);
+                (t == 64 ? list64 : t == 32 ? list32 : list16).push_back({i, j});
             }
         pre64.assign(p, 0);
         pre32.assign(p, 0);
+        pre16.assign(p, 0);
         flops64.assign(p, 0.0);
         flops32.assign(p, 0.0);
+        flops16.assign(p, 0.0);
         trsm64_flops.assign(p, 0.0);
         trsm32_flops.assign(p, 0.0);
-        std::vector<double> col64(p, 0.0), col32(p, 0.0);
-        std::vector<int64_t> cnt64(p, 0), cnt32(p, 0);
+        std::vector<double> col64(p, 0.0), col32(p, 0.0), col16(p, 0.0);
+        std::vector<int64_t> cnt64(p, 0), cnt32(p, 0), cnt16(p, 0);
         for (int j = 1; j < p; ++j)
             for (int i = j; i < p; ++i) {
                 const double f = (i == j) ? (double)rows(j) * (rows(j) + 1) : 2.0 * rows(i) * rows(j);
-                if (i - j <= band) {
-                    col64[j] += f;
-                    cnt64[j]++;
-                } else {
-                    col32[j] += f;
-                    cnt32[j]++;
-                }
+                const int t = tier(i, j);
+                (t == 64 ? col64 : t == 32 ? col32 : col16)[j] += f;
+                (t == 64 ? cnt64 : t == 32 ? cnt32 : cnt16)[j]++;
             }
         colf64 = col64;
         colf32 = col32;
-        double s64 = 0, s32 = 0;
-        int64_t c64 = 0, c32 = 0;
+        colf16 = col16;
+        double s64 = 0, s32 = 0, s16 = 0;
+        int64_t c64 = 0, c32 = 0, c16 = 0;
         for (int k = p - 1; k >= 0; --k) {
             pre64[k] = c64;
             pre32[k] = c32;
+            pre16[k] = c16;
             flops64[k] = s64 * rows(k);
             flops32[k] = s32 * rows(k);
+            flops16[k] = s16 * rows(k);
             s64 += col64[k];
             s32 += col32[k];
+            s16 += col16[k];
             c64 += cnt64[k];
             c32 += cnt32[k];
+            c16 += cnt16[k];
         }
         for (int k = 0; k < p; ++k)
             for (int i = k + 1; i < p; ++i) {
@@ -154,11 +172,11 @@ struct Layout {
 
 enum StatClass {
     kStatCovgen, kStatOrder, kStatPotrf, kStatTrsm64, kStatTrsm32, kStatPanel, kStatUpdate64,
-    kStatUpdate32, kStatFinal, kStatCount
+    kStatUpdate32, kStatFinal, kStatQuant, kStatUpdate16, kStatCount
 };
 const char *kStatNames[kStatCount] = {"covgen", "morton_order", "potrf_tile", "trsm_fp64",
                                       "trsm_fp32", "panel_solve", "update_fp64", "update_fp32",
-                                      "finalize"};
+                                      "finalize", "quantize", "update_lowp"};
 
 }  // namespace
 
@@ -256,8 +274,8 @@ struct mpgeo_dataset {
     // ordered inputs
     DevBuf locs, z, perm, keys, locs_in, z_in;
     // tiles and work buffers
-    DevBuf pool64, pool32, off, all, list64, list32;
-    DevBuf p64, p32, linv, linv32;
+    DevBuf pool64, pool32, off, all, list64, list32, list16;
+    DevBuf p64, p32, linv, linv32, q16, qscale;
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
     bool has_factor = false;
@@ -274,8 +292,9 @@ int check_theta(const mpgeo_theta &t) {
 
 int check_plan(const mpgeo_plan &pl) {
     if (pl.tile < 1 || pl.tile > kMaxTile) return MPGEO_E_ARG;
-    if (pl.band64 < -1) return MPGEO_E_ARG;
-    if (pl.band32 != -1 || pl.lowp != 0) return MPGEO_E_ARG;
+    if (pl.band64 < -1 || pl.band32 < -1) return MPGEO_E_ARG;
+    if (pl.lowp < 0 || pl.lowp > 2) return MPGEO_E_ARG;
+    if ((pl.band32 >= 0) != (pl.lowp != 0)) return MPGEO_E_ARG;   // a third tier needs its format
     return MPGEO_OK;
 }
 
@@ -296,11 +315,12 @@ TileMap tile_map(const mpgeo_dataset *ds) {
 // Allocate tiles and tables for (n, plan) and upload the tables.
 int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     Layout &L = ds->layout;
-    const int band = pl.band64;
     const int64_t p_new = (ds->n + pl.tile - 1) / pl.tile;
-    const int band_eff = (band < 0 || band > p_new) ? (int)p_new : band;
-    if (L.same(ds->n, pl.tile, band_eff) && ds->off.ptr) return MPGEO_OK;
-    L.build(ds->n, pl.tile, band);
+    const int band_eff = Layout::effective_band(p_new, pl.band64);
+    const int edge_eff = Layout::effective_edge(p_new, pl.band64, pl.band32);
+    const int lowp_eff = (edge_eff < p_new) ? pl.lowp : 0;
+    if (L.same(ds->n, pl.tile, band_eff, edge_eff, lowp_eff) && ds->off.ptr) return MPGEO_OK;
+    L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp);
     ds->has_factor = false;
     const size_t te = (size_t)L.nbp * L.nbp;
     MPGEO_TRY(ds->pool64.ensure(std::max<size_t>(1, (size_t)L.n64 * te * sizeof(double))));
@@ -309,6 +329,11 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     MPGEO_TRY(ds->all.ensure(std::max<size_t>(1, L.all.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list64.ensure(std::max<size_t>(1, L.list64.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list32.ensure(std::max<size_t>(1, L.list32.size()) * sizeof(TileIJ)));
+    MPGEO_TRY(ds->list16.ensure(std::max<size_t>(1, L.list16.size()) * sizeof(TileIJ)));
+    if (L.lowp) {
+        MPGEO_TRY(ds->q16.ensure(2 * (size_t)L.p * te * 2));                 // two steps in flight
+        MPGEO_TRY(ds->qscale.ensure(2 * (size_t)L.p * sizeof(float)));
+    }
     MPGEO_TRY(ds->p64.ensure(2 * (size_t)L.p * te * sizeof(double)));   // two steps in flight
     MPGEO_TRY(ds->p32.ensure(2 * (size_t)L.p * te * sizeof(float)));
     MPGEO_TRY(ds->linv.ensure((size_t)L.p * te * sizeof(double)));
@@ -329,6 +354,9 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
                                  hipMemcpyHostToDevice, s));
     if (!L.list32.empty())
         MPGEO_HIP(hipMemcpyAsync(ds->list32.ptr, L.list32.data(), L.list32.size() * sizeof(TileIJ),
+                                 hipMemcpyHostToDevice, s));
+    if (!L.list16.empty())
+        MPGEO_HIP(hipMemcpyAsync(ds->list16.ptr, L.list16.data(), L.list16.size() * sizeof(TileIJ),
                                  hipMemcpyHostToDevice, s));
     MPGEO_HIP(hipStreamSynchronize(s));   // host vectors may change with the next build
     return MPGEO_OK;
@@ -430,6 +458,9 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     const double nbd = L.nb;
     const TileIJ *l64 = ds->list64.as<TileIJ>();
     const TileIJ *l32 = ds->list32.as<TileIJ>();
+    const TileIJ *l16 = ds->list16.as<TileIJ>();
+    auto qpanel = [&](int k) { return static_cast<void *>(ds->q16.as<char>() + (size_t)(k & 1) * p * te * 2); };
+    auto qscale = [&](int k) { return ds->qscale.as<float>() + (size_t)(k & 1) * p; };
 
     auto panel64 = [&](int k) { return ds->p64.as<double>() + (size_t)(k & 1) * p * te; };
     auto panel32 = [&](int k) { return ds->p32.as<float>() + (size_t)(k & 1) * p * te; };
@@ -468,10 +499,18 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         ctx->timed_on(s1, kStatPanel, 2.0 * (p - 1 - k) * nbd * nbd,
                       (double)(p - 1 - k) * nbd * nbd * 16.0,
                       [&] { launch_panel_solve(map, k, p64, pa.y, r, s1); });
+        if (L.lowp && L.pre16[k] > 0)   // this step updates low-tier tiles: 16-bit panel copy
+            ctx->timed_on(s1, kStatQuant, 0.0, (double)(p - 1 - k) * nbd * nbd * 10.0, [&] {
+                launch_quantize(map, k + 1, p - 1 - k, p32, qpanel(k), qscale(k), L.lowp, s1);
+            });
     };
-    // update of list entries [b, e) of both tiers with panel k on stream st
-    auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, double f64,
-                            double f32, hipStream_t st) {
+    // update of list entries [b, e) of each tier with panel k on stream st
+    auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, int64_t b16,
+                            int64_t e16, double f64, double f32, double f16, hipStream_t st) {
+        if (e16 > b16)
+            ctx->timed_on(st, kStatUpdate16, f16, (double)(e16 - b16) * nbd * nbd * 4.0 * 2.0, [&] {
+                launch_update_lowp(map, l16 + b16, e16 - b16, qpanel(k), qscale(k), L.lowp, st);
+            });
         if (e64 > b64)
             ctx->timed_on(st, kStatUpdate64, f64, (double)(e64 - b64) * nbd * nbd * 8.0 * 2.0, [&] {
                 launch_update(map, l64 + b64, e64 - b64, true, panel64(k), panel32(k), st);
@@ -489,16 +528,18 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         // bulk: columns >= k+2 (list prefix [0, pre[k+1]))
         MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[k], 0));
         if (k + 1 < p) {
-            const double c64 = L.colf64[k + 1] * rk, c32 = L.colf32[k + 1] * rk;
-            update_range(k, 0, L.pre64[k + 1], 0, L.pre32[k + 1], L.flops64[k] - c64,
-                         L.flops32[k] - c32, s0);
+            const double c64 = L.colf64[k + 1] * rk, c32 = L.colf32[k + 1] * rk,
+                         c16 = L.colf16[k + 1] * rk;
+            update_range(k, 0, L.pre64[k + 1], 0, L.pre32[k + 1], 0, L.pre16[k + 1],
+                         L.flops64[k] - c64, L.flops32[k] - c32, L.flops16[k] - c16, s0);
         }
         MPGEO_HIP(hipEventRecord(ev_bulk[k], s0));
         if (k + 1 < p) {
             // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
-            update_range(k, L.pre64[k + 1], L.pre64[k], L.pre32[k + 1], L.pre32[k],
-                         L.colf64[k + 1] * rk, L.colf32[k + 1] * rk, s1);
+            update_range(k, L.pre64[k + 1], L.pre64[k], L.pre32[k + 1], L.pre32[k], L.pre16[k + 1],
+                         L.pre16[k], L.colf64[k + 1] * rk, L.colf32[k + 1] * rk,
+                         L.colf16[k + 1] * rk, s1);
             factor_step(k + 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
@@ -606,7 +647,7 @@ const char *mpgeo_status_string(int status) {
 size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
     if (n < 1 || check_plan(plan) != MPGEO_OK) return 0;
     Layout L;
-    L.build(n, plan.tile, plan.band64);
+    L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp);
     const size_t te = (size_t)L.nbp * L.nbp;
     return (size_t)L.n64 * te * sizeof(double) + (size_t)L.n32 * te * sizeof(float);
 }
@@ -700,6 +741,7 @@ int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
     (void)hipStreamSynchronize(ds->ctx->stream);
     for (DevBuf *b : {&ds->locs, &ds->z, &ds->perm, &ds->keys, &ds->locs_in, &ds->z_in,
                       &ds->pool64, &ds->pool32, &ds->off, &ds->all, &ds->list64, &ds->list32,
+                      &ds->list16, &ds->q16, &ds->qscale,
                       &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
                       &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c})
         b->release();
@@ -1076,7 +1118,8 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
         ctx->timing = false;
     }
     (void)hipStreamSynchronize(s);
-    for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.p64,
+    for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.list16,
+                      &ds.q16, &ds.qscale, &ds.p64,
                       &ds.p32, &ds.linv, &ds.linv32, &ds.r, &ds.y, &ds.parts, &ds.info, &ds.result,
                       &ds.tmp_a, &ds.z})
         b->release();

@@ -109,6 +109,14 @@ void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64,
 void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool fp64,
                    const double *p64, const float *p32, hipStream_t stream);
 
+// Third tier: quantise panel tiles i in [first, first + count) of the FP32 staging panel to
+// 16-bit (lowp 1: FP16, 2: BF16) with a power-of-two scale per tile, row-major.
+void launch_quantize(const TileMap &map, int first, int count, const float *p32, void *q,
+                     float *scale, int lowp, hipStream_t stream);
+// Third tier: A_ij -= s_i s_j Q_i Q_j^T over list[0, count) (FP32-stored tiles).
+void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
+                        const float *scale, int lowp, hipStream_t stream);
+
 // Panel step of the fused forward solve: r_i -= P64_i y_k for i in (k, p), and copy the
 // finished panel tile (i, k) from staging into its storage precision.
 void launch_panel_solve(const TileMap &map, int k, const double *p64, const double *yk,

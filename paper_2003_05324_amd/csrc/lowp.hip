@@ -1,0 +1,259 @@
+// Third precision tier: trailing updates of the farthest tiles with FP16 or BF16 operands on
+// the matrix cores (the paper's future work, Section IX: more than two precision layers).
+//
+// Tiles with i - j > band64 + band32 keep FP32 storage and FP32 accumulation; only the
+// operands of their update A_ij -= L_ik L_jk^T drop to a 16-bit format.  After the panel of
+// step k is solved, every panel tile L_ik is quantised once:
+//   s_i = 2^ceil(log2 max|L_ik|)   (a power of two, so the scaling is exact),
+//   Q_i = round_to_nearest_even(L_ik / s_i)   in FP16 or BF16,
+// stored row-major (K contiguous) for 16-byte operand loads.  The update is then
+//   A_ij -= (s_i s_j) * (Q_i Q_j^T)   with v_mfma_f32_16x16x32_{f16,bf16} accumulating in FP32.
+#include "common.h"
+
+namespace mpgeo {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+template <typename T> struct Lowp;
+template <> struct Lowp<_Float16> {
+    using vec8 = h8;
+    __device__ static f32x4 mac(vec8 a, vec8 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Lowp<__bf16> {
+    using vec8 = b8;
+    __device__ static f32x4 mac(vec8 a, vec8 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int kXcds = 8;
+constexpr int kQThreads = 256;
+constexpr int kQBlk = 64;   // transpose block
+
+// One workgroup per panel tile i in (k, p): max-abs, power-of-two scale, 16-bit transposed copy.
+template <typename T>
+__global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, T *q, float *scale,
+                                                             int first, int nbp) {
+    __shared__ float red[kQThreads / 64];
+    __shared__ float blk[kQBlk][kQBlk + 1];
+    const int i = first + blockIdx.x;
+    const float *src = p32 + (int64_t)i * nbp * nbp;
+    T *dst = q + (int64_t)i * nbp * nbp;
+    float m = 0.0f;
+    for (int64_t e = threadIdx.x; e < (int64_t)nbp * nbp; e += kQThreads) m = fmaxf(m, fabsf(src[e]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    float mx = red[0];
+    for (int w = 1; w < kQThreads / 64; ++w) mx = fmaxf(mx, red[w]);
+    // s = 2^e with 2^(e-1) < mx <= 2^e (s = 1 for an all-zero tile)
+    int ex = 0;
+    if (mx > 0.0f) {
+        const float fr = frexpf(mx, &ex);   // mx = fr * 2^ex, fr in [0.5, 1)
+        if (fr == 0.5f) ex -= 1;            // an exact power of two maps to 1
+    }
+    const float inv = ldexpf(1.0f, -ex);
+    if (threadIdx.x == 0) scale[i] = ldexpf(1.0f, ex);
+    // transposed copy in 64 x 64 blocks: src column-major (row r, col t) -> dst[r * nbp + t]
+    for (int r0 = 0; r0 < nbp; r0 += kQBlk)
+        for (int t0 = 0; t0 < nbp; t0 += kQBlk) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < kQBlk * kQBlk; e += kQThreads) {
+                const int rr = e % kQBlk, tt = e / kQBlk;
+                const int r = r0 + rr, t = t0 + tt;
+                blk[rr][tt] = (r < nbp && t < nbp) ? src[r + (int64_t)t * nbp] * inv : 0.0f;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < kQBlk * kQBlk; e += kQThreads) {
+                const int tt = e % kQBlk, rr = e / kQBlk;
+                const int r = r0 + rr, t = t0 + tt;
+                if (r < nbp && t < nbp) dst[(int64_t)r * nbp + t] = (T)blk[rr][tt];   // RNE
+            }
+        }
+}
+
+struct LowpArgs {
+    TileMap map;
+    int64_t ntiles;
+    const TileIJ *list;
+    const void *q;        // quantised panel, tile i at i * nbp^2, row-major
+    const float *scale;   // per panel tile
+};
+
+template <int BM_, int BN_, int WM_, int WN_, int KC_> struct LShape {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_;
+    static constexpr int kThreads = 64 * WM * WN;
+};
+
+// C[rows, cols] -= s_i s_j * sum_t Q_i[row][t] Q_j[col][t] on one BM x BN block of a tile.
+template <typename T, typename S>
+__global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
+    using L = Lowp<T>;
+    using vec8 = typename L::vec8;
+    constexpr int BM = S::BM, BN = S::BN, KC = S::KC, NT = S::kThreads;
+    constexpr int NBR = BM / S::WM / 16;
+    constexpr int NBC = BN / S::WN / 16;
+    constexpr int LD = KC + 8;             // padded LDS row (16 bytes) spreads rows over banks
+    constexpr int VPR_ROW = KC / 8;        // 16-byte vectors per row of a chunk
+    constexpr int NVQ = BN * VPR_ROW, NVR = BM * VPR_ROW;
+    constexpr int VPQ = (NVQ + NT - 1) / NT, VPR = (NVR + NT - 1) / NT;
+
+    __shared__ __attribute__((aligned(16))) T ldsq[2][BN * LD];
+    __shared__ __attribute__((aligned(16))) T ldsr[2][BM * LD];
+
+    const int nbp = g.map.nbp;
+    const int rows_per = nbp / BM, cols_per = nbp / BN;
+    const int per_tile = rows_per * cols_per;
+    const int xcd = blockIdx.x % kXcds;
+    const int local = blockIdx.x / kXcds;
+    const int macro = local % per_tile;
+    const int tile = (local / per_tile) * kXcds + xcd;
+    if (tile >= g.ntiles) return;
+    const int row0 = (macro % rows_per) * BM;
+    const int col0 = (macro / rows_per) * BN;
+    const TileIJ tij = g.list[tile];
+    const T *qbase = static_cast<const T *>(g.q);
+    const T *R = qbase + (int64_t)tij.i * nbp * nbp + (int64_t)row0 * nbp;
+    const T *Q = qbase + (int64_t)tij.j * nbp * nbp + (int64_t)col0 * nbp;
+    const float factor = -g.scale[tij.i] * g.scale[tij.j];
+    float *C = g.map.pool32 + g.map.off[tri_index(tij.i, tij.j)];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wrow = (wave % S::WM) * (BM / S::WM);
+    const int wcol = (wave / S::WM) * (BN / S::WN);
+    const int lr = lane & 15, lg = lane >> 4;
+
+    f32x4 acc[NBC][NBR];
+#pragma unroll
+    for (int a = 0; a < NBC; ++a)
+#pragma unroll
+        for (int b = 0; b < NBR; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    vec8 rq[VPQ], rr[VPR];
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VPQ; ++v) {
+            const int idx = v * NT + tid;
+            if (NVQ % NT == 0 || idx < NVQ) {
+                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
+                rq[v] = *reinterpret_cast<const vec8 *>(Q + (int64_t)row * nbp + k0 + cv * 8);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VPR; ++v) {
+            const int idx = v * NT + tid;
+            if (NVR % NT == 0 || idx < NVR) {
+                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
+                rr[v] = *reinterpret_cast<const vec8 *>(R + (int64_t)row * nbp + k0 + cv * 8);
+            }
+        }
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < VPQ; ++v) {
+            const int idx = v * NT + tid;
+            if (NVQ % NT == 0 || idx < NVQ) {
+                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
+                *reinterpret_cast<vec8 *>(&ldsq[buf][row * LD + cv * 8]) = rq[v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VPR; ++v) {
+            const int idx = v * NT + tid;
+            if (NVR % NT == 0 || idx < NVR) {
+                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
+                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + cv * 8]) = rr[v];
+            }
+        }
+    };
+
+    const int nchunks = nbp / KC;
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks) load_chunk((c + 1) * KC);
+#pragma unroll
+        for (int s = 0; s < KC / 32; ++s) {
+            const int k = 32 * s + 8 * lg;     // this lane's 8 consecutive k
+            vec8 qa[NBC], rb[NBR];
+#pragma unroll
+            for (int a = 0; a < NBC; ++a)
+                qa[a] = *reinterpret_cast<const vec8 *>(&ldsq[buf][(wcol + a * 16 + lr) * LD + k]);
+#pragma unroll
+            for (int b = 0; b < NBR; ++b)
+                rb[b] = *reinterpret_cast<const vec8 *>(&ldsr[buf][(wrow + b * 16 + lr) * LD + k]);
+#pragma unroll
+            for (int a = 0; a < NBC; ++a)
+#pragma unroll
+                for (int b = 0; b < NBR; ++b) acc[a][b] = L::mac(qa[a], rb[b], acc[a][b]);
+        }
+        if (c + 1 < nchunks) store_chunk(buf ^ 1);
+        __syncthreads();
+    }
+    // result register q of lane (16 g + r): row lr of the b block, column 4 g + q of the a block
+#pragma unroll
+    for (int a = 0; a < NBC; ++a)
+#pragma unroll
+        for (int b = 0; b < NBR; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = row0 + wrow + b * 16 + lr;
+                const int col = col0 + wcol + a * 16 + 4 * lg + q;
+                float *pc = C + row + (int64_t)col * nbp;
+                *pc = *pc + factor * acc[a][b][q];
+            }
+}
+
+template <typename T, typename S>
+void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
+    LowpArgs ga = g;
+    ga.ntiles = ntiles;
+    const int nbp = g.map.nbp;
+    const int64_t slots = (ntiles + kXcds - 1) / kXcds * kXcds;
+    const int64_t blocks = slots * (nbp / S::BM) * (nbp / S::BN);
+    hipLaunchKernelGGL((lowp_update_kernel<T, S>), dim3((unsigned)blocks), dim3(S::kThreads), 0, stream,
+                       ga);
+}
+
+template <typename T>
+void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
+    const int nbp = g.map.nbp;
+    if (nbp % 128 == 0 && nbp % 64 == 0) launch_lowp_shape<T, LShape<128, 128, 2, 2, 64>>(g, ntiles, stream);
+    else if (nbp % 64 == 0) launch_lowp_shape<T, LShape<64, 64, 2, 2, 64>>(g, ntiles, stream);
+    else launch_lowp_shape<T, LShape<32, 32, 2, 2, 32>>(g, ntiles, stream);
+}
+
+}  // namespace
+
+void launch_quantize(const TileMap &map, int first, int count, const float *p32, void *q, float *scale,
+                     int lowp, hipStream_t stream) {
+    if (count <= 0) return;
+    if (lowp == 1)
+        hipLaunchKernelGGL(quantize_kernel<_Float16>, dim3((unsigned)count), dim3(kQThreads), 0, stream, p32,
+                           static_cast<_Float16 *>(q), scale, first, map.nbp);
+    else
+        hipLaunchKernelGGL(quantize_kernel<__bf16>, dim3((unsigned)count), dim3(kQThreads), 0, stream, p32,
+                           static_cast<__bf16 *>(q), scale, first, map.nbp);
+}
+
+void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
+                        const float *scale, int lowp, hipStream_t stream) {
+    if (count <= 0) return;
+    LowpArgs g{};
+    g.map = map;
+    g.list = list;
+    g.q = q;
+    g.scale = scale;
+    if (lowp == 1) launch_lowp<_Float16>(g, count, stream);
+    else launch_lowp<__bf16>(g, count, stream);
+}
+
+}  // namespace mpgeo

@@ -123,3 +123,21 @@ def test_band_path_against_fp64_path(lib, full):
     ds.close()
     assert abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), n) <= 1e-5
     assert abs(a["logdet"] - b["logdet"]) / abs(b["logdet"]) <= 1e-6
+
+
+@pytest.mark.parametrize("lowp", ["fp16", "bf16"])
+def test_three_tier_against_fp64_path(lib, full, lowp):
+    # FP64 band 2, FP32 for the next 8 tiles, 16-bit operands beyond (the n ~ 1e5 workload)
+    ctx, locs = full["ctx"], full["locs"]
+    gen = lib.Dataset(ctx, locs, None)
+    z = gen.simulate(THETA, LARGE.eps(), TILE, -1)
+    gen.close()
+    ds = lib.Dataset(ctx, locs, z)
+    n = LARGE.n
+    a = ds.loglik(THETA, TILE, 2, band32=8, lowp=lowp)
+    b = ds.loglik(THETA, TILE, -1)
+    ds.close()
+    err = abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), n)
+    print(f"n={n} three-tier {lowp}: |dl|/max(|l|,n) vs FP64 path = {err:.3e}, "
+          f"dlogdet/|logdet| = {abs(a['logdet'] - b['logdet']) / abs(b['logdet']):.3e}")
+    assert err <= {"fp16": 1e-2, "bf16": 8e-2}[lowp]

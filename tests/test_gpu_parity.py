@@ -302,3 +302,48 @@ def test_mle_matches_oracle(lib, small_ds, band):
     fit = small_ds.mle(start, SMALL.tile, band)
     for got, want in zip(fit["theta"], gold["theta_hat"]):
         assert abs(got - want) / abs(want) <= 1e-3, (fit, gold)
+
+
+# ---- third precision tier (16-bit operands for the farthest tiles) -------------------------
+# Tolerance (derived): a 16-bit operand carries a relative rounding error u (2^-11 for FP16,
+# 2^-8 for BF16); each far-tile update A_ij -= L_ik L_jk^T then errs by at most 2u of the
+# magnitude sum |L_ik||L_jk| <= sigma2, and those perturbations enter l through
+# tr(Sigma^-1 dSigma) and the quadratic form.  For the n = 1,600 workload this is bounded here
+# by |dl| / max(|l|, n) <= 20u: 1e-2 (FP16) and 8e-2 (BF16) — generous on purpose; the test
+# prints the measured error, which is what the benchmark reports.
+LOWP_TOL = {"fp16": 20 * 2.0 ** -11, "bf16": 20 * 2.0 ** -8}
+
+
+@pytest.mark.parametrize("lowp", ["fp16", "bf16"])
+@pytest.mark.parametrize("band32", [0, 2, 5])
+def test_three_tier_matches_oracle(small_ds, lowp, band32):
+    theta = SMALL.theta
+    want = small_oracle(tuple(theta))
+    got = small_ds.loglik(theta, SMALL.tile, 2, band32=band32, lowp=lowp)
+    err = abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n)
+    print(f"three-tier {lowp} band64=2 band32={band32}: |dl|/max(|l|,n) = {err:.3e}")
+    assert err <= LOWP_TOL[lowp]
+    # the two-tier path is the c -> infinity limit: more FP32 tiles never hurts much
+    two = small_ds.loglik(theta, SMALL.tile, 2)
+    err2 = abs(two["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n)
+    assert err2 <= max(err, 1e-6)
+
+
+@pytest.mark.parametrize("lowp", ["fp16", "bf16"])
+def test_three_tier_block_banded_is_exact(lib, ctx, lowp):
+    # far tiles exactly zero: their 16-bit copies are exact zeros, so every tier gives the
+    # FP64 result bit for bit
+    n, tile, width = 256, 32, 1
+    a = _block_banded_spd(n, tile, width, 15)
+    z = normals(n, 16)
+    ref = ctx.factor_dense(a, z, tile, -1)
+    got = ctx.factor_dense(a, z, tile, width, band32=0, lowp=lowp)
+    assert got["loglik"] == ref["loglik"]
+    assert got["logdet"] == ref["logdet"]
+
+
+def test_three_tier_plan_validation(lib, small_ds):
+    for band32, lowp in [(2, None), (-1, "fp16")]:
+        with pytest.raises(lib.MpgeoError) as e:
+            small_ds.loglik(SMALL.theta, SMALL.tile, 2, band32=band32, lowp=lowp)
+        assert e.value.status == lib.MPGEO_E_ARG
