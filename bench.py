@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--band", type=int, default=2)
     ap.add_argument("--cpu-sample-m", type=int, default=110)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--heldout", type=int, default=2000, help="kriging sites (0: skip)")
     return ap.parse_args()
 
 
@@ -150,8 +151,10 @@ def main():
         sys.exit(2)
     import torch
 
+    import numpy as np
+
     import paper_2003_05324_amd as mp
-    from synthetic import jittered_grid, normals
+    from synthetic import jittered_grid, normals, uniform_sites
 
     m = args.m
     n = m * m
@@ -162,12 +165,20 @@ def main():
     locs = torch.from_numpy(locs_h).to(dev)
     eps = torch.from_numpy(eps_h).to(dev)
     ctx = mp.Context(0)
-    print(f"[bench] n={n} tile={args.tile} band={args.band}: drawing z from the FP64 field",
-          file=sys.stderr, flush=True)
-    gen = mp.Dataset(ctx, locs, None)
-    z = gen.simulate(theta, eps, args.tile, -1)
+    # the field is drawn jointly at the n observed and the held-out kriging sites
+    m_h = args.heldout
+    sites_h = uniform_sites(m_h, 303) if m_h else np.zeros((0, 2))
+    all_locs = torch.from_numpy(np.concatenate([locs_h, sites_h])).to(dev)
+    all_eps = torch.from_numpy(np.concatenate([eps_h, normals(m_h, 304)])).to(dev)
+    print(f"[bench] n={n} tile={args.tile} band={args.band}: drawing z from the FP64 field "
+          f"(+{m_h} held-out sites)", file=sys.stderr, flush=True)
+    gen = mp.Dataset(ctx, all_locs, None)
+    z_all = gen.simulate(theta, all_eps, args.tile, -1)
     gen.close()
     del gen
+    z = z_all[:n].contiguous()
+    z_heldout = z_all[n:].cpu().numpy()
+    sites = all_locs[n:].contiguous()
     torch.cuda.synchronize()
 
     lowp = None if args.lowp == "none" else args.lowp
@@ -188,6 +199,23 @@ def main():
         w64, r64, _ = time_path(mp, ctx, locs, z, theta, args.tile, -1, args.fp64_steps, 1)
         print(f"[bench] fp64: {w64 / args.fp64_steps:.3f} s/step", file=sys.stderr, flush=True)
         legs["fp64"] = (w64, r64, args.fp64_steps)
+    kriging = None
+    if m_h:
+        # simple-kriging predictions at the held-out sites from the headline plan's factor and
+        # from the FP64 factor (resident dataset, outside the timed region)
+        print("[bench] kriging at held-out sites", file=sys.stderr, flush=True)
+        ds = mp.Dataset(ctx, locs, z)
+        ds.loglik(theta, args.tile, args.band, band32=band32, lowp=lowp)
+        t0 = time.perf_counter()
+        pred = ds.krige(sites).cpu().numpy()
+        t_krige = time.perf_counter() - t0
+        ds.loglik(theta, args.tile, -1)
+        pred64 = ds.krige(sites).cpu().numpy()
+        ds.close()
+        kriging = {"sites": m_h, "seconds": t_krige,
+                   "pmse": float(np.mean((pred - z_heldout) ** 2)),
+                   "pmse_fp64": float(np.mean((pred64 - z_heldout) ** 2)),
+                   "max_abs_dpred_vs_fp64": float(np.max(np.abs(pred - pred64)))}
     ctx.close()
 
     ll64 = legs["fp64"][1][-1]["loglik"] if "fp64" in legs else None
@@ -238,6 +266,8 @@ def main():
     }
     if ll64 is not None:
         out["dloglik_rel_vs_fp64"] = main_leg["dloglik_rel_vs_fp64"]
+    if kriging:
+        out["kriging"] = kriging
     for name, (w, r, st) in legs.items():
         out[name] = leg_summary(w, r, st, n, ll64 if name != "fp64" else None)
         out["speedup_vs_" + name] = value / out[name]["evals_per_s"]

@@ -275,7 +275,7 @@ struct mpgeo_dataset {
     DevBuf locs, z, perm, keys, locs_in, z_in;
     // tiles and work buffers
     DevBuf pool64, pool32, off, all, list64, list32, list16;
-    DevBuf p64, p32, linv, linv32, q16, qscale;
+    DevBuf p64, p32, linv, linv32, q16, qscale, qmax;
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
     bool has_factor = false;
@@ -333,6 +333,7 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     if (L.lowp) {
         MPGEO_TRY(ds->q16.ensure(2 * (size_t)L.p * te * 2));                 // two steps in flight
         MPGEO_TRY(ds->qscale.ensure(2 * (size_t)L.p * sizeof(float)));
+        MPGEO_TRY(ds->qmax.ensure(2 * (size_t)L.p * sizeof(unsigned)));
     }
     MPGEO_TRY(ds->p64.ensure(2 * (size_t)L.p * te * sizeof(double)));   // two steps in flight
     MPGEO_TRY(ds->p32.ensure(2 * (size_t)L.p * te * sizeof(float)));
@@ -461,6 +462,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     const TileIJ *l16 = ds->list16.as<TileIJ>();
     auto qpanel = [&](int k) { return static_cast<void *>(ds->q16.as<char>() + (size_t)(k & 1) * p * te * 2); };
     auto qscale = [&](int k) { return ds->qscale.as<float>() + (size_t)(k & 1) * p; };
+    auto qmax = [&](int k) { return ds->qmax.as<unsigned>() + (size_t)(k & 1) * p; };
 
     auto panel64 = [&](int k) { return ds->p64.as<double>() + (size_t)(k & 1) * p * te; };
     auto panel32 = [&](int k) { return ds->p32.as<float>() + (size_t)(k & 1) * p * te; };
@@ -488,21 +490,25 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         const int n32 = first32 < p ? p - first32 : 0;
         double *p64 = panel64(k);
         float *p32 = panel32(k);
+        // this step updates low-tier tiles: the TRSM also records each panel tile's max |x|
+        const bool quant = L.lowp && L.pre16[k] > 0;
+        unsigned *amax = quant ? qmax(k) : nullptr;
+        if (quant) (void)hipMemsetAsync(amax, 0, (size_t)p * sizeof(unsigned), s1);
         if (n64 > 0)
             ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
-                launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, s1);
+                launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, amax, s1);
             });
         if (n32 > 0)
             ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
-                launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, s1);
+                launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, amax, s1);
+            });
+        if (quant)   // 16-bit panel copy with per-tile power-of-two scales
+            ctx->timed_on(s1, kStatQuant, 0.0, (double)(p - 1 - k) * nbd * nbd * 6.0, [&] {
+                launch_quantize(map, k + 1, p - 1 - k, p32, amax, qpanel(k), qscale(k), L.lowp, s1);
             });
         ctx->timed_on(s1, kStatPanel, 2.0 * (p - 1 - k) * nbd * nbd,
                       (double)(p - 1 - k) * nbd * nbd * 16.0,
                       [&] { launch_panel_solve(map, k, p64, pa.y, r, s1); });
-        if (L.lowp && L.pre16[k] > 0)   // this step updates low-tier tiles: 16-bit panel copy
-            ctx->timed_on(s1, kStatQuant, 0.0, (double)(p - 1 - k) * nbd * nbd * 10.0, [&] {
-                launch_quantize(map, k + 1, p - 1 - k, p32, qpanel(k), qscale(k), L.lowp, s1);
-            });
     };
     // update of list entries [b, e) of each tier with panel k on stream st
     auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, int64_t b16,
@@ -741,7 +747,7 @@ int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
     (void)hipStreamSynchronize(ds->ctx->stream);
     for (DevBuf *b : {&ds->locs, &ds->z, &ds->perm, &ds->keys, &ds->locs_in, &ds->z_in,
                       &ds->pool64, &ds->pool32, &ds->off, &ds->all, &ds->list64, &ds->list32,
-                      &ds->list16, &ds->q16, &ds->qscale,
+                      &ds->list16, &ds->q16, &ds->qscale, &ds->qmax,
                       &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
                       &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c})
         b->release();
@@ -1119,7 +1125,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
     }
     (void)hipStreamSynchronize(s);
     for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.list16,
-                      &ds.q16, &ds.qscale, &ds.p64,
+                      &ds.q16, &ds.qscale, &ds.qmax, &ds.p64,
                       &ds.p32, &ds.linv, &ds.linv32, &ds.r, &ds.y, &ds.parts, &ds.info, &ds.result,
                       &ds.tmp_a, &ds.z})
         b->release();

@@ -99,10 +99,11 @@ struct PotrfArgs {
 void launch_potrf(const PotrfArgs &a, hipStream_t stream);
 
 // Panel TRSM of step k through the explicit inverse: X_i = A_ik L_kk^-T for
-// i in [i_begin, i_begin + count); writes the staging panels P64[i], P32[i].
+// i in [i_begin, i_begin + count); writes the staging panels P64[i], P32[i] and, when absmax
+// is not null, raises absmax[i] (float bits) to max |P32[i]| (for the third tier's scales).
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64,
                  const double *linv, const float *linv32, double *p64, float *p32,
-                 hipStream_t stream);
+                 unsigned *absmax, hipStream_t stream);
 
 // Trailing update of step k: A_ij -= P_i P_j^T over list[0, count) (tiles all of one
 // precision), with P the staging panel of that precision.
@@ -110,9 +111,10 @@ void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool f
                    const double *p64, const float *p32, hipStream_t stream);
 
 // Third tier: quantise panel tiles i in [first, first + count) of the FP32 staging panel to
-// 16-bit (lowp 1: FP16, 2: BF16) with a power-of-two scale per tile, row-major.
-void launch_quantize(const TileMap &map, int first, int count, const float *p32, void *q,
-                     float *scale, int lowp, hipStream_t stream);
+// 16-bit (lowp 1: FP16, 2: BF16), row-major, with the power-of-two scale of each tile
+// derived from absmax[i] (float bits of max |P32[i]|); scale[i] receives it.
+void launch_quantize(const TileMap &map, int first, int count, const float *p32,
+                     const unsigned *absmax, void *q, float *scale, int lowp, hipStream_t stream);
 // Third tier: A_ij -= s_i s_j Q_i Q_j^T over list[0, count) (FP32-stored tiles).
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
                         const float *scale, int lowp, hipStream_t stream);

@@ -34,48 +34,37 @@ template <> struct Lowp<__bf16> {
 
 constexpr int kXcds = 8;
 constexpr int kQThreads = 256;
-constexpr int kQBlk = 64;   // transpose block
 
-// One workgroup per panel tile i in (k, p): max-abs, power-of-two scale, 16-bit transposed copy.
-template <typename T>
-__global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, T *q, float *scale,
-                                                             int first, int nbp) {
-    __shared__ float red[kQThreads / 64];
-    __shared__ float blk[kQBlk][kQBlk + 1];
-    const int i = first + blockIdx.x;
-    const float *src = p32 + (int64_t)i * nbp * nbp;
-    T *dst = q + (int64_t)i * nbp * nbp;
-    float m = 0.0f;
-    for (int64_t e = threadIdx.x; e < (int64_t)nbp * nbp; e += kQThreads) m = fmaxf(m, fabsf(src[e]));
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    float mx = red[0];
-    for (int w = 1; w < kQThreads / 64; ++w) mx = fmaxf(mx, red[w]);
-    // s = 2^e with 2^(e-1) < mx <= 2^e (s = 1 for an all-zero tile)
+// One workgroup per 64 x 64 block of a panel tile: scale by the tile's power of two
+// s = 2^e with 2^(e-1) < max|x| <= 2^e (s = 1 for an all-zero tile), round to the 16-bit
+// format (nearest even) and store transposed (row-major, K contiguous).
+template <typename T, int QB>
+__global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, const unsigned *absmax,
+                                                             T *q, float *scale, int first, int nbp) {
+    __shared__ float blk[QB][QB + 1];
+    const int per_side = nbp / QB;
+    const int i = first + blockIdx.x / (per_side * per_side);
+    const int b = blockIdx.x % (per_side * per_side);
+    const int r0 = (b % per_side) * QB, t0 = (b / per_side) * QB;
+    const float mx = __uint_as_float(absmax[i]);
     int ex = 0;
     if (mx > 0.0f) {
         const float fr = frexpf(mx, &ex);   // mx = fr * 2^ex, fr in [0.5, 1)
         if (fr == 0.5f) ex -= 1;            // an exact power of two maps to 1
     }
     const float inv = ldexpf(1.0f, -ex);
-    if (threadIdx.x == 0) scale[i] = ldexpf(1.0f, ex);
-    // transposed copy in 64 x 64 blocks: src column-major (row r, col t) -> dst[r * nbp + t]
-    for (int r0 = 0; r0 < nbp; r0 += kQBlk)
-        for (int t0 = 0; t0 < nbp; t0 += kQBlk) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < kQBlk * kQBlk; e += kQThreads) {
-                const int rr = e % kQBlk, tt = e / kQBlk;
-                const int r = r0 + rr, t = t0 + tt;
-                blk[rr][tt] = (r < nbp && t < nbp) ? src[r + (int64_t)t * nbp] * inv : 0.0f;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < kQBlk * kQBlk; e += kQThreads) {
-                const int tt = e % kQBlk, rr = e / kQBlk;
-                const int r = r0 + rr, t = t0 + tt;
-                if (r < nbp && t < nbp) dst[(int64_t)r * nbp + t] = (T)blk[rr][tt];   // RNE
-            }
-        }
+    if (b == 0 && threadIdx.x == 0) scale[i] = ldexpf(1.0f, ex);
+    const float *src = p32 + (int64_t)i * nbp * nbp;
+    T *dst = q + (int64_t)i * nbp * nbp;
+    for (int e = threadIdx.x; e < QB * QB; e += kQThreads) {
+        const int rr = e % QB, tt = e / QB;
+        blk[rr][tt] = src[(r0 + rr) + (int64_t)(t0 + tt) * nbp] * inv;   // exact (power of two)
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < QB * QB; e += kQThreads) {
+        const int tt = e % QB, rr = e / QB;
+        dst[(int64_t)(r0 + rr) * nbp + t0 + tt] = (T)blk[rr][tt];   // round to nearest even
+    }
 }
 
 struct LowpArgs {
@@ -86,8 +75,11 @@ struct LowpArgs {
     const float *scale;   // per panel tile
 };
 
-template <int BM_, int BN_, int WM_, int WN_, int KC_> struct LShape {
-    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_;
+// BM x BN output block, WM x WN waves, K chunk KC, DEPTH chunks of operands in flight;
+// CPRE: load the C block into registers before the K loop (its latency hides behind it).
+template <int BM_, int BN_, int WM_, int WN_, int KC_, int DEPTH_ = 1, int CPRE_ = 0> struct LShape {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_, DEPTH = DEPTH_;
+    static constexpr bool CPRE = CPRE_ != 0;
     static constexpr int kThreads = 64 * WM * WN;
 };
 
@@ -130,19 +122,30 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     const int lr = lane & 15, lg = lane >> 4;
 
     f32x4 acc[NBC][NBR];
+    f32x4 cpre[S::CPRE ? NBC : 1][S::CPRE ? NBR : 1];
 #pragma unroll
     for (int a = 0; a < NBC; ++a)
 #pragma unroll
-        for (int b = 0; b < NBR; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NBR; ++b) {
+            acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (S::CPRE)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cpre[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp];
+        }
 
-    vec8 rq[VPQ], rr[VPR];
-    auto load_chunk = [&](int k0) {
+    // Operand chunks stream global -> registers -> LDS.  Chunk x waits in register set
+    // x % DEPTH; DEPTH chunks are in flight while the chunk in LDS feeds the matrix cores
+    // (the 16-bit MFMAs consume a chunk far faster than memory returns one).
+    constexpr int D = S::DEPTH;
+    vec8 rq[D][VPQ], rr[D][VPR];
+    auto load_chunk = [&](vec8 (&sq)[VPQ], vec8 (&sr)[VPR], int k0) {
 #pragma unroll
         for (int v = 0; v < VPQ; ++v) {
             const int idx = v * NT + tid;
             if (NVQ % NT == 0 || idx < NVQ) {
                 const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                rq[v] = *reinterpret_cast<const vec8 *>(Q + (int64_t)row * nbp + k0 + cv * 8);
+                sq[v] = *reinterpret_cast<const vec8 *>(Q + (int64_t)row * nbp + k0 + cv * 8);
             }
         }
 #pragma unroll
@@ -150,17 +153,17 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             const int idx = v * NT + tid;
             if (NVR % NT == 0 || idx < NVR) {
                 const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                rr[v] = *reinterpret_cast<const vec8 *>(R + (int64_t)row * nbp + k0 + cv * 8);
+                sr[v] = *reinterpret_cast<const vec8 *>(R + (int64_t)row * nbp + k0 + cv * 8);
             }
         }
     };
-    auto store_chunk = [&](int buf) {
+    auto store_chunk = [&](const vec8 (&sq)[VPQ], const vec8 (&sr)[VPR], int buf) {
 #pragma unroll
         for (int v = 0; v < VPQ; ++v) {
             const int idx = v * NT + tid;
             if (NVQ % NT == 0 || idx < NVQ) {
                 const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                *reinterpret_cast<vec8 *>(&ldsq[buf][row * LD + cv * 8]) = rq[v];
+                *reinterpret_cast<vec8 *>(&ldsq[buf][row * LD + cv * 8]) = sq[v];
             }
         }
 #pragma unroll
@@ -168,18 +171,11 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             const int idx = v * NT + tid;
             if (NVR % NT == 0 || idx < NVR) {
                 const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + cv * 8]) = rr[v];
+                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + cv * 8]) = sr[v];
             }
         }
     };
-
-    const int nchunks = nbp / KC;
-    load_chunk(0);
-    store_chunk(0);
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) load_chunk((c + 1) * KC);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int s = 0; s < KC / 32; ++s) {
             const int k = 32 * s + 8 * lg;     // this lane's 8 consecutive k
@@ -195,8 +191,27 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
 #pragma unroll
                 for (int b = 0; b < NBR; ++b) acc[a][b] = L::mac(qa[a], rb[b], acc[a][b]);
         }
-        if (c + 1 < nchunks) store_chunk(buf ^ 1);
-        __syncthreads();
+    };
+
+    const int nchunks = nbp / KC;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (j < nchunks) load_chunk(rq[j], rr[j], j * KC);
+    store_chunk(rq[0], rr[0], 0);
+    if (D < nchunks) load_chunk(rq[0], rr[0], D * KC);
+    __syncthreads();
+    for (int c0 = 0; c0 < nchunks; c0 += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int c = c0 + j;
+            if (c < nchunks) {
+                compute(c & 1);
+                const int nxt = (j + 1) % D;   // register set of chunk c + 1
+                if (c + 1 < nchunks) store_chunk(rq[nxt], rr[nxt], (c + 1) & 1);
+                if (c + 1 + D < nchunks) load_chunk(rq[nxt], rr[nxt], (c + 1 + D) * KC);
+                __syncthreads();
+            }
+        }
     }
     // result register q of lane (16 g + r): row lr of the b block, column 4 g + q of the a block
 #pragma unroll
@@ -208,7 +223,8 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
                 const int row = row0 + wrow + b * 16 + lr;
                 const int col = col0 + wcol + a * 16 + 4 * lg + q;
                 float *pc = C + row + (int64_t)col * nbp;
-                *pc = *pc + factor * acc[a][b][q];
+                const float c0v = S::CPRE ? cpre[S::CPRE ? a : 0][S::CPRE ? b : 0][q] : *pc;
+                *pc = c0v + factor * acc[a][b][q];
             }
 }
 
@@ -226,22 +242,32 @@ void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
 template <typename T>
 void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
     const int nbp = g.map.nbp;
-    if (nbp % 128 == 0 && nbp % 64 == 0) launch_lowp_shape<T, LShape<128, 128, 2, 2, 64>>(g, ntiles, stream);
-    else if (nbp % 64 == 0) launch_lowp_shape<T, LShape<64, 64, 2, 2, 64>>(g, ntiles, stream);
-    else launch_lowp_shape<T, LShape<32, 32, 2, 2, 32>>(g, ntiles, stream);
+    // 128 x 64 blocks, 4 chunks in flight, C loaded up front: the 16-bit MFMAs outrun memory,
+    // so the kernel is shaped for bytes in flight (measured best on the n ~ 1e5 step-0 list)
+    if (nbp % 128 == 0) launch_lowp_shape<T, LShape<128, 64, 2, 2, 32, 4, 1>>(g, ntiles, stream);
+    else if (nbp % 64 == 0) launch_lowp_shape<T, LShape<64, 64, 2, 2, 32, 4, 1>>(g, ntiles, stream);
+    else launch_lowp_shape<T, LShape<32, 32, 2, 2, 32, 1, 0>>(g, ntiles, stream);
 }
 
 }  // namespace
 
-void launch_quantize(const TileMap &map, int first, int count, const float *p32, void *q, float *scale,
-                     int lowp, hipStream_t stream) {
+void launch_quantize(const TileMap &map, int first, int count, const float *p32, const unsigned *absmax,
+                     void *q, float *scale, int lowp, hipStream_t stream) {
     if (count <= 0) return;
-    if (lowp == 1)
-        hipLaunchKernelGGL(quantize_kernel<_Float16>, dim3((unsigned)count), dim3(kQThreads), 0, stream, p32,
-                           static_cast<_Float16 *>(q), scale, first, map.nbp);
-    else
-        hipLaunchKernelGGL(quantize_kernel<__bf16>, dim3((unsigned)count), dim3(kQThreads), 0, stream, p32,
-                           static_cast<__bf16 *>(q), scale, first, map.nbp);
+    const int qb = (map.nbp % 64 == 0) ? 64 : 32;   // transpose block (nbp is a multiple of 32)
+    const int per_side = map.nbp / qb;
+    const unsigned blocks = (unsigned)((int64_t)count * per_side * per_side);
+#define MPGEO_QUANT(T, QB)                                                                          \
+    hipLaunchKernelGGL((quantize_kernel<T, QB>), dim3(blocks), dim3(kQThreads), 0, stream, p32, absmax, \
+                       static_cast<T *>(q), scale, first, map.nbp)
+    if (lowp == 1) {
+        if (qb == 64) MPGEO_QUANT(_Float16, 64);
+        else MPGEO_QUANT(_Float16, 32);
+    } else {
+        if (qb == 64) MPGEO_QUANT(__bf16, 64);
+        else MPGEO_QUANT(__bf16, 32);
+    }
+#undef MPGEO_QUANT
 }
 
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
