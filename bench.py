@@ -36,25 +36,70 @@ PEAK_FP32_MATRIX = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP64_MATRIX = 78.6    # TFLOP/s, MI355X dense FP64 matrix
 PEAKS = {"update_lowp": PEAK_FP16_MATRIX, "update_fp32": PEAK_FP32_MATRIX,
          "update_fp64": PEAK_FP64_MATRIX}
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "update_fp32_hbm_traffic_matern-n99856-nb512-band2.md")
-GEMM_SOURCE = os.path.join(ROOT, "paper_2003_05324_amd", "csrc", "gemm.hip")
+PEAK_HBM_GBS = 8000.0      # GB/s, MI355X HBM3E
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries, one per update kernel, each naming
+# the kernel source it was measured on (the figure is void once that source changed)
+TRAFFIC_PROFILES = {
+    "update_lowp": ("update_lowp_hbm_traffic_matern-n99856-nb512-band2-band32_8-fp16.md", "lowp.hip"),
+    "update_fp32": ("update_fp32_hbm_traffic_matern-n99856-nb512-band2.md", "gemm.hip"),
+}
 
 
-def measured_traffic(n, tile, band):
-    """HBM bytes per launch of the FP32 update kernel from the committed rocprofv3 counter
-    summary, or None when the workload differs or the kernel source changed since."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of an update kernel from its committed rocprofv3 counter summary,
+    or None when there is none for this workload or the kernel source changed since."""
     import hashlib
     import re
-    if (n, tile, band) != (99856, 512, 2) or not os.path.exists(TRAFFIC_PROFILE):
+    if kernel not in TRAFFIC_PROFILES:
         return None
-    text = open(TRAFFIC_PROFILE).read()
-    sha = re.search(r"gemm.hip sha256 at measurement: ([0-9a-f]+)", text)
+    fname, src = TRAFFIC_PROFILES[kernel]
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    wl = re.search(r"workload: (\S+)", text)
+    sha = re.search(r"sha256 at measurement: ([0-9a-f]+)", text)
     val = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
-    if not sha or not val:
+    if not wl or wl.group(1) != workload or not sha or not val:
         return None
-    if hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest() != sha.group(1):
+    source = os.path.join(ROOT, "paper_2003_05324_amd", "csrc", src)
+    if hashlib.sha256(open(source, "rb").read()).hexdigest() != sha.group(1):
         return None
     return float(val.group(1))
+
+
+def roofline(stats, workload):
+    """Roofline of the dominant kernel: the update class with the largest share of the
+    algorithmic flops.  Its bound follows from its arithmetic intensity: below the ridge
+    point peak_flops / peak_bandwidth it is HBM-bound and is rated in GB/s of algorithmic
+    bytes, above it MFMA-bound and rated in TFLOP/s."""
+    updates = [s for s in stats if s["name"] in PEAKS and s["launches"]]
+    dom = max(updates, key=lambda s: s["flops"])
+    peak_flops = PEAKS[dom["name"]]
+    intensity = dom["flops"] / dom["bytes"]
+    ridge = peak_flops * 1e12 / (PEAK_HBM_GBS * 1e9)
+    tflops = dom["flops"] / dom["seconds"] / 1e12
+    gbs = dom["bytes"] / dom["seconds"] / 1e9
+    out = {"kernel": dom["name"]}
+    if intensity < ridge:
+        out.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": gbs / PEAK_HBM_GBS})
+    else:
+        out.update({"bound": "mfma", "achieved": tflops, "peak": peak_flops, "unit": "TFLOP/s",
+                    "frac": tflops / peak_flops})
+    traffic = measured_traffic(dom["name"], workload)
+    out.update({
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+        "flops_per_launch": dom["flops"] / dom["launches"],
+        "intensity_flop_per_byte": intensity,
+        "ridge_flop_per_byte": ridge,
+        "tflops": tflops,
+        "tflops_frac_of_matrix_peak": tflops / peak_flops,
+        "avg_launch_ms": 1e3 * dom["seconds"] / dom["launches"],
+        "launches": dom["launches"],
+    })
+    return out
 
 
 def parse():
@@ -221,12 +266,9 @@ def main():
     ll64 = legs["fp64"][1][-1]["loglik"] if "fp64" in legs else None
     main_leg = leg_summary(wall, res, args.steps, n, ll64)
     value = main_leg["evals_per_s"]
-    # dominant kernel: the update class with the largest share of kernel time
-    updates = [s for s in stats if s["name"] in PEAKS and s["launches"]]
-    dom = max(updates, key=lambda s: s["seconds"])
-    achieved = dom["flops"] / dom["seconds"] / 1e12
-    peak = PEAKS[dom["name"]]
     dtype = "f64+f32+" + lowp.replace("fp", "f") if lowp else "f64+f32"
+    workload = (f"matern-n{n}-nb{args.tile}-band{args.band}"
+                + (f"-band32_{band32}-{lowp}" if lowp else ""))
     out = {
         "metric": METRIC,
         "value": value,
@@ -240,28 +282,17 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"matern-n{n}-nb{args.tile}-band{args.band}"
-                               + (f"-band32_{band32}-{lowp}" if lowp else ""),
+        "config": {"workload": workload,
                    "n": n, "grid": f"{m}x{m} jittered", "theta": list(theta), "tile": args.tile,
                    "band64": args.band, "band32": band32, "lowp": lowp},
         "cholesky_tflops": main_leg["cholesky_tflops"],
         "p50_s": main_leg["p50_s"],
         "p99_s": main_leg["p99_s"],
         "loglik": main_leg["loglik"],
-        "roofline": {
-            "kernel": dom["name"],
-            "bound": "mfma",
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": (measured_traffic(n, args.tile, args.band)
-                        if dom["name"] == "update_fp32" and not lowp else None),
-            "avg_launch_ms": 1e3 * dom["seconds"] / dom["launches"],
-            "launches": dom["launches"],
-        },
+        "roofline": roofline(stats, workload),
         "kernels": {s["name"]: {"launches": s["launches"], "seconds": s["seconds"],
-                                "tflops": (s["flops"] / s["seconds"] / 1e12) if s["seconds"] else None}
+                                "tflops": (s["flops"] / s["seconds"] / 1e12) if s["seconds"] else None,
+                                "gbs": (s["bytes"] / s["seconds"] / 1e9) if s["seconds"] else None}
                     for s in stats if s["launches"]},
     }
     if ll64 is not None:

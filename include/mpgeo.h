@@ -61,6 +61,16 @@ typedef enum {
 #define MPGEO_ORDER_MORTON 1u   /* reorder locations (and Z) by Z-order key before tiling */
 #define MPGEO_INPUT_DEVICE 2u   /* pointer arguments are device pointers */
 #define MPGEO_TIMING       4u   /* record HIP events per kernel launch (see mpgeo_ctx_kernel_stats) */
+/* Profile likelihood in (theta2, theta3) (Section IV-C: for fixed range and smoothness the
+ * variance maximising eq. (2) is theta1 = Z^T Sigma~^-1 Z / n, Sigma~ the correlation matrix,
+ * i.e. eq. (1) at theta1 = 1).  With this flag theta.sigma2 is ignored (it must still be
+ * finite and positive), the tiles hold
+ * Sigma~, mpgeo_result.logdet = log|Sigma~|, .quad = q~ = Z^T Sigma~^-1 Z, and
+ *   .loglik = -n/2 log(2 pi) - n/2 - n/2 log(q~ / n) - logdet/2,
+ * which equals eq. (2) at theta = (q~/n, theta2, theta3).  The printed profile equation has
+ * its trailing terms garbled; this is the form the substitution gives.  The variance
+ * estimate is q~/n.  Kriging after such an evaluation uses theta1 = q~/n. */
+#define MPGEO_PROFILE      8u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
  * (smoothness); all must be finite and > 0. */
@@ -76,7 +86,7 @@ typedef struct {
  *  band32: c >= 0: FP32 operands for band64 < i - j <= band64 + c, 16-bit operands beyond;
  *          -1: FP32 from band64 + 1 to the edge of the matrix (two tiers).
  *  lowp:   0 with band32 = -1; 1 (FP16) or 2 (BF16) with band32 >= 0.
- *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING. */
+ *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING | MPGEO_PROFILE. */
 typedef struct {
     int32_t tile;
     int32_t band64;
@@ -139,8 +149,9 @@ int mpgeo_dataset_create(mpgeo_ctx *ctx, int64_t n, const double *locs, const do
                          uint32_t flags, mpgeo_dataset **out);
 int mpgeo_dataset_destroy(mpgeo_dataset *ds);
 
-/* eq. (2) at theta for the resident dataset.  plan.flags may add MPGEO_TIMING; its
- * ordering and input flags are ignored (fixed at dataset creation). */
+/* eq. (2) at theta for the resident dataset (or the profile likelihood with
+ * MPGEO_PROFILE).  plan.flags may add MPGEO_TIMING and MPGEO_PROFILE; its ordering and
+ * input flags are ignored (fixed at dataset creation). */
 int mpgeo_dataset_loglik(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
                          mpgeo_result *out);
 
@@ -168,7 +179,8 @@ int mpgeo_dataset_solution(mpgeo_dataset *ds, double *y);
  * z = P^T L P eps, a draw of the zero-mean Gaussian field with covariance Sigma(theta),
  * where P is the dataset's ordering.  eps (n standard normal values) and z_out are in
  * the caller's order, host or device like the dataset.  The dataset's own data vector is
- * not changed; the factor stays resident as after a loglik call. */
+ * not changed; the factor stays resident as after a loglik call.  MPGEO_E_ARG with
+ * MPGEO_PROFILE (a draw needs the variance). */
 int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
                            const double *eps, double *z_out);
 
@@ -187,7 +199,9 @@ int mpgeo_dataset_entries(mpgeo_dataset *ds, int64_t count, const int64_t *rows,
  * scores -infinity.  Stops when the simplex spans less than xtol (log units, max-norm),
  * when ftol > 0 and its log-likelihoods differ by less than ftol * |best|, or after
  * max_evals evaluations.  Writes the best theta, its log-likelihood, and the evaluation and
- * iteration counts (any output pointer may be NULL). */
+ * iteration counts (any output pointer may be NULL).  With MPGEO_PROFILE in plan.flags the
+ * simplex is two-dimensional, over (log theta2, log theta3) of the profile likelihood
+ * (start.sigma2 is ignored), and theta_hat.sigma2 = q~/n at the best point. */
 int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
                       double ftol, int32_t max_evals, mpgeo_theta *theta_hat,
                       double *loglik_hat, int32_t *evals, int32_t *iters);
@@ -195,7 +209,8 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
 /* Algorithm 1 on a caller-given symmetric positive-definite matrix: A is n x n,
  * column-major with leading dimension lda >= n, only its lower triangle is read; z
  * (n entries) is optional (NULL: quad = 0 and loglik uses quad = 0).  No reordering.
- * Fills logdet, quad and loglik as for eq. (2). */
+ * Fills logdet, quad and loglik as for eq. (2) (with MPGEO_PROFILE: A is taken as Sigma~ and
+ * loglik is the profile form, which needs z). */
 int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda,
                        const double *z, mpgeo_plan plan, mpgeo_result *out);
 

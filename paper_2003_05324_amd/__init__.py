@@ -23,6 +23,7 @@ MPGEO_OK, MPGEO_E_ARG, MPGEO_E_NOT_SPD, MPGEO_E_NOMEM, MPGEO_E_DEVICE, MPGEO_E_U
 MPGEO_ORDER_MORTON = 1
 MPGEO_INPUT_DEVICE = 2
 MPGEO_TIMING = 4
+MPGEO_PROFILE = 8
 
 EXPORTED = (
     "mpgeo_ctx_create", "mpgeo_ctx_destroy", "mpgeo_ctx_kernel_stats", "mpgeo_ctx_reset_stats",
@@ -165,13 +166,15 @@ class Context:
             pass
 
     def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
-               morton: bool = True, timing: bool = False, band32: int = -1, lowp=None) -> dict:
-        """One-shot eq. (2): ordering, covariance tiles, factor, solve, reduction."""
+               morton: bool = True, timing: bool = False, band32: int = -1, lowp=None,
+               profile: bool = False) -> dict:
+        """One-shot eq. (2) (or the profile likelihood): ordering, covariance tiles, factor,
+        solve, reduction."""
         dev = isinstance(locs, torch.Tensor)
         if not dev:
             locs, z = _host_f64(locs), _host_f64(z)
         flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0) | \
-                (MPGEO_TIMING if timing else 0)
+                (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0)
         res = Result()
         st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
                               make_plan(tile, band64, flags, band32, lowp), ctypes.byref(res))
@@ -231,11 +234,11 @@ class Dataset:
             pass
 
     def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False,
-               band32: int = -1, lowp=None) -> dict:
+               band32: int = -1, lowp=None, profile: bool = False) -> dict:
         res = Result()
+        flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0)
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
-                                      make_plan(tile, band64, MPGEO_TIMING if timing else 0,
-                                                band32, lowp),
+                                      make_plan(tile, band64, flags, band32, lowp),
                                       ctypes.byref(res))
         _check(st, "mpgeo_dataset_loglik", res.info)
         return res.as_dict()
@@ -277,9 +280,12 @@ class Dataset:
         _check(LIB.mpgeo_dataset_perm(self.handle, out.ctypes.data), "mpgeo_dataset_perm")
         return out
 
-    def covariance(self, theta: Sequence[float], tile: int, band64: int) -> np.ndarray:
-        """Sigma as stored in its tiles (tier-rounded), lower triangle, ordered."""
-        _check(LIB.mpgeo_dataset_covariance(self.handle, Theta(*theta), make_plan(tile, band64)),
+    def covariance(self, theta: Sequence[float], tile: int, band64: int,
+                   profile: bool = False) -> np.ndarray:
+        """Sigma (the correlation matrix with profile=True) as stored in its tiles
+        (tier-rounded), lower triangle, ordered."""
+        plan = make_plan(tile, band64, MPGEO_PROFILE if profile else 0)
+        _check(LIB.mpgeo_dataset_covariance(self.handle, Theta(*theta), plan),
                "mpgeo_dataset_covariance")
         return self.matrix()
 
@@ -298,13 +304,16 @@ class Dataset:
         return out
 
     def mle(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
-            ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None) -> dict:
-        """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2))."""
+            ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None,
+            profile: bool = False) -> dict:
+        """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2)); with
+        profile=True a two-dimensional search over (theta2, theta3) of the profile likelihood."""
         th = Theta()
         ll = ctypes.c_double()
         ev = ctypes.c_int32()
         it = ctypes.c_int32()
-        _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), make_plan(tile, band64, 0, band32, lowp), xtol, ftol,
+        plan = make_plan(tile, band64, MPGEO_PROFILE if profile else 0, band32, lowp)
+        _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), plan, xtol, ftol,
                                      max_evals, ctypes.byref(th), ctypes.byref(ll), ctypes.byref(ev),
                                      ctypes.byref(it)), "mpgeo_dataset_mle")
         return {"theta": (th.sigma2, th.beta, th.nu), "loglik": ll.value, "evals": ev.value,

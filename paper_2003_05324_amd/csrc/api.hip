@@ -279,7 +279,9 @@ struct mpgeo_dataset {
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
     bool has_factor = false;
-    mpgeo_theta theta{};
+    mpgeo_theta theta{};      // theta of the resident factor (theta1 = 1 for a profile evaluation)
+    bool profile = false;     // the last evaluation used the profile likelihood
+    double var_scale = 1.0;   // kriging variance scale: the variance estimate q~/n after a profile evaluation
 };
 
 namespace {
@@ -510,19 +512,26 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
                       (double)(p - 1 - k) * nbd * nbd * 16.0,
                       [&] { launch_panel_solve(map, k, p64, pa.y, r, s1); });
     };
-    // update of list entries [b, e) of each tier with panel k on stream st
+    // update of list entries [b, e) of each tier with panel k on stream st.  Algorithmic
+    // bytes: every output tile read and written once, every panel tile it needs read once
+    // (at most p - 1 - k distinct panel tiles, at most two per output tile).
     auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, int64_t b16,
                             int64_t e16, double f64, double f32, double f16, hipStream_t st) {
+        const double tile_elems = (double)nbd * nbd;
+        auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(p - 1 - k, 2 * count); };
         if (e16 > b16)
-            ctx->timed_on(st, kStatUpdate16, f16, (double)(e16 - b16) * nbd * nbd * 4.0 * 2.0, [&] {
+            ctx->timed_on(st, kStatUpdate16, f16,
+                          tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 + panel_tiles(e16 - b16) * 2.0), [&] {
                 launch_update_lowp(map, l16 + b16, e16 - b16, qpanel(k), qscale(k), L.lowp, st);
             });
         if (e64 > b64)
-            ctx->timed_on(st, kStatUpdate64, f64, (double)(e64 - b64) * nbd * nbd * 8.0 * 2.0, [&] {
+            ctx->timed_on(st, kStatUpdate64, f64,
+                          tile_elems * ((double)(e64 - b64) * 8.0 * 2.0 + panel_tiles(e64 - b64) * 8.0), [&] {
                 launch_update(map, l64 + b64, e64 - b64, true, panel64(k), panel32(k), st);
             });
         if (e32 > b32)
-            ctx->timed_on(st, kStatUpdate32, f32, (double)(e32 - b32) * nbd * nbd * 4.0 * 2.0, [&] {
+            ctx->timed_on(st, kStatUpdate32, f32,
+                          tile_elems * ((double)(e32 - b32) * 4.0 * 2.0 + panel_tiles(e32 - b32) * 4.0), [&] {
                 launch_update(map, l32 + b32, e32 - b32, false, panel64(k), panel32(k), st);
             });
     };
@@ -554,7 +563,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[p - 1], 0));
     if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s0));
     ctx->timed(kStatFinal, 2.0 * p, 16.0 * p, [&] {
-        launch_finalize(logdet_part, quad_part, p, L.n, ds->result.as<double>(), s0);
+        launch_finalize(logdet_part, quad_part, p, L.n, ds->profile, ds->result.as<double>(), s0);
     });
     MPGEO_HIP(hipGetLastError());
     return MPGEO_OK;
@@ -606,9 +615,13 @@ int evaluate(mpgeo_dataset *ds, const mpgeo_theta &th, const mpgeo_plan &pl, mpg
     mpgeo_ctx *ctx = ds->ctx;
     hipStream_t s = ctx->stream;
     MPGEO_TRY(prepare_layout(ds, pl));
+    // profile likelihood: the tiles hold the correlation matrix (theta1 = 1)
+    ds->profile = (pl.flags & MPGEO_PROFILE) != 0;
+    mpgeo_theta th_eval = th;
+    if (ds->profile) th_eval.sigma2 = 1.0;
     EventSet ev;
     if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[0], s));
-    MPGEO_TRY(run_covgen(ds, th));
+    MPGEO_TRY(run_covgen(ds, th_eval));
     if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[1], s));
     MPGEO_TRY(run_factor(ds, ev.ok ? ev.e[2] : nullptr));
     if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[3], s));
@@ -625,7 +638,8 @@ int evaluate(mpgeo_dataset *ds, const mpgeo_theta &th, const mpgeo_plan &pl, mpg
     }
     ctx->collect();
     ds->has_factor = (st == MPGEO_OK);
-    ds->theta = th;
+    ds->theta = th_eval;
+    ds->var_scale = ds->profile ? out->quad / (double)ds->layout.n : 1.0;
     return st;
 }
 
@@ -810,7 +824,9 @@ int mpgeo_dataset_covariance(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan pl
     MPGEO_TRY(check_plan(plan));
     Device dev(ds->ctx->device);
     MPGEO_TRY(prepare_layout(ds, plan));
-    MPGEO_TRY(run_covgen(ds, theta));
+    mpgeo_theta th = theta;
+    if (plan.flags & MPGEO_PROFILE) th.sigma2 = 1.0;   // the correlation matrix
+    MPGEO_TRY(run_covgen(ds, th));
     ds->has_factor = false;
     MPGEO_HIP(hipStreamSynchronize(ds->ctx->stream));
     ds->ctx->collect();
@@ -883,7 +899,7 @@ int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs, do
         double *tmp = c + (size_t)ldc * m;
         launch_cross_cov(ds->locs.as<double>(), L.n, L.nb, L.nbp, L.p, dnew, m, mp, c, ldc, s);
         launch_forward_multi(tile_map(ds), ds->linv.as<double>(), c, ldc, m, tmp, s);
-        launch_column_var(c, ldc, ldc, m, ds->theta.sigma2, dvar, s);
+        launch_column_var(c, ldc, ldc, m, ds->theta.sigma2, ds->var_scale, dvar, s);
         MPGEO_HIP(hipGetLastError());
     }
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -927,9 +943,15 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
     if (!dev.ok) return MPGEO_E_DEVICE;
     static const double lo[3] = {0.01, 0.001, 0.1};
     static const double hi[3] = {10.0, 2.0, 3.0};
+    // the simplex lives in log-parameter space: (theta1, theta2, theta3), or (theta2, theta3)
+    // for the profile likelihood, whose theta1 is then q~/n at the best point
+    const bool profile = (plan.flags & MPGEO_PROFILE) != 0;
+    const int dim = profile ? 2 : 3;
+    const int first = profile ? 1 : 0;
     auto to_theta = [&](const double *u) {
-        double t[3];
-        for (int q = 0; q < 3; ++q) t[q] = std::min(std::max(std::exp(u[q]), lo[q]), hi[q]);
+        double t[3] = {1.0, 1.0, 1.0};
+        for (int q = 0; q < dim; ++q)
+            t[first + q] = std::min(std::max(std::exp(u[q]), lo[first + q]), hi[first + q]);
         return mpgeo_theta{t[0], t[1], t[2]};
     };
     int hard_error = MPGEO_OK;
@@ -941,87 +963,95 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
         if (st != MPGEO_E_NOT_SPD && hard_error == MPGEO_OK) hard_error = st;
         return INFINITY;
     };
-    double x[4][3];
+    const int nv = dim + 1;
+    double x[4][3] = {};
     double fv[4];
-    const double u0[3] = {std::log(start.sigma2), std::log(start.beta), std::log(start.nu)};
-    for (int v = 0; v < 4; ++v)
-        for (int q = 0; q < 3; ++q) x[v][q] = u0[q] + ((v > 0 && q == v - 1) ? 0.1 : 0.0);
+    const double start_t[3] = {start.sigma2, start.beta, start.nu};
+    for (int v = 0; v < nv; ++v)
+        for (int q = 0; q < dim; ++q)
+            x[v][q] = std::log(start_t[first + q]) + ((v > 0 && q == v - 1) ? 0.1 : 0.0);
     int evals = 0, iters = 0;
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < nv; ++v) {
         fv[v] = f(x[v]);
         ++evals;
     }
+    const size_t row = sizeof(x[0]);
     while (evals < max_evals && hard_error == MPGEO_OK) {
         int order[4] = {0, 1, 2, 3};
-        std::stable_sort(order, order + 4, [&](int a, int b) { return fv[a] < fv[b]; });
-        double xs[4][3], fs[4];
-        for (int v = 0; v < 4; ++v) {
+        std::stable_sort(order, order + nv, [&](int a, int b) { return fv[a] < fv[b]; });
+        double xs[4][3] = {}, fs[4];
+        for (int v = 0; v < nv; ++v) {
             fs[v] = fv[order[v]];
-            for (int q = 0; q < 3; ++q) xs[v][q] = x[order[v]][q];
+            for (int q = 0; q < dim; ++q) xs[v][q] = x[order[v]][q];
         }
         std::memcpy(x, xs, sizeof(x));
         std::memcpy(fv, fs, sizeof(fv));
         double span = 0.0;
-        for (int v = 1; v < 4; ++v)
-            for (int q = 0; q < 3; ++q) span = std::max(span, std::fabs(x[v][q] - x[0][q]));
-        if (span < xtol || (ftol > 0.0 && std::fabs(fv[3] - fv[0]) <= ftol * std::fabs(fv[0]))) break;
+        for (int v = 1; v < nv; ++v)
+            for (int q = 0; q < dim; ++q) span = std::max(span, std::fabs(x[v][q] - x[0][q]));
+        if (span < xtol || (ftol > 0.0 && std::fabs(fv[dim] - fv[0]) <= ftol * std::fabs(fv[0]))) break;
         ++iters;
-        double c[3], xr[3], xe[3], xc[3];
-        for (int q = 0; q < 3; ++q) c[q] = (x[0][q] + x[1][q] + x[2][q]) / 3.0;
-        for (int q = 0; q < 3; ++q) xr[q] = c[q] + (c[q] - x[3][q]);
+        const int w = dim;   // worst vertex
+        double c[3] = {}, xr[3] = {}, xe[3] = {}, xc[3] = {};
+        for (int q = 0; q < dim; ++q) {
+            for (int v = 0; v < dim; ++v) c[q] += x[v][q];
+            c[q] /= (double)dim;
+        }
+        for (int q = 0; q < dim; ++q) xr[q] = c[q] + (c[q] - x[w][q]);
         const double fr = f(xr);
         ++evals;
         if (fr < fv[0]) {
-            for (int q = 0; q < 3; ++q) xe[q] = c[q] + 2.0 * (c[q] - x[3][q]);
+            for (int q = 0; q < dim; ++q) xe[q] = c[q] + 2.0 * (c[q] - x[w][q]);
             const double fe = f(xe);
             ++evals;
             if (fe < fr) {
-                std::memcpy(x[3], xe, sizeof(xe));
-                fv[3] = fe;
+                std::memcpy(x[w], xe, row);
+                fv[w] = fe;
             } else {
-                std::memcpy(x[3], xr, sizeof(xr));
-                fv[3] = fr;
+                std::memcpy(x[w], xr, row);
+                fv[w] = fr;
             }
             continue;
         }
-        if (fr < fv[2]) {
-            std::memcpy(x[3], xr, sizeof(xr));
-            fv[3] = fr;
+        if (fr < fv[w - 1]) {
+            std::memcpy(x[w], xr, row);
+            fv[w] = fr;
             continue;
         }
-        if (fr < fv[3]) {
-            for (int q = 0; q < 3; ++q) xc[q] = c[q] + 0.5 * (xr[q] - c[q]);   // outside
+        if (fr < fv[w]) {
+            for (int q = 0; q < dim; ++q) xc[q] = c[q] + 0.5 * (xr[q] - c[q]);   // outside
             const double fc = f(xc);
             ++evals;
             if (fc <= fr) {
-                std::memcpy(x[3], xc, sizeof(xc));
-                fv[3] = fc;
+                std::memcpy(x[w], xc, row);
+                fv[w] = fc;
                 continue;
             }
         } else {
-            for (int q = 0; q < 3; ++q) xc[q] = c[q] + 0.5 * (x[3][q] - c[q]);   // inside
+            for (int q = 0; q < dim; ++q) xc[q] = c[q] + 0.5 * (x[w][q] - c[q]);   // inside
             const double fc = f(xc);
             ++evals;
-            if (fc < fv[3]) {
-                std::memcpy(x[3], xc, sizeof(xc));
-                fv[3] = fc;
+            if (fc < fv[w]) {
+                std::memcpy(x[w], xc, row);
+                fv[w] = fc;
                 continue;
             }
         }
-        for (int v = 1; v < 4; ++v) {   // shrink towards the best vertex
-            for (int q = 0; q < 3; ++q) x[v][q] = x[0][q] + 0.5 * (x[v][q] - x[0][q]);
+        for (int v = 1; v < nv; ++v) {   // shrink towards the best vertex
+            for (int q = 0; q < dim; ++q) x[v][q] = x[0][q] + 0.5 * (x[v][q] - x[0][q]);
             fv[v] = f(x[v]);
             ++evals;
         }
     }
     if (hard_error != MPGEO_OK) return hard_error;
     int best = 0;
-    for (int v = 1; v < 4; ++v)
+    for (int v = 1; v < nv; ++v)
         if (fv[v] < fv[best]) best = v;
     if (!std::isfinite(fv[best])) return MPGEO_E_NOT_SPD;
-    const mpgeo_theta th = to_theta(x[best]);
+    mpgeo_theta th = to_theta(x[best]);
     mpgeo_result r{};
     MPGEO_TRY(evaluate(ds, th, plan, &r, nullptr));   // leave the factor of theta_hat resident
+    if (profile) th.sigma2 = r.quad / (double)ds->layout.n;
     if (theta_hat) *theta_hat = th;
     if (loglik_hat) *loglik_hat = r.loglik;
     if (evals_out) *evals_out = evals;
@@ -1031,7 +1061,7 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
 
 int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
                            const double *eps, double *z_out) {
-    if (!ds || !eps || !z_out) return MPGEO_E_ARG;
+    if (!ds || !eps || !z_out || (plan.flags & MPGEO_PROFILE)) return MPGEO_E_ARG;
     MPGEO_TRY(check_theta(theta));
     MPGEO_TRY(check_plan(plan));
     Device dev(ds->ctx->device);
@@ -1078,6 +1108,7 @@ int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan
 int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, const double *z,
                        mpgeo_plan plan, mpgeo_result *out) {
     if (!ctx || !out || !a || n < 1 || lda < n) return MPGEO_E_ARG;
+    if ((plan.flags & MPGEO_PROFILE) && !z) return MPGEO_E_ARG;
     out->info = -1;
     MPGEO_TRY(check_plan(plan));
     Device dev(ctx->device);
@@ -1085,6 +1116,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
     mpgeo_dataset ds;
     ds.ctx = ctx;
     ds.n = n;
+    ds.profile = (plan.flags & MPGEO_PROFILE) != 0;
     hipStream_t s = ctx->stream;
     const bool on_dev = (plan.flags & MPGEO_INPUT_DEVICE) != 0;
     int st = prepare_layout(&ds, plan);

@@ -132,7 +132,7 @@ void launch_permute(const double *src, double *dst, const int64_t *perm, int64_t
 
 // Reduction of the per-step parts into {loglik, logdet, quad} (device double[3]).
 void launch_finalize(const double *logdet_part, const double *quad_part, int p, int64_t n,
-                     double *result, hipStream_t stream);
+                     bool profile, double *result, hipStream_t stream);
 
 // Backward solve w = L^-T y over the tiles (uses the stored diagonal inverses).
 void launch_backward_solve(const TileMap &map, const double *linv_all, const double *y,
@@ -148,10 +148,11 @@ void launch_cross_cov(const double *locs, int64_t n, int nb, int nbp, int p,
                       const double *new_locs, int64_t m, const MaternParams &mp, double *c,
                       int64_t ldc, hipStream_t stream);
 
-// Forward solve of many right-hand sides and their column norms: var_j = sigma2 - |L^-1 c_j|^2.
+// Forward solve of many right-hand sides and their column norms:
+// var_j = scale * (sigma2 - |L^-1 c_j|^2).
 void launch_forward_multi(const TileMap &map, const double *linv_all, double *c, int64_t ldc,
                           int64_t m, double *tmp, hipStream_t stream);
 void launch_column_var(const double *c, int64_t ldc, int64_t rows, int64_t m, double sigma2,
-                       double *var, hipStream_t stream);
+                       double scale, double *var, hipStream_t stream);
 
 }  // namespace mpgeo

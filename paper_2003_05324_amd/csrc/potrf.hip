@@ -1,18 +1,19 @@
 // FP64 Cholesky of one diagonal tile (dpotrf of Algorithm 1) fused with its inverse,
 // the forward-solve block and the log-determinant / quadratic-form parts of eq. (2).
 //
-// One workgroup factors the nbp x nbp tile A in 32-column blocks, right-looking, and
-// applies the same eliminations to an identity matrix B, so that on exit A holds L (lower,
-// positive diagonal) and B holds L^-1.  Per block c (columns cb .. cb+31, split = cb + 32):
-//   1. one wave factors the 32 x 32 diagonal block D in LDS and inverts it (Dinv);
-//   2. the block rows c of B are multiplied by Dinv (rows of L^-1 for this block), and the
-//      panel rows t >= split of A are solved against D^T (rows of L) — both in place, on
-//      the matrix cores;
+// One workgroup factors the nbp x nbp tile A in 32-column blocks, right-looking, and builds
+// B = L^-1 block row by block row, so that on exit A holds L (lower, positive diagonal) and
+// B holds L^-1 (upper part zero).  Per block c (columns cb .. cb+31, split = cb + 32):
+//   1. the 32 x 32 diagonal block D is staged in LDS and factored by one wave;
+//   2. forward substitution with D, one thread per index t: for t < split the block rows c
+//      of L^-1 (right-hand side B[cb + q][t], or the identity inside the diagonal block),
+//      for t >= split the panel rows of L (right-hand side A[t][cb + q], solved against
+//      D^T).  These block rows of B are final, so their FP32 copy is written here too;
 //   3. for rows i >= split and columns j <= i:  M_ij -= sum_l V_il V_jl, with M = B and
 //      V_j = (new B block rows)(:, j) for j < split, M = A and V_j = L(j, block c) otherwise.
-//      This rank-32 update runs on v_mfma_f64_16x16x4_f64 over 16 x 16 blocks, with the
-//      operands read from the tile (L2-resident) rather than staged in LDS, so the kernel
-//      needs little LDS and can share a compute unit with the trailing-update kernels.
+//      This rank-32 update runs on v_mfma_f64_16x16x4_f64, each wave taking 32 x 32 regions,
+//      with the operands read from the tile (L2-resident) rather than staged in LDS, so the
+//      kernel needs little LDS and can share a compute unit with the trailing-update kernels.
 // Then y = L^-1 r, quad = y^T y and logdet = 2 sum log L_ii are formed.
 #include "common.h"
 
@@ -22,11 +23,22 @@ namespace mpgeo {
 
 namespace {
 
-constexpr int kPotrfThreads = 1024;
-constexpr int kWaves = kPotrfThreads / 64;
 constexpr int kBlk = 32;
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// value of v in lane l (l uniform), through the scalar registers
+__device__ inline double readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// diagonal block and the reciprocals of its diagonal (LDS); rows padded so that the staging
+// writes (one column per pass) spread over the banks and row reads stay 16-byte aligned
+__shared__ double D[kBlk][kBlk + 2];
+__shared__ double rdiag[kBlk];
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -34,9 +46,47 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Diagonal 32 x 32 block (in D) factored in place by one wave.  Lane i holds row i in
+// registers; for column j the pivot and the entries L(l, j) of the other rows are read
+// across lanes (readlane) and each lane applies the rank-1 update to its own row.
+__device__ inline double factor_diag_block(int lane, int cb, int *fail_col) {
+    // Opaque copy of the lane index: the per-column lane masks below are then formed where
+    // they are used instead of being hoisted out of the caller's loop.
+    asm volatile("" : "+v"(lane));
+    const int row = lane & (kBlk - 1);
+    double d[kBlk];
+#pragma unroll
+    for (int l = 0; l < kBlk; ++l) d[l] = D[row][l];
+    double diag = 1.0;
+    int bad = INT_MAX;
+#pragma unroll
+    for (int j = 0; j < kBlk; ++j) {
+        double pj = readlane(d[j], j);
+        if (!(pj > 0.0)) {                              // non-positive or NaN pivot
+            bad = min(bad, j);
+            pj = 1.0;
+        }
+        const double piv = sqrt(pj);
+        const double lij = (row == j) ? piv : d[j] / piv;
+        d[j] = lij;
+        if (row == j) diag = piv;
+#pragma unroll
+        for (int l = j + 1; l < kBlk; ++l) d[l] -= lij * readlane(lij, l);
+    }
+    if (lane == 0 && bad != INT_MAX && *fail_col == INT_MAX) *fail_col = cb + bad;
+    double ld = 0.0;
+    if (lane < kBlk) {
+#pragma unroll
+        for (int l = 0; l < kBlk; ++l) D[lane][l] = (l <= lane) ? d[l] : 0.0;
+        rdiag[lane] = 1.0 / diag;
+        ld = 2.0 * log(diag);
+    }
+    return ld;
+}
+
+template <int kPotrfThreads>
 __global__ __launch_bounds__(kPotrfThreads) void potrf_tile_kernel(PotrfArgs args) {
-    __shared__ double D[kBlk][kBlk + 1];
-    __shared__ double Dinv[kBlk][kBlk + 1];
+    constexpr int kWaves = kPotrfThreads / 64;
     __shared__ double rs[kMaxTile];
     __shared__ double red[2][kWaves];
     __shared__ int fail_col;
@@ -47,130 +97,140 @@ __global__ __launch_bounds__(kPotrfThreads) void potrf_tile_kernel(PotrfArgs arg
     const int wave = tid >> 6;
     double *A = args.a;
     double *B = args.linv;
+    float *B32 = args.linv32;
     if (tid == 0) fail_col = INT_MAX;
-    for (int64_t e = tid; e < (int64_t)nbp * nbp; e += kPotrfThreads) {
-        const int r = (int)(e % nbp), c = (int)(e / nbp);
-        B[e] = (r == c) ? 1.0 : 0.0;
-    }
     double logdet = 0.0;
     __syncthreads();
 
     for (int cb = 0; cb < nbp; cb += kBlk) {
         const int split = cb + kBlk;
-        // ---- 1. diagonal block, one wave ---------------------------------------------
-        if (wave == 0) {
-            for (int e = lane; e < kBlk * kBlk; e += 64) {
-                const int i = e % kBlk, j = e / kBlk;
-                D[i][j] = (i >= j) ? A[(cb + i) + (int64_t)(cb + j) * nbp] : 0.0;
-            }
-            wave_sync();
-            for (int j = 0; j < kBlk; ++j) {
-                double d = D[j][j];
-                if (!(d > 0.0)) {                       // non-positive or NaN pivot
-                    if (lane == 0 && fail_col == INT_MAX) fail_col = cb + j;
-                    d = 1.0;
-                }
-                const double piv = sqrt(d);
-                wave_sync();
-                if (lane == 0) D[j][j] = piv;
-                if (lane > j && lane < kBlk) D[lane][j] /= piv;
-                wave_sync();
-                for (int e = lane; e < kBlk * kBlk; e += 64) {
-                    const int i = e % kBlk, l = e / kBlk;
-                    if (l > j && i >= l) D[i][l] -= D[i][j] * D[l][j];
-                }
-                wave_sync();
-            }
-            if (lane < kBlk) {                          // column `lane` of Dinv
-                const int j = lane;
-                for (int i = 0; i < j; ++i) Dinv[i][j] = 0.0;
-                Dinv[j][j] = 1.0 / D[j][j];
-                for (int i = j + 1; i < kBlk; ++i) {
-                    double s = 0.0;
-                    for (int t = j; t < i; ++t) s += D[i][t] * Dinv[t][j];
-                    Dinv[i][j] = -s / D[i][i];
-                }
-                logdet += 2.0 * log(D[j][j]);
-            }
-            wave_sync();
-            for (int e = lane; e < kBlk * kBlk; e += 64) {
-                const int i = e % kBlk, j = e / kBlk;
-                if (i >= j) A[(cb + i) + (int64_t)(cb + j) * nbp] = D[i][j];
-            }
+        // ---- 1. diagonal block: staged in LDS by all threads, factored by one wave ------
+        for (int e = tid; e < kBlk * kBlk; e += kPotrfThreads) {
+            const int r = e & (kBlk - 1), c = e / kBlk;
+            D[r][c] = (r >= c) ? A[(cb + r) + (int64_t)(cb + c) * nbp] : 0.0;
         }
         __syncthreads();
+        if (wave == 0) logdet += factor_diag_block(lane, cb, &fail_col);
+        __syncthreads();
+        // L block back to the tile (the diagonal block is not touched by steps 2 and 3)
+        for (int e = tid; e < kBlk * kBlk; e += kPotrfThreads) {
+            const int r = e & (kBlk - 1), c = e / kBlk;
+            if (r >= c) A[(cb + r) + (int64_t)(cb + c) * nbp] = D[r][c];
+        }
         // ---- 2. block rows of B (columns t < split) and panel rows of A (t >= split) ------
-        // For 16 indices t at a time: out[t][l] = sum_q X[t][q] Dinv[l][q], where X[t][q] is
-        // B[cb + q][t] (t < split) or A[t][cb + q] (t >= split); two 16 x 16 MFMA blocks
-        // (l in 0..15 and 16..31), result register q of lane (16 g + r) = out[t0 + r][l0 + g + 4q].
-        {
-            const int lr = lane & 15, lg = lane >> 4;
-            for (int t0 = wave * 16; t0 < nbp; t0 += kWaves * 16) {
-                const bool isB = t0 < split;   // split is a multiple of 16
-                f64x4 o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
+        // Thread t solves D y = x: x[q] = B[cb + q][t] for t < cb, the unit vector e_(t - cb)
+        // inside the diagonal block, A[t][cb + q] for t >= split.  The compiler barrier per
+        // column keeps the broadcast reads of D from being issued all at once.
+        for (int t = tid; t < nbp; t += kPotrfThreads) {
+            const bool isB = t < split;
+            double y[kBlk];
+            if (t < cb) {
 #pragma unroll
-                for (int s = 0; s < kBlk / 4; ++s) {
-                    const int k = 4 * s + lg;
-                    const double xv = isB ? B[(cb + k) + (int64_t)(t0 + lr) * nbp]
-                                          : A[(t0 + lr) + (int64_t)(cb + k) * nbp];
-                    o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Dinv[lr][k], xv, o0, 0, 0, 0);
-                    o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Dinv[16 + lr][k], xv, o1, 0, 0, 0);
+                for (int q = 0; q < kBlk; ++q) y[q] = B[(cb + q) + (int64_t)t * nbp];
+            } else if (isB) {
+#pragma unroll
+                for (int q = 0; q < kBlk; ++q) y[q] = (q == t - cb) ? 1.0 : 0.0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < kBlk; ++q) y[q] = A[t + (int64_t)(cb + q) * nbp];
+            }
+#pragma unroll
+            for (int l = 0; l < kBlk; ++l) {
+                double s0 = y[l], s1 = 0.0;
+#pragma unroll
+                for (int q = 0; q + 1 < l; q += 2) {
+                    s0 -= D[l][q] * y[q];
+                    s1 -= D[l][q + 1] * y[q + 1];
                 }
+                if (l & 1) s0 -= D[l][l - 1] * y[l - 1];
+                y[l] = (s0 + s1) * rdiag[l];
+                asm volatile("" ::: "memory");
+            }
+            if (isB) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int t = t0 + lr;
-                    const int l0 = lg + 4 * q, l1 = 16 + lg + 4 * q;
-                    if (isB) {
-                        B[(cb + l0) + (int64_t)t * nbp] = o0[q];
-                        B[(cb + l1) + (int64_t)t * nbp] = o1[q];
-                    } else {
-                        A[t + (int64_t)(cb + l0) * nbp] = o0[q];
-                        A[t + (int64_t)(cb + l1) * nbp] = o1[q];
-                    }
+                for (int l = 0; l < kBlk; ++l) {
+                    B[(cb + l) + (int64_t)t * nbp] = y[l];
+                    B32[(cb + l) + (int64_t)t * nbp] = (float)y[l];
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < kBlk; ++l) {
+                    A[t + (int64_t)(cb + l) * nbp] = y[l];
+                    B[(cb + l) + (int64_t)t * nbp] = 0.0;
+                    B32[(cb + l) + (int64_t)t * nbp] = 0.0f;
                 }
             }
         }
         __syncthreads();
-        // ---- 3. rank-32 update of rows >= split on 16 x 16 MFMA blocks ----------------
+        // ---- 3. rank-32 update of rows >= split, 32 x 32 regions per wave item ----------
+        // Regions are numbered row strip by row strip (strip rb has a2 + rb + 1 of them, the
+        // last one on the diagonal, where the block above it is skipped) and dealt to the
+        // waves round-robin.  The products are accumulated from zero and subtracted once.
+        // B below the diagonal block (columns cb .. split-1) has not been written yet: its
+        // entries are those of the identity there, i.e. zero.
         const int rows = nbp - split;
         if (rows > 0) {
-            const int nrb = rows / 16;
-            const int a0 = split / 16;          // 16-column blocks of B left of row block 0
-            const int total = nrb * a0 + nrb * (nrb + 1) / 2;
+            const int nr2 = rows / 32;
+            const int a2 = split / 32;
             const int lr = lane & 15, lg = lane >> 4;
-            for (int w = wave; w < total; w += kWaves) {
-                int rb = (int)((-(2.0 * a0 + 1.0) + sqrt((2.0 * a0 + 1.0) * (2.0 * a0 + 1.0) + 8.0 * w)) * 0.5);
-                if (rb < 0) rb = 0;
-                while (rb > 0 && rb * a0 + rb * (rb + 1) / 2 > w) --rb;
-                while ((rb + 1) * a0 + (rb + 1) * (rb + 2) / 2 <= w) ++rb;
-                const int cbk = w - (rb * a0 + rb * (rb + 1) / 2);
-                const int i0 = split + rb * 16;
-                const int j0 = cbk * 16;
+            int rb = 0, cbk = wave;
+            while (rb < nr2 && cbk >= a2 + rb + 1) cbk -= a2 + ++rb;
+            while (rb < nr2) {
+                const int i0 = split + rb * 32, j0 = cbk * 32;
                 const bool inB = j0 < split;
+                const bool diag = j0 == i0;
+                const bool fresh = inB && j0 >= cb;
                 double *M = inB ? B : A;
-                // result register q of lane (16 g + r) is M[i0 + r][j0 + g + 4q]
-                f64x4 acc;
+                double rv[2][kBlk / 4], qv[2][kBlk / 4], cv[2][2][4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = M[(i0 + lr) + (int64_t)(j0 + lg + 4 * q) * nbp];
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int s = 0; s < kBlk / 4; ++s) {
-                    const int k = cb + 4 * s + lg;
-                    const double rv = A[(i0 + lr) + (int64_t)k * nbp];
-                    const double qv = inB ? B[k + (int64_t)(j0 + lr) * nbp] : A[(j0 + lr) + (int64_t)k * nbp];
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-qv, rv, acc, 0, 0, 0);
-                }
+                    for (int st = 0; st < kBlk / 4; ++st) {
+                        const int k = cb + 4 * st + lg;
+                        rv[h][st] = A[(i0 + 16 * h + lr) + (int64_t)k * nbp];
+                        qv[h][st] = inB ? B[k + (int64_t)(j0 + 16 * h + lr) * nbp]
+                                        : A[(j0 + 16 * h + lr) + (int64_t)k * nbp];
+                    }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = i0 + lr, j = j0 + lg + 4 * q;
-                    if (inB || j <= i) M[i + (int64_t)j * nbp] = acc[q];
-                }
+                for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+                    for (int hj = 0; hj < 2; ++hj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            cv[hi][hj][q] = ((diag && hj > hi) || fresh) ? 0.0
+                                : M[(i0 + 16 * hi + lr) + (int64_t)(j0 + 16 * hj + lg + 4 * q) * nbp];
+                f64x4 acc[2][2];
+#pragma unroll
+                for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+                    for (int hj = 0; hj < 2; ++hj) acc[hi][hj] = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int st = 0; st < kBlk / 4; ++st)
+#pragma unroll
+                    for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+                        for (int hj = 0; hj < 2; ++hj)
+                            if (!(diag && hj > hi))
+                                acc[hi][hj] = __builtin_amdgcn_mfma_f64_16x16x4f64(qv[hj][st], rv[hi][st], acc[hi][hj], 0, 0, 0);
+#pragma unroll
+                for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+                    for (int hj = 0; hj < 2; ++hj) {
+                        if (diag && hj > hi) continue;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int i = i0 + 16 * hi + lr, j = j0 + 16 * hj + lg + 4 * q;
+                            if (!diag || j <= i) M[i + (int64_t)j * nbp] = cv[hi][hj][q] - acc[hi][hj][q];
+                        }
+                    }
+                cbk += kWaves;
+                while (rb < nr2 && cbk >= a2 + rb + 1) cbk -= a2 + ++rb;
             }
         }
         __syncthreads();
     }
 
-    // ---- FP32 copy of the inverse, forward-solve block, reductions ---------------------
-    for (int64_t e = tid; e < (int64_t)nbp * nbp; e += kPotrfThreads) args.linv32[e] = (float)B[e];
+    // ---- forward-solve block, reductions ------------------------------------------------
     for (int t = tid; t < nbp; t += kPotrfThreads) rs[t] = args.r[t];
     __syncthreads();
     double quad = 0.0;
@@ -205,8 +265,11 @@ __global__ __launch_bounds__(kPotrfThreads) void potrf_tile_kernel(PotrfArgs arg
 
 }  // namespace
 
-void launch_potrf(const PotrfArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(potrf_tile_kernel, dim3(1), dim3(kPotrfThreads), 0, stream, a);
+template <int T>
+void launch_potrf_threads(const PotrfArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL((potrf_tile_kernel<T>), dim3(1), dim3(T), 0, stream, a);
 }
+
+void launch_potrf(const PotrfArgs &a, hipStream_t stream) { launch_potrf_threads<512>(a, stream); }
 
 }  // namespace mpgeo

@@ -36,15 +36,21 @@ __global__ __launch_bounds__(256) void panel_solve_kernel(TileMap map, int k, co
     r[(int64_t)i * nbp + row] -= s;
 }
 
+// eq. (2) from the per-tile parts; with `profile` the tiles held the correlation matrix and
+// eq. (2) is taken at its maximising variance q~/n (the profile likelihood).
 __global__ void finalize_kernel(const double *logdet_part, const double *quad_part, int p,
-                                int64_t n, double *result) {
+                                int64_t n, int profile, double *result) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double logdet = 0.0, quad = 0.0;
     for (int k = 0; k < p; ++k) {
         logdet += logdet_part[k];
         quad += quad_part[k];
     }
-    result[0] = -0.5 * (double)n * kLog2Pi - 0.5 * logdet - 0.5 * quad;
+    const double dn = (double)n;
+    if (profile)
+        result[0] = -0.5 * dn * (kLog2Pi + 1.0) - 0.5 * dn * log(quad / dn) - 0.5 * logdet;
+    else
+        result[0] = -0.5 * dn * kLog2Pi - 0.5 * logdet - 0.5 * quad;
     result[1] = logdet;
     result[2] = quad;
 }
@@ -123,8 +129,9 @@ __global__ __launch_bounds__(256) void multi_update_kernel(TileMap map, int k, c
     c[(int64_t)i * nbp + row + j * ldc] -= s;
 }
 
+// var_j = scale * (sigma2 - |c_j|^2)
 __global__ void column_var_kernel(const double *c, int64_t ldc, int64_t rows, int64_t m,
-                                  double sigma2, double *var) {
+                                  double sigma2, double scale, double *var) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     double s = 0.0;
@@ -132,7 +139,7 @@ __global__ void column_var_kernel(const double *c, int64_t ldc, int64_t rows, in
         const double v = c[r + j * ldc];
         s += v * v;
     }
-    var[j] = sigma2 - s;
+    var[j] = scale * (sigma2 - s);
 }
 
 // z_i = sum_{j <= i} L_ij eps_j: one workgroup per (tile row i, 256-row block).
@@ -189,9 +196,9 @@ void launch_panel_solve(const TileMap &map, int k, const double *p64, const doub
 }
 
 void launch_finalize(const double *logdet_part, const double *quad_part, int p, int64_t n,
-                     double *result, hipStream_t stream) {
+                     bool profile, double *result, hipStream_t stream) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, stream, logdet_part, quad_part, p, n,
-                       result);
+                       profile ? 1 : 0, result);
 }
 
 // t (physical, p*nbp) holds y on entry and is consumed; w (physical) receives L^-T y.
@@ -227,10 +234,10 @@ void launch_forward_multi(const TileMap &map, const double *linv_all, double *c,
 }
 
 void launch_column_var(const double *c, int64_t ldc, int64_t rows, int64_t m, double sigma2,
-                       double *var, hipStream_t stream) {
+                       double scale, double *var, hipStream_t stream) {
     if (m == 0) return;
     hipLaunchKernelGGL(column_var_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, c,
-                       ldc, rows, m, sigma2, var);
+                       ldc, rows, m, sigma2, scale, var);
 }
 
 }  // namespace mpgeo

@@ -347,3 +347,52 @@ def test_three_tier_plan_validation(lib, small_ds):
         with pytest.raises(lib.MpgeoError) as e:
             small_ds.loglik(SMALL.theta, SMALL.tile, 2, band32=band32, lowp=lowp)
         assert e.value.status == lib.MPGEO_E_ARG
+
+
+# ---- profile likelihood in (theta2, theta3) ---------------------------------------------------
+@pytest.mark.parametrize("band,tol", [(-1, 1e-10), (2, 1e-5)])
+@pytest.mark.parametrize("theta", [SMALL.theta, (0.7, 0.13, 0.62)])
+def test_profile_likelihood_matches_oracle(small_ds, theta, band, tol):
+    locs, z = small_case()
+    want = oracle.profile_loglik(locs, z, theta[1], theta[2])
+    got = small_ds.loglik(theta, SMALL.tile, band, profile=True)   # theta1 is ignored
+    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), len(z)) <= tol
+    assert rel(got["quad"], want["quad"]) <= (1e-10 if band < 0 else 1e-4)
+    # eq. (2) through the library at the variance estimate q/n equals the profile value
+    full = small_ds.loglik((got["quad"] / len(z), theta[1], theta[2]), SMALL.tile, band)
+    assert abs(full["loglik"] - got["loglik"]) / max(abs(got["loglik"]), len(z)) <= tol
+
+
+def test_profile_kriging_uses_the_variance_estimate(lib, ctx):
+    locs = jittered_grid(20, 61)
+    theta = (1.4, 0.1, 0.5)
+    z = oracle.simulate_field(locs, theta, normals(len(locs), 62))
+    new = np.random.default_rng(63).uniform(0, 1, size=(25, 2))
+    ds = lib.Dataset(ctx, locs, z)
+    r = ds.loglik(theta, 80, -1, profile=True)
+    s2 = r["quad"] / len(z)
+    pred, var = ds.krige(new, variance=True)
+    ds.close()
+    want = oracle.krige(locs, z, (s2, theta[1], theta[2]), new)
+    assert np.max(np.abs(pred - want["pred"])) <= 1e-9 * np.max(np.abs(want["pred"]))
+    assert np.max(np.abs(var - want["var"])) <= 1e-9 * s2
+
+
+@pytest.mark.parametrize("band", [2, -1])
+def test_profile_mle_matches_oracle(lib, small_ds, band):
+    gold = json.load(open(os.path.join(HERE, "golden", "mle_profile_small.json")))
+    start = [min(max(t * s, lo), hi) for t, s, lo, hi in
+             zip(SMALL.theta, oracle.mle.START_SCALE, oracle.mle.LOWER, oracle.mle.UPPER)]
+    fit = small_ds.mle(start, SMALL.tile, band, profile=True)
+    for got, want in zip(fit["theta"], gold["theta_hat"]):
+        assert abs(got - want) / abs(want) <= 1e-3, (fit, gold)
+
+
+def test_profile_rejected_where_it_has_no_meaning(lib, small_ds):
+    # a field draw needs the variance: simulate refuses the profile flag
+    eps = np.zeros(small_ds.n)
+    out = np.zeros(small_ds.n)
+    st = lib.LIB.mpgeo_dataset_simulate(small_ds.handle, lib.Theta(*SMALL.theta),
+                                        lib.make_plan(SMALL.tile, 2, lib.MPGEO_PROFILE),
+                                        eps.ctypes.data, out.ctypes.data)
+    assert st == lib.MPGEO_E_ARG
