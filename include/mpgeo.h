@@ -27,7 +27,8 @@
  *    destroy.  Pointer arguments are host memory unless MPGEO_INPUT_DEVICE is set in the
  *    flags of the call (or of the dataset), in which case they are device pointers on
  *    the context's device (for example torch's tensor.data_ptr()).
- *  - Layout: locations are n x 2 row-major float64 (x, y); vectors are float64.
+ *  - Layout: locations are n x 2 row-major float64 (x, y), or (longitude, latitude) in
+ *    degrees with MPGEO_DIST_GCD; vectors are float64.
  *  - Ordering: all calls are ordered on the context's HIP stream and are synchronous at
  *    return (results filled in).  A context is used by one host thread at a time.
  *  - Errors: on a non-OK return the outputs are undefined except mpgeo_result.info.
@@ -71,6 +72,13 @@ typedef enum {
  * its trailing terms garbled; this is the form the substitution gives.  The variance
  * estimate is q~/n.  Kriging after such an evaluation uses theta1 = q~/n. */
 #define MPGEO_PROFILE      8u
+/* Great-circle distance (Section IV-B: for large regions): locations are (longitude,
+ * latitude) in degrees and r in eq. (1) is the great-circle distance in km on a sphere of
+ * radius 6371 km (the mean Earth radius), by the haversine formula
+ *   a = sin^2(dlat/2) + cos(lat1) cos(lat2) sin^2(dlon/2),  r = 2 R asin(sqrt(min(a, 1))).
+ * The Z-order key is then taken of ((lon + 180)/360, (lat + 90)/180).  A dataset flag (and
+ * a one-shot plan flag); kriging sites use the same convention. */
+#define MPGEO_DIST_GCD    16u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
  * (smoothness); all must be finite and > 0. */
@@ -86,7 +94,8 @@ typedef struct {
  *  band32: c >= 0: FP32 operands for band64 < i - j <= band64 + c, 16-bit operands beyond;
  *          -1: FP32 from band64 + 1 to the edge of the matrix (two tiers).
  *  lowp:   0 with band32 = -1; 1 (FP16) or 2 (BF16) with band32 >= 0.
- *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING | MPGEO_PROFILE. */
+ *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING | MPGEO_PROFILE |
+ *          MPGEO_DIST_GCD. */
 typedef struct {
     int32_t tile;
     int32_t band64;

@@ -16,14 +16,15 @@ from .likelihood import cholesky_lower
 from .matern import cross_distances, matern, matern_matrix
 
 
-def krige(locs: np.ndarray, z: np.ndarray, theta, new_locs: np.ndarray) -> dict:
+def krige(locs: np.ndarray, z: np.ndarray, theta, new_locs: np.ndarray,
+          metric: str = "euclidean") -> dict:
     """Predictions and variances at new_locs (m x 2) from data z at locs (n x 2)."""
     sigma2, beta, nu = theta
-    low = cholesky_lower(matern_matrix(locs, theta))
+    low = cholesky_lower(matern_matrix(locs, theta, metric))
     y = sla.solve_triangular(low, np.asarray(z, dtype=np.float64), lower=True)
     w = sla.solve_triangular(low.T, y, lower=False)          # Sigma^-1 Z
     c = matern(cross_distances(np.asarray(new_locs, dtype=np.float64),
-                               np.asarray(locs, dtype=np.float64)), sigma2, beta, nu)
+                               np.asarray(locs, dtype=np.float64), metric), sigma2, beta, nu)
     pred = c @ w
     v = sla.solve_triangular(low, c.T, lower=True)           # L^-1 Sigma(S, s0)
     var = sigma2 - np.sum(v * v, axis=0)

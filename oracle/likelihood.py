@@ -48,16 +48,16 @@ def loglik_parts(a: np.ndarray, z: np.ndarray) -> dict:
     }
 
 
-def loglik(locs: np.ndarray, z: np.ndarray, theta) -> dict:
+def loglik(locs: np.ndarray, z: np.ndarray, theta, metric: str = "euclidean") -> dict:
     """Eq. (2) at theta for locations locs (n x 2) and data z (n)."""
-    return loglik_parts(matern_matrix(locs, theta), z)
+    return loglik_parts(matern_matrix(locs, theta, metric), z)
 
 
-def simulate_field(locs: np.ndarray, theta, eps: np.ndarray) -> np.ndarray:
+def simulate_field(locs: np.ndarray, theta, eps: np.ndarray, metric: str = "euclidean") -> np.ndarray:
     """A draw of the zero-mean Matérn field at locs: z = L eps with Sigma(theta) = L L^T.
 
     This is how synthetic measurements are produced from a parameter vector
     theta_0 (Section VIII-B.1): the standard normal vector eps is an input.
     """
-    low = cholesky_lower(matern_matrix(locs, theta))
+    low = cholesky_lower(matern_matrix(locs, theta, metric))
     return low @ np.asarray(eps, dtype=np.float64)

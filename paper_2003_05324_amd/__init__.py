@@ -24,6 +24,7 @@ MPGEO_ORDER_MORTON = 1
 MPGEO_INPUT_DEVICE = 2
 MPGEO_TIMING = 4
 MPGEO_PROFILE = 8
+MPGEO_DIST_GCD = 16
 
 EXPORTED = (
     "mpgeo_ctx_create", "mpgeo_ctx_destroy", "mpgeo_ctx_kernel_stats", "mpgeo_ctx_reset_stats",
@@ -167,14 +168,15 @@ class Context:
 
     def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
                morton: bool = True, timing: bool = False, band32: int = -1, lowp=None,
-               profile: bool = False) -> dict:
+               profile: bool = False, gcd: bool = False) -> dict:
         """One-shot eq. (2) (or the profile likelihood): ordering, covariance tiles, factor,
         solve, reduction."""
         dev = isinstance(locs, torch.Tensor)
         if not dev:
             locs, z = _host_f64(locs), _host_f64(z)
         flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0) | \
-                (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0)
+                (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0) | \
+                (MPGEO_DIST_GCD if gcd else 0)
         res = Result()
         st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
                               make_plan(tile, band64, flags, band32, lowp), ctypes.byref(res))
@@ -208,7 +210,9 @@ class Context:
 class Dataset:
     """Locations and data resident on the device, Morton-ordered once."""
 
-    def __init__(self, ctx: Context, locs, z=None, morton: bool = True):
+    def __init__(self, ctx: Context, locs, z=None, morton: bool = True, gcd: bool = False):
+        """gcd=True: locations are (longitude, latitude) in degrees and distances are
+        great-circle distances in km."""
         self.ctx = ctx
         dev = isinstance(locs, torch.Tensor)
         if not dev:
@@ -216,7 +220,8 @@ class Dataset:
             z = None if z is None else _host_f64(z)
         self.device_io = dev
         self.n = int(locs.shape[0])
-        flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0)
+        flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0) | \
+                (MPGEO_DIST_GCD if gcd else 0)
         handle = ctypes.c_void_p()
         _check(LIB.mpgeo_dataset_create(ctx.handle, self.n, _ptr(locs), _ptr(z), flags,
                                         ctypes.byref(handle)), "mpgeo_dataset_create")

@@ -392,7 +392,7 @@ int load_inputs(mpgeo_dataset *ds, const double *locs, const double *z, uint32_t
         while (n2 < n) n2 *= 2;
         MPGEO_TRY(ds->keys.ensure((size_t)n2 * sizeof(uint64_t)));
         ctx->timed(kStatOrder, 0.0, (double)n * 40.0, [&] {
-            launch_morton_order(dl, dz, n, ds->keys.as<uint64_t>(), n2, ds->locs.as<double>(),
+            launch_morton_order(dl, dz, n, (flags & MPGEO_DIST_GCD) != 0, ds->keys.as<uint64_t>(), n2, ds->locs.as<double>(),
                                 dz ? ds->z.as<double>() : nullptr, ds->perm.as<int64_t>(), s);
         });
         MPGEO_HIP(hipGetLastError());
@@ -415,7 +415,8 @@ int load_inputs(mpgeo_dataset *ds, const double *locs, const double *z, uint32_t
 int run_covgen(mpgeo_dataset *ds, const mpgeo_theta &th) {
     mpgeo_ctx *ctx = ds->ctx;
     const Layout &L = ds->layout;
-    const MaternParams mp = make_matern_params(th.sigma2, th.beta, th.nu);
+    MaternParams mp = make_matern_params(th.sigma2, th.beta, th.nu);
+    mp.gcd = (ds->flags & MPGEO_DIST_GCD) ? 1 : 0;
     const TileMap map = tile_map(ds);
     const double evals = (double)L.n * (L.n + 1) / 2.0;
     const double bytes = (double)L.n64 * L.nb * L.nb * 8.0 + (double)L.n32 * L.nb * L.nb * 4.0;
@@ -889,7 +890,8 @@ int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs, do
     double *dvar = dpred + m;
     if (on_dev) MPGEO_HIP(hipMemcpyAsync(dnew, new_locs, (size_t)m * 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
     else MPGEO_HIP(hipMemcpyAsync(dnew, new_locs, (size_t)m * 2 * sizeof(double), hipMemcpyHostToDevice, s));
-    const MaternParams mp = make_matern_params(ds->theta.sigma2, ds->theta.beta, ds->theta.nu);
+    MaternParams mp = make_matern_params(ds->theta.sigma2, ds->theta.beta, ds->theta.nu);
+    mp.gcd = (ds->flags & MPGEO_DIST_GCD) ? 1 : 0;
     launch_krige_predict(ds->locs.as<double>(), L.n, L.nb, L.nbp, dnew, m, w, mp, dpred, s);
     MPGEO_HIP(hipGetLastError());
     if (var) {

@@ -52,7 +52,11 @@ struct MaternParams {
     int nl;        // nu = mu + nl with mu in [-1/2, 1/2)
     double mu;
     int mode;      // 0 general nu, 1: nu = 1/2, 2: nu = 3/2, 3: nu = 5/2
+    int gcd;       // 0: Euclidean distance; 1: great-circle distance of (lon, lat) in degrees
 };
+
+// Sphere radius of the great-circle distance (mean Earth radius, km).
+constexpr double kEarthRadiusKm = 6371.0;
 MaternParams make_matern_params(double sigma2, double beta, double nu);
 
 void launch_covgen(const TileMap &map, const double *locs, const TileIJ *tiles,
@@ -77,7 +81,7 @@ void launch_unpad_vector(const double *src, double *dst, int64_t n, int nb, int 
                          hipStream_t stream);
 
 // Z-order keys, sort, and gather of locations and data.
-void launch_morton_order(const double *locs_in, const double *z_in, int64_t n,
+void launch_morton_order(const double *locs_in, const double *z_in, int64_t n, bool lonlat,
                          uint64_t *keys, int64_t n2, double *locs_out, double *z_out,
                          int64_t *perm_out, hipStream_t stream);
 

@@ -129,7 +129,7 @@ __device__ inline double matern_cov(double r, const MaternParams &mp) {
 }
 
 MaternParams make_matern_params(double sigma2, double beta, double nu) {
-    MaternParams mp;
+    MaternParams mp{};
     mp.sigma2 = sigma2;
     mp.beta = beta;
     mp.nu = nu;
@@ -141,6 +141,29 @@ MaternParams make_matern_params(double sigma2, double beta, double nu) {
 }
 
 namespace {
+
+constexpr double kDegToRad = 3.14159265358979323846 / 180.0;
+
+// Great-circle distance by the haversine formula, from latitudes in radians (with their
+// cosines) and the longitude difference in degrees:
+//   a = sin^2(dlat / 2) + cos(lat1) cos(lat2) sin^2(dlon / 2),  d = 2 R asin(sqrt(min(a, 1))).
+__device__ inline double haversine(double dlon_deg, double lat1, double cos1, double lat2, double cos2) {
+    const double sp = sin(0.5 * (lat2 - lat1));
+    const double sl = sin(0.5 * (dlon_deg * kDegToRad));
+    double a = sp * sp + (cos1 * cos2) * (sl * sl);
+    a = a < 1.0 ? a : 1.0;
+    return 2.0 * kEarthRadiusKm * asin(sqrt(a));
+}
+
+// Distance between two sites: Euclidean, or great-circle for (lon, lat) in degrees.
+__device__ inline double site_distance(double x1, double y1, double x2, double y2, int gcd) {
+    if (gcd) {
+        const double p1 = y1 * kDegToRad, p2 = y2 * kDegToRad;
+        return haversine(x2 - x1, p1, cos(p1), p2, cos(p2));
+    }
+    const double dx = x1 - x2, dy = y1 - y2;
+    return sqrt(dx * dx + dy * dy);
+}
 
 constexpr int kCovCols = 32;   // tile columns per workgroup
 constexpr int kCovThreads = 256;
@@ -182,26 +205,35 @@ __global__ __launch_bounds__(kCovThreads) void fill_tiles_kernel(TileMap map, co
 struct MaternSource {
     const double *locs;
     MaternParams mp;
-    double xr, yr;
-    double *sx, *sy;   // shared column coordinates
+    double xr, yr, cr;          // row site: x, y (great-circle: lon in degrees, lat in radians, cos lat)
+    double *sx, *sy, *sc;       // shared column sites, same convention
     __device__ void prepare_cols(const TileIJ &, int, const int64_t *gcol) {
-        __shared__ double cx[kCovCols], cy[kCovCols];
+        __shared__ double cx[kCovCols], cy[kCovCols], ccs[kCovCols];
         sx = cx;
         sy = cy;
+        sc = ccs;
         if (threadIdx.x < kCovCols) {
             const int64_t g = gcol[threadIdx.x];
-            cx[threadIdx.x] = g >= 0 ? locs[2 * g] : 0.0;
-            cy[threadIdx.x] = g >= 0 ? locs[2 * g + 1] : 0.0;
+            const double x = g >= 0 ? locs[2 * g] : 0.0;
+            const double y = g >= 0 ? locs[2 * g + 1] : 0.0;
+            cx[threadIdx.x] = x;
+            cy[threadIdx.x] = mp.gcd ? y * kDegToRad : y;
+            ccs[threadIdx.x] = mp.gcd ? cos(y * kDegToRad) : 0.0;
         }
     }
     __device__ void prepare_row(int64_t gr) {
         if (gr >= 0) {
             xr = locs[2 * gr];
             yr = locs[2 * gr + 1];
+            if (mp.gcd) {
+                yr *= kDegToRad;
+                cr = cos(yr);
+            }
         }
     }
     __device__ double value(int64_t gr, int cc, int64_t gc) const {
         if (gr == gc) return mp.sigma2;
+        if (mp.gcd) return matern_cov(haversine(sx[cc] - xr, yr, cr, sy[cc], sc[cc]), mp);
         const double dx = xr - sx[cc];
         const double dy = yr - sy[cc];
         return matern_cov(sqrt(dx * dx + dy * dy), mp);
@@ -296,11 +328,7 @@ __global__ __launch_bounds__(kKrigeThreads) void krige_predict_kernel(
         }
         __syncthreads();
         const int cnt = (int)((n - a0) < kKrigeChunk ? (n - a0) : kKrigeChunk);
-        for (int q = 0; q < cnt; ++q) {
-            const double dx = x0 - sx[q];
-            const double dy = y0 - sy[q];
-            acc += matern_cov(sqrt(dx * dx + dy * dy), mp) * sw[q];
-        }
+        for (int q = 0; q < cnt; ++q) acc += matern_cov(site_distance(x0, y0, sx[q], sy[q], mp.gcd), mp) * sw[q];
         __syncthreads();
     }
     if (j < m) pred[j] = acc;
@@ -317,11 +345,8 @@ __global__ void cross_cov_kernel(const double *locs, int64_t n, int nb, int nbp,
     const int r = (int)(e - ti * nbp);
     const int64_t a = ti * nb + r;
     double v = 0.0;
-    if (r < nb && a < n) {
-        const double dx = new_locs[2 * j] - locs[2 * a];
-        const double dy = new_locs[2 * j + 1] - locs[2 * a + 1];
-        v = matern_cov(sqrt(dx * dx + dy * dy), mp);
-    }
+    if (r < nb && a < n)
+        v = matern_cov(site_distance(new_locs[2 * j], new_locs[2 * j + 1], locs[2 * a], locs[2 * a + 1], mp.gcd), mp);
     c[e + j * ldc] = v;
 }
 
@@ -330,7 +355,7 @@ __global__ void cross_cov_kernel(const double *locs, int64_t n, int nb, int nbp,
 void launch_covgen(const TileMap &map, const double *locs, const TileIJ *tiles, int64_t ntiles,
                    const MaternParams &mp, hipStream_t stream) {
     if (ntiles == 0) return;
-    MaternSource src{locs, mp, 0.0, 0.0, nullptr, nullptr};
+    MaternSource src{locs, mp, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr};
     dim3 grid((unsigned)ntiles, map.nbp / kCovCols);
     hipLaunchKernelGGL(fill_tiles_kernel<MaternSource>, grid, dim3(kCovThreads), 0, stream, map,
                        tiles, src);

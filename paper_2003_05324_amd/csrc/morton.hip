@@ -2,7 +2,8 @@
 //
 // Key of a point: each coordinate clamped to [0, 1] and quantised to 16 bits,
 // q = min(floor(c * 2^16), 2^16 - 1); the bits of q_x go to the even positions and those
-// of q_y to the odd positions of a 32-bit key.  Sorting the 64-bit values
+// of q_y to the odd positions of a 32-bit key; (longitude, latitude) points in degrees are
+// first mapped to ((lon + 180) / 360, (lat + 90) / 180).  Sorting the 64-bit values
 // (key << 32) | index ascending gives the stable order by key (ties keep input order).
 // The sort is a bitonic network over the padded power-of-two array: stages whose
 // partner distance fits in a workgroup run in LDS, the others as global passes.
@@ -30,14 +31,20 @@ __device__ inline uint32_t quantise(double c) {
     return q > 65535.0 ? 65535u : (uint32_t)q;
 }
 
-__global__ void morton_keys_kernel(const double *locs, int64_t n, int64_t n2, uint64_t *keys) {
+__global__ void morton_keys_kernel(const double *locs, int64_t n, int64_t n2, int lonlat,
+                                   uint64_t *keys) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n2) return;
     if (e >= n) {
         keys[e] = ~0ull;
         return;
     }
-    const uint32_t key = spread_bits(quantise(locs[2 * e])) | (spread_bits(quantise(locs[2 * e + 1])) << 1);
+    double x = locs[2 * e], y = locs[2 * e + 1];
+    if (lonlat) {
+        x = (x + 180.0) / 360.0;
+        y = (y + 90.0) / 180.0;
+    }
+    const uint32_t key = spread_bits(quantise(x)) | (spread_bits(quantise(y)) << 1);
     keys[e] = ((uint64_t)key << 32) | (uint64_t)e;
 }
 
@@ -98,11 +105,12 @@ __global__ void gather_kernel(const double *locs_in, const double *z_in, const u
 }  // namespace
 
 // n2 must be a power of two >= max(n, kSortLocal); keys has n2 entries.
-void launch_morton_order(const double *locs_in, const double *z_in, int64_t n, uint64_t *keys,
-                         int64_t n2, double *locs_out, double *z_out, int64_t *perm_out,
-                         hipStream_t stream) {
+void launch_morton_order(const double *locs_in, const double *z_in, int64_t n, bool lonlat,
+                         uint64_t *keys, int64_t n2, double *locs_out, double *z_out,
+                         int64_t *perm_out, hipStream_t stream) {
     const unsigned kb = (unsigned)((n2 + 255) / 256);
-    hipLaunchKernelGGL(morton_keys_kernel, dim3(kb), dim3(256), 0, stream, locs_in, n, n2, keys);
+    hipLaunchKernelGGL(morton_keys_kernel, dim3(kb), dim3(256), 0, stream, locs_in, n, n2,
+                       lonlat ? 1 : 0, keys);
     const unsigned lb = (unsigned)(n2 / kSortLocal);
     hipLaunchKernelGGL(bitonic_local_kernel, dim3(lb), dim3(kSortThreads), 0, stream, keys,
                        (int64_t)0);

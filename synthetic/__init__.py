@@ -34,6 +34,16 @@ def jittered_grid(m: int, seed: int, jitter: float = JITTER) -> np.ndarray:
     return locs
 
 
+def lonlat_grid(m: int, seed: int, lon=(35.0, 55.0), lat=(12.0, 32.0)) -> np.ndarray:
+    """m*m (longitude, latitude) points in degrees: the jittered grid mapped onto a
+    lon x lat box (a large region, where distances are great-circle distances)."""
+    g = jittered_grid(m, seed)
+    out = np.empty_like(g)
+    out[:, 0] = lon[0] + (lon[1] - lon[0]) * g[:, 0]
+    out[:, 1] = lat[0] + (lat[1] - lat[0]) * g[:, 1]
+    return out
+
+
 def line_grid(n: int, h: float) -> np.ndarray:
     """n points (i*h, 0) on a regular 1-D grid, as an n x 2 array."""
     locs = np.zeros((n, 2), dtype=np.float64)

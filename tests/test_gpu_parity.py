@@ -18,7 +18,7 @@ import pytest
 import scipy.linalg as sla
 
 import oracle
-from synthetic import SMALL, jittered_grid, line_grid, normals, perturbed_thetas
+from synthetic import SMALL, jittered_grid, line_grid, lonlat_grid, normals, perturbed_thetas
 
 pytestmark = pytest.mark.gpu
 
@@ -396,3 +396,51 @@ def test_profile_rejected_where_it_has_no_meaning(lib, small_ds):
                                         lib.make_plan(SMALL.tile, 2, lib.MPGEO_PROFILE),
                                         eps.ctypes.data, out.ctypes.data)
     assert st == lib.MPGEO_E_ARG
+
+
+# ---- great-circle distance ((lon, lat) in degrees) -----------------------------------------
+GCD_THETA = (1.0, 150.0, 0.5)     # range 150 km on a 20 x 20 degree box (~2,000 km)
+
+
+@functools.lru_cache(maxsize=None)
+def gcd_case(m=30, seed=71):
+    locs = lonlat_grid(m, seed)
+    z = oracle.simulate_field(locs, GCD_THETA, normals(len(locs), seed + 1), "gcd")
+    return locs, z
+
+
+def test_gcd_morton_permutation_is_bit_exact(lib, ctx):
+    locs, z = gcd_case()
+    ds = lib.Dataset(ctx, locs, z, gcd=True)
+    assert np.array_equal(ds.perm(), oracle.morton_order(locs, "gcd"))
+    ds.close()
+
+
+@pytest.mark.parametrize("theta", [GCD_THETA, (1.3, 90.0, 1.1)])
+def test_gcd_covariance_entries(lib, ctx, theta):
+    locs, z = gcd_case()
+    ds = lib.Dataset(ctx, locs, z, gcd=True)
+    got = ds.covariance(theta, 128, -1)
+    perm = ds.perm()
+    ds.close()
+    want = oracle.matern_matrix(locs[perm], theta, "gcd")
+    low = np.tril_indices(len(z))
+    tol = 1e-13 if theta[2] == 0.5 else 5e-13
+    np.testing.assert_allclose(got[low], want[low], rtol=tol, atol=0)
+
+
+@pytest.mark.parametrize("band,tol", [(-1, 1e-10), (1, 1e-5)])
+def test_gcd_loglik_and_kriging_match_oracle(lib, ctx, band, tol):
+    locs, z = gcd_case()
+    want = oracle.loglik(locs, z, GCD_THETA, "gcd")
+    got = ctx.loglik(locs, z, GCD_THETA, 128, band, gcd=True)
+    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), len(z)) <= tol
+    new = lonlat_grid(6, 77)
+    kr = oracle.krige(locs, z, GCD_THETA, new, "gcd")
+    ds = lib.Dataset(ctx, locs, z, gcd=True)
+    ds.loglik(GCD_THETA, 128, band)
+    pred, var = ds.krige(new, variance=True)
+    ds.close()
+    ktol = 1e-9 if band < 0 else 1e-4
+    assert np.max(np.abs(pred - kr["pred"])) <= ktol * np.max(np.abs(kr["pred"]))
+    assert np.max(np.abs(var - kr["var"])) <= ktol * GCD_THETA[0]
