@@ -117,6 +117,9 @@ def parse():
     ap.add_argument("--cpu-sample-m", type=int, default=110)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--heldout", type=int, default=2000, help="kriging sites (0: skip)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline: the n = 40,000 band sweep (6 fields x bands "
+                         "0, 1, 4, 16, all), one JSON line")
     return ap.parse_args()
 
 
@@ -188,8 +191,59 @@ def cpu_baseline(m_sample, n_full, theta):
     }
 
 
+def band_sweep(args):
+    """n = 40,000 band sweep: sigma2 = 1, beta in {0.03, 0.1, 0.3} x nu in {0.5, 1.0}, each field
+    drawn by the library's FP64 sampler; for every FP64 band b the log-likelihood at the true
+    theta, its error against the all-FP64 path, SPD failures and the factor rate."""
+    import torch
+
+    import paper_2003_05324_amd as mp
+    from synthetic import SWEEP
+    ctx = mp.Context(0)
+    dev = torch.device("cuda:0")
+    rows = []
+    for w in SWEEP:
+        locs = torch.from_numpy(w.locations()).to(dev)
+        gen = mp.Dataset(ctx, locs, None)
+        z = gen.simulate(w.theta, torch.from_numpy(w.eps()).to(dev), w.tile, -1)
+        gen.close()
+        ds = mp.Dataset(ctx, locs, z)
+        ref = None
+        for band in sorted(w.bands, key=lambda b: (b < 0, b), reverse=True):   # all-FP64 first
+            st, _ = ds.try_loglik(w.theta, w.tile, band)                       # warm-up
+            times, res = [], None
+            if st == 0:
+                for _ in range(args.steps):
+                    res = ds.loglik(w.theta, w.tile, band, timing=False)
+                    times.append(res["t_factor"])
+            row = {"field": w.name, "beta": w.theta[1], "nu": w.theta[2], "band64": band,
+                   "status": mp.status_string(st)}
+            if res is not None:
+                t = statistics.median(times)
+                row.update({"loglik": res["loglik"], "logdet": res["logdet"], "quad": res["quad"],
+                            "t_factor_s": t, "cholesky_tflops": w.n ** 3 / 3.0 / t / 1e12})
+                if band < 0:
+                    ref = res
+                elif ref is not None:
+                    row["dloglik_rel"] = abs(res["loglik"] - ref["loglik"]) / max(abs(ref["loglik"]), w.n)
+                    row["dlogdet_rel"] = abs(res["logdet"] - ref["logdet"]) / abs(ref["logdet"])
+                    row["dquad_rel"] = abs(res["quad"] - ref["quad"]) / ref["quad"]
+            rows.append(row)
+            print(f"[sweep] {row}", file=sys.stderr, flush=True)
+        ds.close()
+    for r in rows:
+        base = next(x for x in rows if x["field"] == r["field"] and x["band64"] < 0)
+        if "t_factor_s" in r and "t_factor_s" in base:
+            r["speedup_vs_fp64"] = base["t_factor_s"] / r["t_factor_s"]
+    ctx.close()
+    print(json.dumps({"sweep": "matern-n40000-nb512", "steps": args.steps, "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
+    if args.sweep:
+        band_sweep(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               f"sharding of the path is a design note, not a build", file=sys.stderr)

@@ -32,7 +32,7 @@
  *  - Ordering: all calls are ordered on the context's HIP stream and are synchronous at
  *    return (results filled in).  A context is used by one host thread at a time.
  *  - Errors: on a non-OK return the outputs are undefined except mpgeo_result.info.
- *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 < -1, lowp outside 0..2,
+ *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 < -1, band0 < -1, lowp outside 0..2,
  *    band32 >= 0 without a lowp format or lowp without band32 >= 0, a non-finite or
  *    non-positive theta component, a null pointer that is not nullable.
  *    MPGEO_E_NOT_SPD: a non-positive (or NaN) pivot; info = its 0-based global column in
@@ -95,13 +95,19 @@ typedef struct {
  *          -1: FP32 from band64 + 1 to the edge of the matrix (two tiers).
  *  lowp:   0 with band32 = -1; 1 (FP16) or 2 (BF16) with band32 >= 0.
  *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING | MPGEO_PROFILE |
- *          MPGEO_DIST_GCD. */
+ *          MPGEO_DIST_GCD.
+ *  band0:  z >= 0: tiles with i - j > z are dropped (taken as zero, never stored, generated or
+ *          updated: the diagonal-super-tile approximation the paper compares against, which
+ *          factors the block-banded matrix exactly because the Cholesky factor of a matrix of
+ *          tile bandwidth z has no fill-in beyond z); the other bands are capped at z.
+ *          -1: no tile is dropped. */
 typedef struct {
     int32_t tile;
     int32_t band64;
     int32_t band32;
     int32_t lowp;
     uint32_t flags;
+    int32_t band0;
 } mpgeo_plan;
 
 /* Result of one evaluation.  loglik, logdet (natural log of det Sigma) and quad
@@ -225,6 +231,26 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda,
 
 /* HBM bytes of the lower-triangle tiles for n and plan (admission control). */
 size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan);
+
+/* The precision map of Algorithm 1 for n and plan, computed on the host (no device call):
+ * effective bands, tile counts per tier and the algorithmic flops of each tier (the trailing
+ * SYRK/GEMM updates counted by the tier of the tile they write, the panel TRSMs by the tier of
+ * the panel tile, POTRF as rows^3/3 per diagonal tile).  MPGEO_E_ARG for an invalid plan. */
+typedef struct {
+    int64_t p;                 /* tile rows, ceil(n / tile) */
+    int32_t nbp;               /* physical tile size (tile rounded up to 32) */
+    int32_t band64;            /* effective: FP64 iff i - j <= band64 */
+    int32_t edge;              /* effective: 16-bit update operands iff i - j > edge */
+    int32_t band0;             /* effective: dropped iff i - j > band0 */
+    int32_t lowp;              /* effective 16-bit format (0 when no tile is in that tier) */
+    int32_t reserved;
+    int64_t tiles[4];          /* FP64, FP32, FP32 with 16-bit operands, dropped */
+    double update_flops[3];    /* FP64, FP32, 16-bit tier */
+    double trsm_flops[2];      /* FP64, FP32 */
+    double potrf_flops;
+    uint64_t footprint_bytes;  /* as mpgeo_footprint_bytes */
+} mpgeo_tier_summary;
+int mpgeo_plan_tiers(int64_t n, mpgeo_plan plan, mpgeo_tier_summary *out);
 
 /* Static text for a status code. */
 const char *mpgeo_status_string(int status);

@@ -31,7 +31,7 @@ EXPORTED = (
     "mpgeo_loglik", "mpgeo_dataset_create", "mpgeo_dataset_destroy", "mpgeo_dataset_loglik",
     "mpgeo_dataset_krige", "mpgeo_dataset_perm", "mpgeo_dataset_covariance",
     "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
-    "mpgeo_footprint_bytes", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
+    "mpgeo_footprint_bytes", "mpgeo_plan_tiers", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
     "mpgeo_dataset_simulate",
 )
 
@@ -42,7 +42,7 @@ class Theta(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("band64", ctypes.c_int32), ("band32", ctypes.c_int32),
-                ("lowp", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("lowp", ctypes.c_int32), ("flags", ctypes.c_uint32), ("band0", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -53,6 +53,14 @@ class Result(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PlanTiers(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int64), ("nbp", ctypes.c_int32), ("band64", ctypes.c_int32),
+                ("edge", ctypes.c_int32), ("band0", ctypes.c_int32), ("lowp", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tiles", ctypes.c_int64 * 4),
+                ("update_flops", ctypes.c_double * 3), ("trsm_flops", ctypes.c_double * 2),
+                ("potrf_flops", ctypes.c_double), ("footprint_bytes", ctypes.c_uint64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -96,6 +104,7 @@ def _load() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
                                ctypes.POINTER(I32)], ctypes.c_int),
         "mpgeo_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "mpgeo_plan_tiers": ([I64, Plan, ctypes.POINTER(PlanTiers)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -132,14 +141,29 @@ def _ptr(a) -> Optional[int]:
 LOWP = {None: 0, "fp16": 1, "bf16": 2}
 
 
-def make_plan(tile: int, band64: int, flags: int = 0, band32: int = -1, lowp=None) -> Plan:
+def make_plan(tile: int, band64: int, flags: int = 0, band32: int = -1, lowp=None,
+              band0: int = -1) -> Plan:
     """Plan: FP64 within band64 tiles of the diagonal, FP32 beyond; with band32 >= 0 and
-    lowp in {"fp16", "bf16"}, 16-bit operands for tiles farther than band64 + band32."""
-    return Plan(tile=tile, band64=band64, band32=band32, lowp=LOWP[lowp], flags=flags)
+    lowp in {"fp16", "bf16"}, 16-bit operands for tiles farther than band64 + band32; with
+    band0 >= 0, tiles farther than band0 are dropped (zero)."""
+    return Plan(tile=tile, band64=band64, band32=band32, lowp=LOWP[lowp], flags=flags,
+                band0=band0)
 
 
-def mpgeo_footprint_bytes(n: int, tile: int, band64: int, band32: int = -1, lowp=None) -> int:
-    return int(LIB.mpgeo_footprint_bytes(n, make_plan(tile, band64, 0, band32, lowp)))
+def mpgeo_footprint_bytes(n: int, tile: int, band64: int, band32: int = -1, lowp=None,
+                          band0: int = -1) -> int:
+    return int(LIB.mpgeo_footprint_bytes(n, make_plan(tile, band64, 0, band32, lowp, band0)))
+
+
+def plan_tiers(n: int, tile: int, band64: int, band32: int = -1, lowp=None, band0: int = -1) -> dict:
+    """The precision map for n and a plan (host computation): tiers, tile counts, flops."""
+    out = PlanTiers()
+    _check(LIB.mpgeo_plan_tiers(n, make_plan(tile, band64, 0, band32, lowp, band0), ctypes.byref(out)),
+           "mpgeo_plan_tiers")
+    return {"p": out.p, "nbp": out.nbp, "band64": out.band64, "edge": out.edge, "band0": out.band0,
+            "lowp": out.lowp, "tiles": list(out.tiles), "update_flops": list(out.update_flops),
+            "trsm_flops": list(out.trsm_flops), "potrf_flops": out.potrf_flops,
+            "footprint_bytes": out.footprint_bytes}
 
 
 class Context:
@@ -168,7 +192,7 @@ class Context:
 
     def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
                morton: bool = True, timing: bool = False, band32: int = -1, lowp=None,
-               profile: bool = False, gcd: bool = False) -> dict:
+               profile: bool = False, gcd: bool = False, band0: int = -1) -> dict:
         """One-shot eq. (2) (or the profile likelihood): ordering, covariance tiles, factor,
         solve, reduction."""
         dev = isinstance(locs, torch.Tensor)
@@ -179,19 +203,19 @@ class Context:
                 (MPGEO_DIST_GCD if gcd else 0)
         res = Result()
         st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
-                              make_plan(tile, band64, flags, band32, lowp), ctypes.byref(res))
+                              make_plan(tile, band64, flags, band32, lowp, band0), ctypes.byref(res))
         _check(st, "mpgeo_loglik", res.info)
         return res.as_dict()
 
     def factor_dense(self, a: np.ndarray, z, tile: int, band64: int, band32: int = -1,
-                     lowp=None) -> dict:
+                     lowp=None, band0: int = -1) -> dict:
         """Algorithm 1 on a given symmetric positive-definite matrix (lower triangle read)."""
         a = np.asfortranarray(np.asarray(a, dtype=np.float64))
         n = a.shape[0]
         zz = None if z is None else _host_f64(z)
         res = Result()
         st = LIB.mpgeo_factor_dense(self.handle, n, a.ctypes.data, n, _ptr(zz),
-                                    make_plan(tile, band64, 0, band32, lowp), ctypes.byref(res))
+                                    make_plan(tile, band64, 0, band32, lowp, band0), ctypes.byref(res))
         _check(st, "mpgeo_factor_dense", res.info)
         return res.as_dict()
 
@@ -239,20 +263,20 @@ class Dataset:
             pass
 
     def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False,
-               band32: int = -1, lowp=None, profile: bool = False) -> dict:
+               band32: int = -1, lowp=None, profile: bool = False, band0: int = -1) -> dict:
         res = Result()
         flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0)
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
-                                      make_plan(tile, band64, flags, band32, lowp),
+                                      make_plan(tile, band64, flags, band32, lowp, band0),
                                       ctypes.byref(res))
         _check(st, "mpgeo_dataset_loglik", res.info)
         return res.as_dict()
 
-    def try_loglik(self, theta: Sequence[float], tile: int, band64: int) -> tuple:
+    def try_loglik(self, theta: Sequence[float], tile: int, band64: int, band0: int = -1) -> tuple:
         """(status, result dict) without raising (for optimisers that meet non-SPD points)."""
         res = Result()
-        st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta), make_plan(tile, band64),
-                                      ctypes.byref(res))
+        st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
+                                      make_plan(tile, band64, 0, -1, None, band0), ctypes.byref(res))
         return st, res.as_dict()
 
     def krige(self, new_locs, variance: bool = False):

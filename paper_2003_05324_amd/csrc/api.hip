@@ -68,42 +68,67 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
-// Tiles, precision tiers and per-step work lists for one (n, nb, band).
+// Tiles, precision tiers and per-step work lists for one (n, nb, band64, band32, band0).
 struct Layout {
     int64_t n = 0;
     int nb = 0, nbp = 0, p = 0, band = -2;
     int edge = 0;                             // low tier (16-bit operands) iff i - j > edge
+    int zband = 0;                            // zero tier (dropped tiles) iff i - j > zband
     int lowp = 0;                             // 0: none, 1: FP16, 2: BF16
     std::vector<int64_t> off;
     std::vector<TileIJ> all, list64, list32, list16;
-    std::vector<int64_t> pre64, pre32, pre16; // entries of each list with j > k (step k)
-    std::vector<double> flops64, flops32, flops16;   // algorithmic flops of each step's update
-    std::vector<double> colf64, colf32, colf16;      // per tile column j (without K = rows(k))
+    // per step k and tier (0: FP64, 1: FP32, 2: 16-bit operands): the list ranges of the bulk
+    // update (tile columns j >= k+2) and of the lookahead column j = k+1, with their flops
+    struct Range {
+        int64_t b = 0, e = 0;
+        double flops = 0.0;
+    };
+    std::vector<Range> bulk[3], col[3];
     std::vector<double> trsm64_flops, trsm32_flops;
     int64_t n64 = 0, n32 = 0;                 // tiles per storage precision (FP32 holds tier 16)
+    bool has_zero_tile = false;               // dropped tiles share one zero FP32 tile (index n32)
 
-    bool same(int64_t n_, int nb_, int band_, int edge_, int lowp_) const {
-        return n == n_ && nb == nb_ && band == band_ && edge == edge_ && lowp == lowp_;
+    bool same(int64_t n_, int nb_, int band_, int edge_, int zband_, int lowp_) const {
+        return n == n_ && nb == nb_ && band == band_ && edge == edge_ && zband == zband_ && lowp == lowp_;
     }
-    // tier of tile (i, j): 64, 32 or 16
-    int tier(int i, int j) const { return (i - j <= band) ? 64 : (i - j <= edge ? 32 : 16); }
+    // tier of tile (i, j): 64, 32, 16, or 0 for a dropped tile
+    int tier(int i, int j) const {
+        const int d = i - j;
+        return d > zband ? 0 : (d <= band ? 64 : (d <= edge ? 32 : 16));
+    }
+    static int slot(int t) { return t == 64 ? 0 : (t == 32 ? 1 : 2); }
 
     int64_t rows(int i) const { return std::min<int64_t>(nb, n - (int64_t)i * nb); }
+    // panel tiles of step k that are not dropped: rows k+1 .. k+panel_count(k)
+    int panel_count(int k) const { return std::max(0, std::min(p - 1 - k, zband)); }
 
-    static int effective_band(int64_t p_, int band64) { return (band64 < 0 || band64 > p_) ? (int)p_ : band64; }
-    static int effective_edge(int64_t p_, int band64, int band32) {
-        const int b = effective_band(p_, band64);
-        return (band32 < 0 || (int64_t)b + band32 > p_) ? (int)p_ : b + band32;
+    static int effective_zband(int64_t p_, int band0) { return (band0 < 0 || band0 > p_) ? (int)p_ : band0; }
+    static int effective_band(int64_t p_, int band64, int band0 = -1) {
+        const int b = (band64 < 0 || band64 > p_) ? (int)p_ : band64;
+        return std::min(b, effective_zband(p_, band0));
+    }
+    static int effective_edge(int64_t p_, int band64, int band32, int band0 = -1) {
+        const int b = effective_band(p_, band64, band0);
+        const int e = (band32 < 0 || (int64_t)b + band32 > p_) ? (int)p_ : b + band32;
+        return std::min(e, effective_zband(p_, band0));
     }
 
-    void build(int64_t n_, int nb_, int band64, int band32 = -1, int lowp_ = 0) {
+    // algorithmic flops of the update of tile (i, j) per unit of K (SYRK on the diagonal)
+    double tile_flops(int i, int j) const {
+        return (i == j) ? (double)rows(j) * (rows(j) + 1) : 2.0 * rows(i) * rows(j);
+    }
+    // ... and with panel k (K = rows(k))
+    double update_flops(int i, int j, int k) const { return tile_flops(i, j) * rows(k); }
+
+    void build(int64_t n_, int nb_, int band64, int band32 = -1, int lowp_ = 0, int band0 = -1) {
         n = n_;
         nb = nb_;
         nbp = (nb + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
         p = (int)((n + nb - 1) / nb);
-        band = effective_band(p, band64);
-        edge = effective_edge(p, band64, band32);
-        lowp = (edge < p) ? lowp_ : 0;
+        zband = effective_zband(p, band0);
+        band = effective_band(p, band64, band0);
+        edge = effective_edge(p, band64, band32, band0);
+        lowp = (edge < std::min(zband, p - 1)) ? lowp_ : 0;
         const int64_t nt = (int64_t)p * (p + 1) / 2;
         off.assign(nt, 0);
         all.clear();
@@ -112,61 +137,93 @@ struct Layout {
         list16.clear();
         n64 = n32 = 0;
         const int64_t tile_elems = (int64_t)nbp * nbp;
+        std::vector<int64_t> zero_tiles;
         for (int i = 0; i < p; ++i)
             for (int j = 0; j <= i; ++j) {
+                const int t = tier(i, j);
+                if (t == 0) {
+                    zero_tiles.push_back(tri_index(i, j));
+                    continue;
+                }
                 all.push_back({i, j});
-                if (i - j <= band) off[tri_index(i, j)] = (n64++) * tile_elems;
+                if (t == 64) off[tri_index(i, j)] = (n64++) * tile_elems;
                 else off[tri_index(i, j)] = (n32++) * tile_elems;
             }
-        // update lists: columns j = p-1 down to 1, rows ascending; the prefix with j > k is
-        // exactly the trailing work of step k
-        for (int j = p - 1; j >= 1; --j)
-            for (int i = j; i < p; ++i) {
-                const int t = tier(i, j);
-                (t == 64 ? list64 : t == 32 ? list32 : list16).push_back({i, j});
+        has_zero_tile = !zero_tiles.empty();
+        for (int64_t z : zero_tiles) off[z] = n32 * tile_elems;
+        std::vector<TileIJ> *lists[3] = {&list64, &list32, &list16};
+        for (int q = 0; q < 3; ++q) {
+            bulk[q].assign(p, Range{});
+            col[q].assign(p, Range{});
+        }
+        if (zband >= p) {
+            // one list per tier: columns j = p-1 down to 1, rows ascending; the prefix with
+            // j > k is exactly the trailing work of step k
+            for (int j = p - 1; j >= 1; --j)
+                for (int i = j; i < p; ++i) lists[slot(tier(i, j))]->push_back({i, j});
+            std::vector<double> colf[3];
+            std::vector<int64_t> cnt[3];
+            for (int q = 0; q < 3; ++q) {
+                colf[q].assign(p, 0.0);
+                cnt[q].assign(p, 0);
             }
-        pre64.assign(p, 0);
-        pre32.assign(p, 0);
-        pre16.assign(p, 0);
-        flops64.assign(p, 0.0);
-        flops32.assign(p, 0.0);
-        flops16.assign(p, 0.0);
+            for (int j = 1; j < p; ++j)
+                for (int i = j; i < p; ++i) {
+                    const int q = slot(tier(i, j));
+                    colf[q][j] += tile_flops(i, j);
+                    cnt[q][j]++;
+                }
+            for (int q = 0; q < 3; ++q) {
+                std::vector<int64_t> pre(p + 1, 0);       // entries with j > k
+                std::vector<double> suf(p + 1, 0.0);      // flops per unit K of columns > k
+                for (int k = p - 1; k >= 0; --k) {
+                    pre[k] = pre[k + 1] + (k + 1 < p ? cnt[q][k + 1] : 0);
+                    suf[k] = suf[k + 1] + (k + 1 < p ? colf[q][k + 1] : 0.0);
+                }
+                for (int k = 0; k + 1 < p; ++k) {
+                    const double rk = (double)rows(k);
+                    bulk[q][k] = Range{0, pre[k + 1], suf[k + 1] * rk};
+                    col[q][k] = Range{pre[k + 1], pre[k], colf[q][k + 1] * rk};
+                }
+            }
+        } else {
+            // dropped tiles: per step, only tiles with k < j <= i <= k + zband change, so each
+            // step gets its own list section: the lookahead column first, then the bulk
+            // (columns descending, rows ascending)
+            for (int k = 0; k + 1 < p; ++k) {
+                const int last = std::min(p - 1, k + zband);
+                for (int q = 0; q < 3; ++q) {
+                    col[q][k].b = (int64_t)lists[q]->size();
+                    for (int i = k + 1; i <= last; ++i) {
+                        const int t = tier(i, k + 1);
+                        if (slot(t) != q || t == 0) continue;
+                        lists[q]->push_back({i, k + 1});
+                        col[q][k].flops += update_flops(i, k + 1, k);
+                    }
+                    col[q][k].e = bulk[q][k].b = (int64_t)lists[q]->size();
+                    for (int j = last; j >= k + 2; --j)
+                        for (int i = j; i <= last; ++i) {
+                            const int t = tier(i, j);
+                            if (slot(t) != q || t == 0) continue;
+                            lists[q]->push_back({i, j});
+                            bulk[q][k].flops += update_flops(i, j, k);
+                        }
+                    bulk[q][k].e = (int64_t)lists[q]->size();
+                }
+            }
+        }
         trsm64_flops.assign(p, 0.0);
         trsm32_flops.assign(p, 0.0);
-        std::vector<double> col64(p, 0.0), col32(p, 0.0), col16(p, 0.0);
-        std::vector<int64_t> cnt64(p, 0), cnt32(p, 0), cnt16(p, 0);
-        for (int j = 1; j < p; ++j)
-            for (int i = j; i < p; ++i) {
-                const double f = (i == j) ? (double)rows(j) * (rows(j) + 1) : 2.0 * rows(i) * rows(j);
-                const int t = tier(i, j);
-                (t == 64 ? col64 : t == 32 ? col32 : col16)[j] += f;
-                (t == 64 ? cnt64 : t == 32 ? cnt32 : cnt16)[j]++;
-            }
-        colf64 = col64;
-        colf32 = col32;
-        colf16 = col16;
-        double s64 = 0, s32 = 0, s16 = 0;
-        int64_t c64 = 0, c32 = 0, c16 = 0;
-        for (int k = p - 1; k >= 0; --k) {
-            pre64[k] = c64;
-            pre32[k] = c32;
-            pre16[k] = c16;
-            flops64[k] = s64 * rows(k);
-            flops32[k] = s32 * rows(k);
-            flops16[k] = s16 * rows(k);
-            s64 += col64[k];
-            s32 += col32[k];
-            s16 += col16[k];
-            c64 += cnt64[k];
-            c32 += cnt32[k];
-            c16 += cnt16[k];
-        }
         for (int k = 0; k < p; ++k)
-            for (int i = k + 1; i < p; ++i) {
+            for (int i = k + 1; i <= k + panel_count(k); ++i) {
                 const double f = (double)rows(i) * rows(k) * rows(k);   // triangular solve
                 if (i - k <= band) trsm64_flops[k] += f;
                 else trsm32_flops[k] += f;
             }
+    }
+    // step k has updates in the 16-bit tier
+    bool lowp_step(int k) const {
+        return lowp && k + 1 < p && (bulk[2][k].e > bulk[2][k].b || col[2][k].e > col[2][k].b);
     }
 };
 
@@ -294,7 +351,7 @@ int check_theta(const mpgeo_theta &t) {
 
 int check_plan(const mpgeo_plan &pl) {
     if (pl.tile < 1 || pl.tile > kMaxTile) return MPGEO_E_ARG;
-    if (pl.band64 < -1 || pl.band32 < -1) return MPGEO_E_ARG;
+    if (pl.band64 < -1 || pl.band32 < -1 || pl.band0 < -1) return MPGEO_E_ARG;
     if (pl.lowp < 0 || pl.lowp > 2) return MPGEO_E_ARG;
     if ((pl.band32 >= 0) != (pl.lowp != 0)) return MPGEO_E_ARG;   // a third tier needs its format
     return MPGEO_OK;
@@ -318,15 +375,17 @@ TileMap tile_map(const mpgeo_dataset *ds) {
 int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     Layout &L = ds->layout;
     const int64_t p_new = (ds->n + pl.tile - 1) / pl.tile;
-    const int band_eff = Layout::effective_band(p_new, pl.band64);
-    const int edge_eff = Layout::effective_edge(p_new, pl.band64, pl.band32);
-    const int lowp_eff = (edge_eff < p_new) ? pl.lowp : 0;
-    if (L.same(ds->n, pl.tile, band_eff, edge_eff, lowp_eff) && ds->off.ptr) return MPGEO_OK;
-    L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp);
+    const int zband_eff = Layout::effective_zband(p_new, pl.band0);
+    const int band_eff = Layout::effective_band(p_new, pl.band64, pl.band0);
+    const int edge_eff = Layout::effective_edge(p_new, pl.band64, pl.band32, pl.band0);
+    const int lowp_eff = (edge_eff < std::min<int64_t>(zband_eff, p_new - 1)) ? pl.lowp : 0;
+    if (L.same(ds->n, pl.tile, band_eff, edge_eff, zband_eff, lowp_eff) && ds->off.ptr) return MPGEO_OK;
+    L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp, pl.band0);
     ds->has_factor = false;
     const size_t te = (size_t)L.nbp * L.nbp;
+    const size_t tiles32 = (size_t)L.n32 + (L.has_zero_tile ? 1 : 0);
     MPGEO_TRY(ds->pool64.ensure(std::max<size_t>(1, (size_t)L.n64 * te * sizeof(double))));
-    MPGEO_TRY(ds->pool32.ensure(std::max<size_t>(1, (size_t)L.n32 * te * sizeof(float))));
+    MPGEO_TRY(ds->pool32.ensure(std::max<size_t>(1, tiles32 * te * sizeof(float))));
     MPGEO_TRY(ds->off.ensure(L.off.size() * sizeof(int64_t)));
     MPGEO_TRY(ds->all.ensure(std::max<size_t>(1, L.all.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list64.ensure(std::max<size_t>(1, L.list64.size()) * sizeof(TileIJ)));
@@ -348,6 +407,8 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     MPGEO_TRY(ds->info.ensure(sizeof(unsigned long long)));
     MPGEO_TRY(ds->result.ensure(4 * sizeof(double)));
     hipStream_t s = ds->ctx->stream;
+    if (L.has_zero_tile)   // the shared tile every dropped tile maps to: zero, never written
+        MPGEO_HIP(hipMemsetAsync(ds->pool32.as<float>() + (size_t)L.n32 * te, 0, te * sizeof(float), s));
     MPGEO_HIP(hipMemcpyAsync(ds->off.ptr, L.off.data(), L.off.size() * sizeof(int64_t),
                              hipMemcpyHostToDevice, s));
     MPGEO_HIP(hipMemcpyAsync(ds->all.ptr, L.all.data(), L.all.size() * sizeof(TileIJ),
@@ -488,13 +549,14 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         ctx->timed_on(s1, kStatPotrf, rk * rk * rk / 3.0, rk * rk * 8.0 * 3.0,
                       [&] { launch_potrf(pa, s1); });
         if (k + 1 >= p) return;
-        const int n64 = std::min(L.band, p - 1 - k);
-        const int first32 = k + L.band + 1;
-        const int n32 = first32 < p ? p - first32 : 0;
+        const int npanel = L.panel_count(k);            // panel tiles that are not dropped
+        const int n64 = std::min(L.band, npanel);
+        const int first32 = k + n64 + 1;
+        const int n32 = npanel - n64;
         double *p64 = panel64(k);
         float *p32 = panel32(k);
         // this step updates low-tier tiles: the TRSM also records each panel tile's max |x|
-        const bool quant = L.lowp && L.pre16[k] > 0;
+        const bool quant = L.lowp_step(k);
         unsigned *amax = quant ? qmax(k) : nullptr;
         if (quant) (void)hipMemsetAsync(amax, 0, (size_t)p * sizeof(unsigned), s1);
         if (n64 > 0)
@@ -506,12 +568,11 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
                 launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, amax, s1);
             });
         if (quant)   // 16-bit panel copy with per-tile power-of-two scales
-            ctx->timed_on(s1, kStatQuant, 0.0, (double)(p - 1 - k) * nbd * nbd * 6.0, [&] {
-                launch_quantize(map, k + 1, p - 1 - k, p32, amax, qpanel(k), qscale(k), L.lowp, s1);
+            ctx->timed_on(s1, kStatQuant, 0.0, (double)npanel * nbd * nbd * 6.0, [&] {
+                launch_quantize(map, k + 1, npanel, p32, amax, qpanel(k), qscale(k), L.lowp, s1);
             });
-        ctx->timed_on(s1, kStatPanel, 2.0 * (p - 1 - k) * nbd * nbd,
-                      (double)(p - 1 - k) * nbd * nbd * 16.0,
-                      [&] { launch_panel_solve(map, k, p64, pa.y, r, s1); });
+        ctx->timed_on(s1, kStatPanel, 2.0 * npanel * nbd * nbd, (double)npanel * nbd * nbd * 16.0,
+                      [&] { launch_panel_solve(map, k, npanel, p64, pa.y, r, s1); });
     };
     // update of list entries [b, e) of each tier with panel k on stream st.  Algorithmic
     // bytes: every output tile read and written once, every panel tile it needs read once
@@ -519,7 +580,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, int64_t b16,
                             int64_t e16, double f64, double f32, double f16, hipStream_t st) {
         const double tile_elems = (double)nbd * nbd;
-        auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(p - 1 - k, 2 * count); };
+        auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(L.panel_count(k), 2 * count); };
         if (e16 > b16)
             ctx->timed_on(st, kStatUpdate16, f16,
                           tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 + panel_tiles(e16 - b16) * 2.0), [&] {
@@ -540,22 +601,19 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     factor_step(0);
     MPGEO_HIP(hipEventRecord(ev_f[0], s1));
     for (int k = 0; k < p; ++k) {
-        const double rk = (double)L.rows(k);
-        // bulk: columns >= k+2 (list prefix [0, pre[k+1]))
+        // bulk: tile columns >= k+2
         MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[k], 0));
-        if (k + 1 < p) {
-            const double c64 = L.colf64[k + 1] * rk, c32 = L.colf32[k + 1] * rk,
-                         c16 = L.colf16[k + 1] * rk;
-            update_range(k, 0, L.pre64[k + 1], 0, L.pre32[k + 1], 0, L.pre16[k + 1],
-                         L.flops64[k] - c64, L.flops32[k] - c32, L.flops16[k] - c16, s0);
-        }
+        if (k + 1 < p)
+            update_range(k, L.bulk[0][k].b, L.bulk[0][k].e, L.bulk[1][k].b, L.bulk[1][k].e,
+                         L.bulk[2][k].b, L.bulk[2][k].e, L.bulk[0][k].flops, L.bulk[1][k].flops,
+                         L.bulk[2][k].flops, s0);
         MPGEO_HIP(hipEventRecord(ev_bulk[k], s0));
         if (k + 1 < p) {
             // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
-            update_range(k, L.pre64[k + 1], L.pre64[k], L.pre32[k + 1], L.pre32[k], L.pre16[k + 1],
-                         L.pre16[k], L.colf64[k + 1] * rk, L.colf32[k + 1] * rk,
-                         L.colf16[k + 1] * rk, s1);
+            update_range(k, L.col[0][k].b, L.col[0][k].e, L.col[1][k].b, L.col[1][k].e,
+                         L.col[2][k].b, L.col[2][k].e, L.col[0][k].flops, L.col[1][k].flops,
+                         L.col[2][k].flops, s1);
             factor_step(k + 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
@@ -668,9 +726,39 @@ const char *mpgeo_status_string(int status) {
 size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
     if (n < 1 || check_plan(plan) != MPGEO_OK) return 0;
     Layout L;
-    L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp);
+    L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp, plan.band0);
     const size_t te = (size_t)L.nbp * L.nbp;
-    return (size_t)L.n64 * te * sizeof(double) + (size_t)L.n32 * te * sizeof(float);
+    return (size_t)L.n64 * te * sizeof(double) +
+           ((size_t)L.n32 + (L.has_zero_tile ? 1 : 0)) * te * sizeof(float);
+}
+
+int mpgeo_plan_tiers(int64_t n, mpgeo_plan plan, mpgeo_tier_summary *out) {
+    if (!out || n < 1 || check_plan(plan) != MPGEO_OK) return MPGEO_E_ARG;
+    Layout L;
+    L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp, plan.band0);
+    mpgeo_tier_summary info{};
+    info.p = L.p;
+    info.nbp = L.nbp;
+    info.band64 = L.band;
+    info.edge = L.edge;
+    info.band0 = L.zband;
+    info.lowp = L.lowp;
+    for (int i = 0; i < L.p; ++i)
+        for (int j = 0; j <= i; ++j) {
+            const int t = L.tier(i, j);
+            info.tiles[t == 64 ? 0 : t == 32 ? 1 : t == 16 ? 2 : 3]++;
+        }
+    for (int q = 0; q < 3; ++q)
+        for (int k = 0; k + 1 < L.p; ++k) info.update_flops[q] += L.bulk[q][k].flops + L.col[q][k].flops;
+    for (int k = 0; k < L.p; ++k) {
+        info.trsm_flops[0] += L.trsm64_flops[k];
+        info.trsm_flops[1] += L.trsm32_flops[k];
+        const double r = (double)L.rows(k);
+        info.potrf_flops += r * r * r / 3.0;
+    }
+    info.footprint_bytes = mpgeo_footprint_bytes(n, plan);
+    *out = info;
+    return MPGEO_OK;
 }
 
 int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {

@@ -123,9 +123,9 @@ void launch_quantize(const TileMap &map, int first, int count, const float *p32,
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
                         const float *scale, int lowp, hipStream_t stream);
 
-// Panel step of the fused forward solve: r_i -= P64_i y_k for i in (k, p), and copy the
-// finished panel tile (i, k) from staging into its storage precision.
-void launch_panel_solve(const TileMap &map, int k, const double *p64, const double *yk,
+// Panel step of the fused forward solve: r_i -= P64_i y_k for i = k+1 .. k+count, and copy
+// the finished panel tile (i, k) from staging into its storage precision.
+void launch_panel_solve(const TileMap &map, int k, int count, const double *p64, const double *yk,
                         double *r, hipStream_t stream);
 
 // z = L eps over the tiles (physical padded vectors), lower triangle of diagonal tiles only.

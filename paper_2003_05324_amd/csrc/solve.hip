@@ -187,9 +187,8 @@ void launch_permute(const double *src, double *dst, const int64_t *perm, int64_t
                        dst, perm, n, to_caller);
 }
 
-void launch_panel_solve(const TileMap &map, int k, const double *p64, const double *yk, double *r,
-                        hipStream_t stream) {
-    const int count = map.p - k - 1;
+void launch_panel_solve(const TileMap &map, int k, int count, const double *p64, const double *yk,
+                        double *r, hipStream_t stream) {
     if (count <= 0) return;
     dim3 grid((unsigned)count, (unsigned)((map.nbp + 255) / 256));
     hipLaunchKernelGGL(panel_solve_kernel, grid, dim3(256), 0, stream, map, k, p64, yk, r);

@@ -444,3 +444,48 @@ def test_gcd_loglik_and_kriging_match_oracle(lib, ctx, band, tol):
     ktol = 1e-9 if band < 0 else 1e-4
     assert np.max(np.abs(pred - kr["pred"])) <= ktol * np.max(np.abs(kr["pred"]))
     assert np.max(np.abs(var - kr["var"])) <= ktol * GCD_THETA[0]
+
+
+# ---- dropped tiles (diagonal super tile: tiles beyond band0 taken as zero) -----------------
+def test_dropped_tiles_are_exact_on_a_block_banded_matrix(lib, ctx):
+    # a matrix of tile bandwidth w has a Cholesky factor of the same bandwidth, so dropping
+    # the tiles beyond any band0 >= w changes nothing (bitwise: only exact zeros are skipped)
+    n, tile, width = 200, 32, 2
+    a = _block_banded_spd(n, tile, width, 5)
+    z = normals(n, 6)
+    full = ctx.factor_dense(a, z, tile, -1)
+    for band0 in (width, width + 1, 6):
+        for band in (-1, 1):
+            r = ctx.factor_dense(a, z, tile, band, band0=band0)
+            ref = full if band < 0 else ctx.factor_dense(a, z, tile, band)
+            assert r["loglik"] == ref["loglik"], (band0, band)
+            assert r["logdet"] == ref["logdet"], (band0, band)
+
+
+@pytest.mark.parametrize("theta,band0", [((1.0, 0.1, 0.5), 0), ((1.0, 0.1, 0.5), 3),
+                                         ((1.0, 0.1, 0.5), 6), ((1.0, 0.03, 0.5), 1),
+                                         ((1.0, 0.03, 0.5), 2), ((1.0, 0.03, 0.5), 5)])
+@pytest.mark.parametrize("band,tol", [(-1, 1e-10), (1, 1e-5)])
+def test_dropped_tiles_match_the_truncated_matrix(small_ds, theta, band0, band, tol):
+    # the oracle's definition: Sigma in the ordered frame with every entry of a tile farther
+    # than band0 from the diagonal set to zero, then eq. (2); it may not be positive definite,
+    # in which case the library must say so
+    locs, z = small_case()
+    perm = oracle.morton_order(locs)
+    sig = oracle.matern_matrix(locs[perm], theta)
+    ti = np.arange(len(z)) // SMALL.tile
+    sig[np.abs(ti[:, None] - ti[None, :]) > band0] = 0.0
+    try:
+        want = oracle.likelihood.loglik_parts(sig, z[perm])
+    except oracle.likelihood.NotPositiveDefinite:
+        want = None
+    st, got = small_ds.try_loglik(theta, SMALL.tile, band, band0=band0)
+    if want is None:
+        assert st == 2, (st, got)       # MPGEO_E_NOT_SPD
+        return
+    assert st == 0
+    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), len(z)) <= tol
+    # dropped tiles read back as zero
+    if band0 < 2:
+        far = small_ds.entries(np.array([len(z) - 1]), np.array([0]))
+        assert far[0] == 0.0
