@@ -13,7 +13,10 @@
 #include "common.h"
 #include "../../include/mpgeo.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -242,6 +245,12 @@ struct mpgeo_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t side = nullptr;            // lookahead stream (next panel's critical path)
+    // Bulk trailing updates run on a stream whose CU mask leaves `reserved_cus` compute units
+    // to the lookahead stream alone: the one-workgroup POTRF and the small FP64 TRSM of the
+    // critical path then never wait for the wide update kernels to drain.  nullptr: the bulk
+    // runs on `stream` with every CU.
+    hipStream_t bulk = nullptr;
+    int reserved_cus = 0;
     std::vector<hipEvent_t> sync_events;   // dependency events between the two streams
 
     // at least `count` timing-free events for stream dependencies
@@ -503,6 +512,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     mpgeo_ctx *ctx = ds->ctx;
     hipStream_t s0 = ctx->stream;
     hipStream_t s1 = ctx->side;
+    hipStream_t sb = ctx->bulk ? ctx->bulk : s0;   // bulk trailing updates
     const Layout &L = ds->layout;
     const TileMap map = tile_map(ds);
     const int nbp = L.nbp, p = L.p;
@@ -520,6 +530,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
     MPGEO_HIP(hipEventRecord(ev_start, s0));
     MPGEO_HIP(hipStreamWaitEvent(s1, ev_start, 0));
+    if (sb != s0) MPGEO_HIP(hipStreamWaitEvent(sb, ev_start, 0));
     const double nbd = L.nb;
     const TileIJ *l64 = ds->list64.as<TileIJ>();
     const TileIJ *l32 = ds->list32.as<TileIJ>();
@@ -561,7 +572,8 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         if (quant) (void)hipMemsetAsync(amax, 0, (size_t)p * sizeof(unsigned), s1);
         if (n64 > 0)
             ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
-                launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, amax, s1);
+                launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, amax, s1,
+                            /*narrow=*/true);
             });
         if (n32 > 0)
             ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
@@ -589,7 +601,8 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         if (e64 > b64)
             ctx->timed_on(st, kStatUpdate64, f64,
                           tile_elems * ((double)(e64 - b64) * 8.0 * 2.0 + panel_tiles(e64 - b64) * 8.0), [&] {
-                launch_update(map, l64 + b64, e64 - b64, true, panel64(k), panel32(k), st);
+                launch_update(map, l64 + b64, e64 - b64, true, panel64(k), panel32(k), st,
+                              /*narrow=*/st == s1);   // the lookahead column
             });
         if (e32 > b32)
             ctx->timed_on(st, kStatUpdate32, f32,
@@ -602,12 +615,12 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     MPGEO_HIP(hipEventRecord(ev_f[0], s1));
     for (int k = 0; k < p; ++k) {
         // bulk: tile columns >= k+2
-        MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[k], 0));
+        MPGEO_HIP(hipStreamWaitEvent(sb, ev_f[k], 0));
         if (k + 1 < p)
             update_range(k, L.bulk[0][k].b, L.bulk[0][k].e, L.bulk[1][k].b, L.bulk[1][k].e,
                          L.bulk[2][k].b, L.bulk[2][k].e, L.bulk[0][k].flops, L.bulk[1][k].flops,
-                         L.bulk[2][k].flops, s0);
-        MPGEO_HIP(hipEventRecord(ev_bulk[k], s0));
+                         L.bulk[2][k].flops, sb);
+        MPGEO_HIP(hipEventRecord(ev_bulk[k], sb));
         if (k + 1 < p) {
             // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
@@ -620,6 +633,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         MPGEO_HIP(hipGetLastError());
     }
     MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[p - 1], 0));
+    if (sb != s0) MPGEO_HIP(hipStreamWaitEvent(s0, ev_bulk[p - 1], 0));
     if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s0));
     ctx->timed(kStatFinal, 2.0 * p, 16.0 * p, [&] {
         launch_finalize(logdet_part, quad_part, p, L.n, ds->profile, ds->result.as<double>(), s0);
@@ -732,6 +746,33 @@ size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
            ((size_t)L.n32 + (L.has_zero_tile ? 1 : 0)) * te * sizeof(float);
 }
 
+// Reserved compute units for the critical path: MPGEO_RESERVED_CUS (default 0: none),
+// spread over the mask so that they fall on different XCDs.
+static void create_bulk_stream(mpgeo_ctx *c) {
+    int reserve = 0;
+    if (const char *env = std::getenv("MPGEO_RESERVED_CUS")) reserve = std::atoi(env);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (reserve <= 0 || reserve >= cus / 2) return;
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    for (int i = 0; i < cus; ++i) mask[(size_t)i / 32] |= 1u << (i % 32);
+    const int stride = cus / reserve;
+    for (int j = 0; j < reserve; ++j) {
+        const int i = (j * stride + j) % cus;
+        mask[(size_t)i / 32] &= ~(1u << (i % 32));
+    }
+    hipStream_t st = nullptr;
+    if (hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    c->bulk = st;
+    c->reserved_cus = reserve;
+}
+
 int mpgeo_plan_tiers(int64_t n, mpgeo_plan plan, mpgeo_tier_summary *out) {
     if (!out || n < 1 || check_plan(plan) != MPGEO_OK) return MPGEO_E_ARG;
     Layout L;
@@ -790,6 +831,7 @@ int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {
         delete c;
         return MPGEO_E_DEVICE;
     }
+    create_bulk_stream(c);
     c->reset_stats();
     *out = c;
     return MPGEO_OK;
@@ -807,6 +849,10 @@ int mpgeo_ctx_destroy(mpgeo_ctx *ctx) {
     for (auto e : ctx->sync_events) (void)hipEventDestroy(e);
     (void)hipStreamSynchronize(ctx->side);
     (void)hipStreamDestroy(ctx->side);
+    if (ctx->bulk) {
+        (void)hipStreamSynchronize(ctx->bulk);
+        (void)hipStreamDestroy(ctx->bulk);
+    }
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return MPGEO_OK;

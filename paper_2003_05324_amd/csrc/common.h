@@ -107,12 +107,14 @@ void launch_potrf(const PotrfArgs &a, hipStream_t stream);
 // is not null, raises absmax[i] (float bits) to max |P32[i]| (for the third tier's scales).
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64,
                  const double *linv, const float *linv32, double *p64, float *p32,
-                 unsigned *absmax, hipStream_t stream);
+                 unsigned *absmax, hipStream_t stream,
+                 bool narrow = false);
 
 // Trailing update of step k: A_ij -= P_i P_j^T over list[0, count) (tiles all of one
 // precision), with P the staging panel of that precision.
 void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool fp64,
-                   const double *p64, const float *p32, hipStream_t stream);
+                   const double *p64, const float *p32, hipStream_t stream,
+                   bool narrow = false);
 
 // Third tier: quantise panel tiles i in [first, first + count) of the FP32 staging panel to
 // 16-bit (lowp 1: FP16, 2: BF16), row-major, with the power-of-two scale of each tile

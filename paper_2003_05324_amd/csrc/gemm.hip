@@ -281,12 +281,15 @@ void launch_shape(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
 }
 
 // Production shapes: 128 x 128 blocks of 4 waves when the tile allows, else 64 or 32;
-// K chunks of 16 columns.
+// K chunks of 16 columns.  `narrow` (the few-tile FP64 launches of the critical path, which
+// run beside the wide trailing updates): 64 x 64 blocks with K chunks of 8, 20 KB of LDS
+// instead of 72 KB, so a workgroup fits where one of the concurrent update workgroups ends.
 template <typename T, int EPI>
-void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
+void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream, bool narrow = false) {
     const int nbp = g.map.nbp;
     if (ntiles <= 0) return;
-    if (nbp % 128 == 0) launch_shape<T, Shape<128, 128, 2, 2, 16>, EPI>(g, ntiles, stream);
+    if (narrow && nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 8>, EPI>(g, ntiles, stream);
+    else if (nbp % 128 == 0) launch_shape<T, Shape<128, 128, 2, 2, 16>, EPI>(g, ntiles, stream);
     else if (nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 16>, EPI>(g, ntiles, stream);
     else launch_shape<T, Shape<32, 32, 2, 2, 16>, EPI>(g, ntiles, stream);
 }
@@ -295,7 +298,7 @@ void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
 
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, const double *linv,
                  const float *linv32, double *p64, float *p32, unsigned *absmax,
-                 hipStream_t stream) {
+                 hipStream_t stream, bool narrow) {
     if (count <= 0) return;
     GemmArgs g{};
     g.map = map;
@@ -306,7 +309,7 @@ void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, c
     g.absmax = absmax;
     if (fp64) {
         g.linv = linv;
-        launch_gemm<double, kTrsm>(g, count, stream);
+        launch_gemm<double, kTrsm>(g, count, stream, narrow);
     } else {
         g.linv = linv32;
         launch_gemm<float, kTrsm>(g, count, stream);
@@ -314,14 +317,14 @@ void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, c
 }
 
 void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool fp64,
-                   const double *p64, const float *p32, hipStream_t stream) {
+                   const double *p64, const float *p32, hipStream_t stream, bool narrow) {
     if (count <= 0) return;
     GemmArgs g{};
     g.map = map;
     g.list = list;
     if (fp64) {
         g.panel = p64;
-        launch_gemm<double, kUpdate>(g, count, stream);
+        launch_gemm<double, kUpdate>(g, count, stream, narrow);
     } else {
         g.panel = p32;
         launch_gemm<float, kUpdate>(g, count, stream);

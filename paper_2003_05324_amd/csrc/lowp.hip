@@ -76,9 +76,11 @@ struct LowpArgs {
 };
 
 // BM x BN output block, WM x WN waves, K chunk KC, DEPTH chunks of operands in flight;
-// CPRE: load the C block into registers before the K loop (its latency hides behind it).
-template <int BM_, int BN_, int WM_, int WN_, int KC_, int DEPTH_ = 1, int CPRE_ = 0> struct LShape {
-    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_, DEPTH = DEPTH_;
+// CPRE: load the C block into registers before the K loop (its latency hides behind it);
+// PAD: 16-bit elements of padding per LDS row (spreads the rows over the banks).
+template <int BM_, int BN_, int WM_, int WN_, int KC_, int DEPTH_ = 1, int CPRE_ = 0, int PAD_ = 8>
+struct LShape {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_, DEPTH = DEPTH_, PAD = PAD_;
     static constexpr bool CPRE = CPRE_ != 0;
     static constexpr int kThreads = 64 * WM * WN;
 };
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     constexpr int BM = S::BM, BN = S::BN, KC = S::KC, NT = S::kThreads;
     constexpr int NBR = BM / S::WM / 16;
     constexpr int NBC = BN / S::WN / 16;
-    constexpr int LD = KC + 8;             // padded LDS row (16 bytes) spreads rows over banks
+    constexpr int LD = KC + S::PAD;        // padded LDS row
     constexpr int VPR_ROW = KC / 8;        // 16-byte vectors per row of a chunk
     constexpr int NVQ = BN * VPR_ROW, NVR = BM * VPR_ROW;
     constexpr int VPQ = (NVQ + NT - 1) / NT, VPR = (NVR + NT - 1) / NT;
@@ -242,10 +244,11 @@ void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
 template <typename T>
 void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
     const int nbp = g.map.nbp;
-    // 128 x 64 blocks, 4 chunks in flight, C loaded up front: the 16-bit MFMAs outrun memory,
-    // so the kernel is shaped for bytes in flight (measured best on the n ~ 1e5 step-0 list)
-    if (nbp % 128 == 0) launch_lowp_shape<T, LShape<128, 64, 2, 2, 32, 4, 1>>(g, ntiles, stream);
-    else if (nbp % 64 == 0) launch_lowp_shape<T, LShape<64, 64, 2, 2, 32, 4, 1>>(g, ntiles, stream);
+    // 128 x 64 blocks, K chunks of 64 with two in flight, C loaded up front, LDS rows padded by
+    // 16 elements (no bank conflicts): measured best on the n ~ 1e5 step-0 list (402 TFLOP/s;
+    // K chunks of 32: 373, and padding 8 showed 5 conflict cycles per LDS instruction)
+    if (nbp % 128 == 0) launch_lowp_shape<T, LShape<128, 64, 2, 2, 64, 2, 1, 16>>(g, ntiles, stream);
+    else if (nbp % 64 == 0) launch_lowp_shape<T, LShape<64, 64, 2, 2, 64, 2, 1, 16>>(g, ntiles, stream);
     else launch_lowp_shape<T, LShape<32, 32, 2, 2, 32, 1, 0>>(g, ntiles, stream);
 }
 
