@@ -117,6 +117,15 @@ def parse():
     ap.add_argument("--cpu-sample-m", type=int, default=110)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--heldout", type=int, default=2000, help="kriging sites (0: skip)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the headline: a batch of this many independent problems "
+                         "(n log-uniform in [500, 8000]) through the batched entry point, against "
+                         "one-at-a-time evaluation; one JSON line")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="instead of the headline: this many requests (Poisson arrivals) for 16 "
+                         "resident datasets (n log-uniform in [2000, 60000]) through the serving "
+                         "loop, mixed plan and FP64 plan; one JSON line")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="arrivals per second")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline: the n = 40,000 band sweep (6 fields x bands "
                          "0, 1, 4, 16, all), one JSON line")
@@ -239,10 +248,115 @@ def band_sweep(args):
     print(json.dumps({"sweep": "matern-n40000-nb512", "steps": args.steps, "rows": rows}), flush=True)
 
 
+def batch_bench(args):
+    """Batched evaluation: `args.batch` problems with their own sites, data and theta, all-FP64
+    plan, tiles from the autotuner (tuned on an untimed first batch), against evaluating the
+    same problems one after another through the one-shot entry point (tile 512)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2003_05324_amd as mp
+    from synthetic import batch_instances
+    probs = batch_instances(args.batch, 11)
+    ns = np.array([len(z) for _, z, _ in probs])
+    flops = float(np.sum(ns.astype(np.float64) ** 3 / 3.0))
+    ctx = mp.Context(0)
+    print(f"[batch] {len(probs)} problems, n in [{ns.min()}, {ns.max()}], sum n^3/3 = {flops:.3e}",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    st, _, tiles = ctx.batch_loglik(probs, tile=0, band64=-1)          # tunes the tile sizes
+    t_tune = time.perf_counter() - t0
+    walls = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, res, tiles = ctx.batch_loglik(probs, tile=0, band64=-1)
+        walls.append(time.perf_counter() - t0)
+    wall = statistics.median(walls)
+    print(f"[batch] batched: {wall:.3f} s (tuning pass {t_tune:.2f} s)", file=sys.stderr, flush=True)
+    for locs, z, theta in probs[:2]:
+        ctx.loglik(locs, z, theta, 512, -1)                              # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [ctx.loglik(locs, z, theta, 512, -1) for locs, z, theta in probs]
+    t_seq = time.perf_counter() - t0
+    print(f"[batch] one at a time: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    dev = max(abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), len(p[1]))
+              for a, b, p in zip(res, seq, probs))
+    # oracle spot check on the three smallest problems
+    small = np.argsort(ns)[:3]
+    orc = max(abs(res[q]["loglik"] - oracle.loglik(*probs[q])["loglik"]) /
+              abs(oracle.loglik(*probs[q])["loglik"]) for q in small)
+    hist = {}
+    for t in tiles:
+        hist[str(t)] = hist.get(str(t), 0) + 1
+    ctx.close()
+    print(json.dumps({
+        "batch": "matern-batch512-n500-8000" if args.batch == 512 else f"matern-batch{args.batch}-n500-8000",
+        "problems": len(probs), "status": st, "sum_n3_over_3": flops,
+        "batched_s": wall, "batched_evals_per_s": len(probs) / wall,
+        "batched_tflops": flops / wall / 1e12,
+        "sequential_s": t_seq, "sequential_evals_per_s": len(probs) / t_seq,
+        "speedup": t_seq / wall, "tuning_pass_s": t_tune, "tiles": hist,
+        "max_dloglik_batched_vs_sequential": dev, "max_rel_dloglik_vs_oracle_3_smallest": orc,
+        "lanes": int(os.environ.get("MPGEO_BATCH_LANES", "4"))}), flush=True)
+
+
+def serve_bench(args):
+    """Serving loop: Poisson arrivals of likelihood requests (theta drawn around (1, 0.1, 0.5) as
+    an optimiser's trajectory would visit it) for 16 datasets, HBM budget 96 GB, 4 lanes; the same
+    trace with the two-tier plan (FP64 band 2, tile 512) and with the all-FP64 plan."""
+    import numpy as np
+
+    import paper_2003_05324_amd as mp
+    from synthetic import jittered_grid, normals
+    rng = np.random.default_rng(21)
+    sizes = [int(round(np.exp(rng.uniform(np.log(2000), np.log(60000))))) for _ in range(16)]
+    data = []
+    for q, n in enumerate(sizes):
+        m = int(np.ceil(np.sqrt(n)))
+        data.append((jittered_grid(m, 700 + q)[:n].copy(), normals(n, 800 + q)))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, args.serve))
+    picks = rng.integers(0, len(sizes), args.serve)
+    thetas = [(float(np.exp(rng.normal(0, 0.15))), float(0.1 * np.exp(rng.normal(0, 0.15))), 0.5)
+              for _ in range(args.serve)]
+    flops = float(sum(sizes[d] ** 3 / 3.0 for d in picks))
+    ctx = mp.Context(0)
+    out = {"serve": f"matern-serve{args.serve}-16sets-n2000-60000", "requests": args.serve,
+           "rate_per_s": args.serve_rate, "dataset_sizes": sizes, "sum_n3_over_3": flops}
+    for name, band in (("two_tier_b2", 2), ("fp64", -1)):
+        srv = mp.Server(ctx, 96 * 2 ** 30, 4)
+        ids = [srv.add_dataset(locs, z, 512, band) for locs, z in data]
+        for q in range(args.serve):
+            srv.submit(ids[picks[q]], thetas[q], float(arrivals[q]))
+        print(f"[serve] {name}: {args.serve} requests over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
+        st, res = srv.run()
+        srv.close()
+        lat = np.array([r["finish_s"] - r["arrival_s"] for r in res])
+        wait = np.array([r["start_s"] - r["arrival_s"] for r in res])
+        span = max(r["finish_s"] for r in res)
+        out[name] = {"status": st, "p50_latency_s": float(np.percentile(lat, 50)),
+                     "p99_latency_s": float(np.percentile(lat, 99)),
+                     "mean_wait_s": float(wait.mean()), "makespan_s": span,
+                     "evals_per_s": args.serve / span, "tflops": flops / span / 1e12,
+                     "loglik_first": res[0]["loglik"]}
+        print(f"[serve] {name}: {out[name]}", file=sys.stderr, flush=True)
+    ctx.close()
+    out["p50_speedup_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["two_tier_b2"]["p50_latency_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.serve:
+        serve_bench(args)
+        return
     if args.sweep:
         band_sweep(args)
+        return
+    if args.batch:
+        batch_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "

@@ -100,7 +100,14 @@ typedef struct {
  *          updated: the diagonal-super-tile approximation the paper compares against, which
  *          factors the block-banded matrix exactly because the Cholesky factor of a matrix of
  *          tile bandwidth z has no fill-in beyond z); the other bands are capped at z.
- *          -1: no tile is dropped. */
+ *          -1: no tile is dropped.
+ *  dist64: > 0: the precision map is drawn from distances instead of tile offsets: tile (i, j)
+ *          is FP64 when the bounding boxes of its two blocks of (ordered) sites come within
+ *          dist64 of each other (diagonal tiles always), FP32 otherwise, or, with dist32 > 0 and
+ *          a lowp format, FP32 within dist32 and 16-bit operands beyond.  band64 and band32
+ *          are then ignored; band0 must be -1; Euclidean sites only; needs a dataset (not
+ *          mpgeo_factor_dense).  0: the tile-offset bands above.
+ *  dist32: see dist64; 0 unless dist64 > 0 with a lowp format (then dist32 >= dist64). */
 typedef struct {
     int32_t tile;
     int32_t band64;
@@ -108,6 +115,8 @@ typedef struct {
     int32_t lowp;
     uint32_t flags;
     int32_t band0;
+    double dist64;
+    double dist32;
 } mpgeo_plan;
 
 /* Result of one evaluation.  loglik, logdet (natural log of det Sigma) and quad
@@ -229,7 +238,58 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
 int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda,
                        const double *z, mpgeo_plan plan, mpgeo_result *out);
 
-/* HBM bytes of the lower-triangle tiles for n and plan (admission control). */
+/* One problem of a batch: its own n sites (n x 2, host memory), data z (n, host) and theta. */
+typedef struct {
+    int64_t n;
+    const double *locs;
+    const double *z;
+    mpgeo_theta theta;
+} mpgeo_instance;
+
+/* Batched evaluation of eq. (2) for `count` independent problems (many small and medium
+ * likelihoods, e.g. one per region or per candidate model, Section VIII).  Every instance is
+ * Morton-ordered, tiled and factored with the plan's precision map, exactly as
+ * mpgeo_loglik would; the evaluations are spread over private lanes of the context (each its
+ * own pair of streams and workspace; MPGEO_BATCH_LANES, default 4) and enqueued without host
+ * synchronisation, largest first.  plan.tile = 0 selects the tile size per instance by an
+ * autotuner: for each half-octave of n (and precision plan) the first instance is timed with a
+ * tile covering it and with 128, 256, 384, 512 below n, and the fastest is kept in the context
+ * for later batches.  out[i] receives loglik, logdet, quad and info (times are 0); tiles, if
+ * not NULL, the tile size used.  Inputs are host memory (MPGEO_INPUT_DEVICE and MPGEO_TIMING
+ * are rejected).  Returns MPGEO_E_NOT_SPD if any instance failed (see out[i].info). */
+int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
+                       mpgeo_result *out, int32_t *tiles);
+
+/* Serving loop for many likelihood requests (the inner loop of many maximum-likelihood fits,
+ * Section VIII-E): datasets are registered once (host copies kept); requests (dataset, theta)
+ * are submitted with arrival times in seconds; mpgeo_server_run replays them in real time from
+ * its start: a request is ready at its arrival, and a dispatcher gives the oldest ready
+ * request whose dataset is idle to a free lane (lanes as in mpgeo_batch_loglik) without waiting
+ * for other requests.  A dataset's tiles stay resident on the device between its requests;
+ * a dataset is admitted when its tile footprint (mpgeo_footprint_bytes) fits in
+ * hbm_budget_bytes next to the resident ones, evicting idle datasets least recently used first.
+ * Results match mpgeo_dataset_loglik of the same dataset and theta (same kernels).  A server
+ * belongs to one context; run is synchronous and clears the submitted requests. */
+typedef struct mpgeo_server mpgeo_server;
+typedef struct {
+    double loglik, logdet, quad;
+    int64_t info;        /* -1, or the failing column (MPGEO_E_NOT_SPD is then returned) */
+    double arrival_s;    /* as submitted */
+    double start_s;      /* dispatched to a lane, seconds since the run began */
+    double finish_s;     /* completion observed by the dispatcher */
+} mpgeo_served;
+int mpgeo_server_create(mpgeo_ctx *ctx, uint64_t hbm_budget_bytes, int32_t lanes, mpgeo_server **out);
+/* MPGEO_E_NOMEM if the dataset could never fit in the budget. */
+int mpgeo_server_add_dataset(mpgeo_server *srv, int64_t n, const double *locs, const double *z,
+                             mpgeo_plan plan, int32_t *id);
+int mpgeo_server_submit(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, double arrival_s,
+                        int64_t *ticket);
+/* out: one entry per submitted request, in submission (ticket) order. */
+int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out);
+int mpgeo_server_destroy(mpgeo_server *srv);
+
+/* HBM bytes of the lower-triangle tiles for n and plan (admission control; for a map drawn
+ * from distances, which needs the sites, the all-FP64 bound). */
 size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan);
 
 /* The precision map of Algorithm 1 for n and plan, computed on the host (no device call):

@@ -32,7 +32,8 @@ EXPORTED = (
     "mpgeo_dataset_krige", "mpgeo_dataset_perm", "mpgeo_dataset_covariance",
     "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
     "mpgeo_footprint_bytes", "mpgeo_plan_tiers", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
-    "mpgeo_dataset_simulate",
+    "mpgeo_dataset_simulate", "mpgeo_batch_loglik", "mpgeo_server_create",
+    "mpgeo_server_add_dataset", "mpgeo_server_submit", "mpgeo_server_run", "mpgeo_server_destroy",
 )
 
 
@@ -42,7 +43,8 @@ class Theta(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("band64", ctypes.c_int32), ("band32", ctypes.c_int32),
-                ("lowp", ctypes.c_int32), ("flags", ctypes.c_uint32), ("band0", ctypes.c_int32)]
+                ("lowp", ctypes.c_int32), ("flags", ctypes.c_uint32), ("band0", ctypes.c_int32),
+                ("dist64", ctypes.c_double), ("dist32", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -50,6 +52,20 @@ class Result(ctypes.Structure):
                 ("info", ctypes.c_int64), ("t_covgen", ctypes.c_double),
                 ("t_factor", ctypes.c_double), ("t_solve", ctypes.c_double),
                 ("t_total", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("locs", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("theta", Theta)]
+
+
+class Served(ctypes.Structure):
+    _fields_ = [("loglik", ctypes.c_double), ("logdet", ctypes.c_double), ("quad", ctypes.c_double),
+                ("info", ctypes.c_int64), ("arrival_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("finish_s", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -105,6 +121,13 @@ def _load() -> ctypes.CDLL:
                                ctypes.POINTER(I32)], ctypes.c_int),
         "mpgeo_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "mpgeo_plan_tiers": ([I64, Plan, ctypes.POINTER(PlanTiers)], ctypes.c_int),
+        "mpgeo_batch_loglik": ([P, I64, ctypes.POINTER(Instance), Plan, ctypes.POINTER(Result),
+                                ctypes.POINTER(I32)], ctypes.c_int),
+        "mpgeo_server_create": ([P, ctypes.c_uint64, I32, ctypes.POINTER(P)], ctypes.c_int),
+        "mpgeo_server_add_dataset": ([P, I64, P, P, Plan, ctypes.POINTER(I32)], ctypes.c_int),
+        "mpgeo_server_submit": ([P, I32, Theta, D, ctypes.POINTER(I64)], ctypes.c_int),
+        "mpgeo_server_run": ([P, ctypes.POINTER(Served)], ctypes.c_int),
+        "mpgeo_server_destroy": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -142,12 +165,14 @@ LOWP = {None: 0, "fp16": 1, "bf16": 2}
 
 
 def make_plan(tile: int, band64: int, flags: int = 0, band32: int = -1, lowp=None,
-              band0: int = -1) -> Plan:
+              band0: int = -1, dist64: float = 0.0, dist32: float = 0.0) -> Plan:
     """Plan: FP64 within band64 tiles of the diagonal, FP32 beyond; with band32 >= 0 and
     lowp in {"fp16", "bf16"}, 16-bit operands for tiles farther than band64 + band32; with
-    band0 >= 0, tiles farther than band0 are dropped (zero)."""
+    band0 >= 0, tiles farther than band0 are dropped (zero).  dist64 > 0: the tiers are drawn
+    from the distance between the tiles' blocks of sites instead (FP64 within dist64, FP32
+    within dist32 when a 16-bit format is given, 16-bit beyond)."""
     return Plan(tile=tile, band64=band64, band32=band32, lowp=LOWP[lowp], flags=flags,
-                band0=band0)
+                band0=band0, dist64=dist64, dist32=dist32)
 
 
 def mpgeo_footprint_bytes(n: int, tile: int, band64: int, band32: int = -1, lowp=None,
@@ -219,6 +244,26 @@ class Context:
         _check(st, "mpgeo_factor_dense", res.info)
         return res.as_dict()
 
+    def batch_loglik(self, problems, tile: int = 0, band64: int = -1, band32: int = -1, lowp=None,
+                     profile: bool = False, gcd: bool = False, band0: int = -1) -> tuple:
+        """eq. (2) for many independent (locs, z, theta) problems in one call (host arrays).
+        tile = 0: tile size chosen per instance by the autotuner.  Returns (status, results,
+        tiles) without raising on non-positive-definite instances (their info is >= 0)."""
+        keep = []
+        arr = (Instance * max(1, len(problems)))()
+        for q, (locs, z, theta) in enumerate(problems):
+            locs, z = _host_f64(locs), _host_f64(z)
+            keep.append((locs, z))
+            arr[q] = Instance(int(locs.shape[0]), locs.ctypes.data, z.ctypes.data, Theta(*theta))
+        res = (Result * max(1, len(problems)))()
+        tiles = (ctypes.c_int32 * max(1, len(problems)))()
+        flags = (MPGEO_PROFILE if profile else 0) | (MPGEO_DIST_GCD if gcd else 0)
+        st = LIB.mpgeo_batch_loglik(self.handle, len(problems), arr,
+                                    make_plan(tile, band64, flags, band32, lowp, band0), res, tiles)
+        if st not in (MPGEO_OK, MPGEO_E_NOT_SPD):
+            _check(st, "mpgeo_batch_loglik")
+        return st, [res[q].as_dict() for q in range(len(problems))], [tiles[q] for q in range(len(problems))]
+
     def kernel_stats(self) -> list:
         arr = (KernelStat * 32)()
         count = ctypes.c_int()
@@ -263,11 +308,12 @@ class Dataset:
             pass
 
     def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False,
-               band32: int = -1, lowp=None, profile: bool = False, band0: int = -1) -> dict:
+               band32: int = -1, lowp=None, profile: bool = False, band0: int = -1,
+               dist64: float = 0.0, dist32: float = 0.0) -> dict:
         res = Result()
         flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0)
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
-                                      make_plan(tile, band64, flags, band32, lowp, band0),
+                                      make_plan(tile, band64, flags, band32, lowp, band0, dist64, dist32),
                                       ctypes.byref(res))
         _check(st, "mpgeo_dataset_loglik", res.info)
         return res.as_dict()
@@ -310,10 +356,11 @@ class Dataset:
         return out
 
     def covariance(self, theta: Sequence[float], tile: int, band64: int,
-                   profile: bool = False) -> np.ndarray:
+                   profile: bool = False, band32: int = -1, lowp=None, dist64: float = 0.0,
+                   dist32: float = 0.0) -> np.ndarray:
         """Sigma (the correlation matrix with profile=True) as stored in its tiles
         (tier-rounded), lower triangle, ordered."""
-        plan = make_plan(tile, band64, MPGEO_PROFILE if profile else 0)
+        plan = make_plan(tile, band64, MPGEO_PROFILE if profile else 0, band32, lowp, -1, dist64, dist32)
         _check(LIB.mpgeo_dataset_covariance(self.handle, Theta(*theta), plan),
                "mpgeo_dataset_covariance")
         return self.matrix()
@@ -352,3 +399,51 @@ class Dataset:
         out = np.empty(self.n)
         _check(LIB.mpgeo_dataset_solution(self.handle, out.ctypes.data), "mpgeo_dataset_solution")
         return out
+
+
+class Server:
+    """Serving loop: resident datasets, requests with arrival times, continuous dispatch."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, lanes: int = 4):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(LIB.mpgeo_server_create(ctx.handle, int(hbm_budget_bytes), lanes, ctypes.byref(h)),
+               "mpgeo_server_create")
+        self.handle = h
+        self.count = 0
+
+    def add_dataset(self, locs, z, tile: int, band64: int, band32: int = -1, lowp=None) -> int:
+        locs, z = _host_f64(locs), _host_f64(z)
+        out = ctypes.c_int32()
+        _check(LIB.mpgeo_server_add_dataset(self.handle, locs.shape[0], locs.ctypes.data, z.ctypes.data,
+                                            make_plan(tile, band64, 0, band32, lowp), ctypes.byref(out)),
+               "mpgeo_server_add_dataset")
+        return out.value
+
+    def submit(self, dataset: int, theta: Sequence[float], arrival_s: float) -> int:
+        t = ctypes.c_int64()
+        _check(LIB.mpgeo_server_submit(self.handle, dataset, Theta(*theta), float(arrival_s), ctypes.byref(t)),
+               "mpgeo_server_submit")
+        self.count += 1
+        return t.value
+
+    def run(self) -> tuple:
+        """Replays the submitted requests; returns (status, per-request dicts in ticket order)."""
+        out = (Served * max(1, self.count))()
+        st = LIB.mpgeo_server_run(self.handle, out)
+        if st not in (MPGEO_OK, MPGEO_E_NOT_SPD):
+            _check(st, "mpgeo_server_run")
+        res = [out[q].as_dict() for q in range(self.count)]
+        self.count = 0
+        return st, res
+
+    def close(self) -> None:
+        if self.handle:
+            LIB.mpgeo_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,9 +16,13 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <thread>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -46,11 +50,14 @@ int status_from(hipError_t e) {
         if (_s != MPGEO_OK) return _s;          \
     } while (0)
 
+// Device buffer that only grows.  Growing frees the old block, so it first waits for every
+// stream of the device: work already enqueued (another lane's evaluation, say) may still use it.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
     int ensure(size_t b) {
         if (b <= bytes && ptr) return MPGEO_OK;
+        if (ptr && hipDeviceSynchronize() != hipSuccess) (void)hipGetLastError();
         release();
         if (b == 0) return MPGEO_OK;
         hipError_t e = hipMalloc(&ptr, b);
@@ -78,6 +85,13 @@ struct Layout {
     int edge = 0;                             // low tier (16-bit operands) iff i - j > edge
     int zband = 0;                            // zero tier (dropped tiles) iff i - j > zband
     int lowp = 0;                             // 0: none, 1: FP16, 2: BF16
+    // precision map drawn from distances (dist64 > 0): the tier of each tile from the distance
+    // between the bounding boxes of its two blocks of sites, instead of from i - j
+    double dist64 = 0.0, dist32 = 0.0;
+    int lowp_req = 0;                         // the plan's 16-bit format (distance map only)
+    std::vector<signed char> tierv;           // per tri_index: 64, 32 or 16 (distance map only)
+    std::vector<TileIJ> trsm64, trsm32;       // panel tiles per step by tier (distance map only)
+    std::vector<int64_t> trsm64_b, trsm32_b;  // step k's section: [b[k], b[k+1])
     std::vector<int64_t> off;
     std::vector<TileIJ> all, list64, list32, list16;
     // per step k and tier (0: FP64, 1: FP32, 2: 16-bit operands): the list ranges of the bulk
@@ -91,11 +105,15 @@ struct Layout {
     int64_t n64 = 0, n32 = 0;                 // tiles per storage precision (FP32 holds tier 16)
     bool has_zero_tile = false;               // dropped tiles share one zero FP32 tile (index n32)
 
-    bool same(int64_t n_, int nb_, int band_, int edge_, int zband_, int lowp_) const {
-        return n == n_ && nb == nb_ && band == band_ && edge == edge_ && zband == zband_ && lowp == lowp_;
+    bool same(int64_t n_, int nb_, int band_, int edge_, int zband_, int lowp_, double d64 = 0.0,
+              double d32 = 0.0) const {
+        return n == n_ && nb == nb_ && band == band_ && edge == edge_ && zband == zband_ &&
+               lowp == lowp_ && dist64 == d64 && dist32 == d32;
     }
+    bool distance_map() const { return !tierv.empty(); }
     // tier of tile (i, j): 64, 32, 16, or 0 for a dropped tile
     int tier(int i, int j) const {
+        if (!tierv.empty()) return tierv[(size_t)tri_index(i, j)];
         const int d = i - j;
         return d > zband ? 0 : (d <= band ? 64 : (d <= edge ? 32 : 16));
     }
@@ -123,7 +141,9 @@ struct Layout {
     // ... and with panel k (K = rows(k))
     double update_flops(int i, int j, int k) const { return tile_flops(i, j) * rows(k); }
 
-    void build(int64_t n_, int nb_, int band64, int band32 = -1, int lowp_ = 0, int band0 = -1) {
+    // boxes: per tile row, {xmin, xmax, ymin, ymax} of its sites (distance map only)
+    void build(int64_t n_, int nb_, int band64, int band32 = -1, int lowp_ = 0, int band0 = -1,
+               const std::vector<double> *boxes = nullptr, double d64 = 0.0, double d32 = 0.0) {
         n = n_;
         nb = nb_;
         nbp = (nb + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
@@ -132,6 +152,38 @@ struct Layout {
         band = effective_band(p, band64, band0);
         edge = effective_edge(p, band64, band32, band0);
         lowp = (edge < std::min(zband, p - 1)) ? lowp_ : 0;
+        dist64 = d64;
+        dist32 = d32;
+        lowp_req = lowp_;
+        tierv.clear();
+        trsm64.clear();
+        trsm32.clear();
+        trsm64_b.assign(p + 1, 0);
+        trsm32_b.assign(p + 1, 0);
+        if (boxes && d64 > 0.0) {
+            // tile (i, j) is FP64 when its two blocks of sites come within d64 of each other (the
+            // diagonal always), FP32 within d32 when a 16-bit tier is asked for, 16-bit beyond
+            zband = p;
+            band = 0;
+            edge = p;
+            lowp = 0;
+            tierv.assign((size_t)p * (p + 1) / 2, 64);
+            for (int i = 0; i < p; ++i)
+                for (int j = 0; j < i; ++j) {
+                    const double *a = boxes->data() + 4 * i, *b = boxes->data() + 4 * j;
+                    const double dx = std::max(0.0, std::max(a[0] - b[1], b[0] - a[1]));
+                    const double dy = std::max(0.0, std::max(a[2] - b[3], b[2] - a[3]));
+                    const double d = std::sqrt(dx * dx + dy * dy);
+                    const int t = d <= d64 ? 64 : ((lowp_ == 0 || d <= d32) ? 32 : 16);
+                    tierv[(size_t)tri_index(i, j)] = (signed char)t;
+                    if (t == 16) lowp = lowp_;
+                }
+            for (int k = 0; k < p; ++k) {
+                for (int i = k + 1; i < p; ++i) (tier(i, k) == 64 ? trsm64 : trsm32).push_back({i, k});
+                trsm64_b[k + 1] = (int64_t)trsm64.size();
+                trsm32_b[k + 1] = (int64_t)trsm32.size();
+            }
+        }
         const int64_t nt = (int64_t)p * (p + 1) / 2;
         off.assign(nt, 0);
         all.clear();
@@ -220,7 +272,7 @@ struct Layout {
         for (int k = 0; k < p; ++k)
             for (int i = k + 1; i <= k + panel_count(k); ++i) {
                 const double f = (double)rows(i) * rows(k) * rows(k);   // triangular solve
-                if (i - k <= band) trsm64_flops[k] += f;
+                if (tier(i, k) == 64) trsm64_flops[k] += f;
                 else trsm32_flops[k] += f;
             }
     }
@@ -275,6 +327,13 @@ struct mpgeo_ctx {
     mpgeo_kernel_stat stats[kStatCount];
     bool timing = false;
     mpgeo_dataset *scratch_ds = nullptr;   // workspace of the one-shot calls
+    // batched evaluation: lanes (each its own streams, events and workspace) that run
+    // independent instances concurrently, and the tile sizes the autotuner measured, keyed by
+    // (half-octave bucket of n, precision plan)
+    std::vector<mpgeo_ctx *> lanes;
+    std::vector<mpgeo_dataset *> lane_ds;
+    std::map<std::string, int> tuned_tile;
+    DevBuf batch_res;                         // per-instance {loglik, logdet, quad, info}
 
     hipEvent_t take_event() {
         if (!spare.empty()) {
@@ -344,6 +403,7 @@ struct mpgeo_dataset {
     DevBuf p64, p32, linv, linv32, q16, qscale, qmax;
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
+    DevBuf fp64tab, trsm64l, trsm32l;   // distance-drawn precision map
     bool has_factor = false;
     mpgeo_theta theta{};      // theta of the resident factor (theta1 = 1 for a profile evaluation)
     bool profile = false;     // the last evaluation used the profile likelihood
@@ -362,6 +422,15 @@ int check_plan(const mpgeo_plan &pl) {
     if (pl.tile < 1 || pl.tile > kMaxTile) return MPGEO_E_ARG;
     if (pl.band64 < -1 || pl.band32 < -1 || pl.band0 < -1) return MPGEO_E_ARG;
     if (pl.lowp < 0 || pl.lowp > 2) return MPGEO_E_ARG;
+    if (!(pl.dist64 >= 0.0) || !(pl.dist32 >= 0.0) || !std::isfinite(pl.dist64) || !std::isfinite(pl.dist32))
+        return MPGEO_E_ARG;
+    if (pl.dist64 > 0.0) {   // precision map drawn from distances: its own third-tier switch
+        if (pl.band0 >= 0 || (pl.flags & MPGEO_DIST_GCD)) return MPGEO_E_ARG;
+        if ((pl.dist32 > 0.0) != (pl.lowp != 0) || (pl.dist32 > 0.0 && pl.dist32 < pl.dist64))
+            return MPGEO_E_ARG;
+        return MPGEO_OK;
+    }
+    if (pl.dist32 > 0.0) return MPGEO_E_ARG;
     if ((pl.band32 >= 0) != (pl.lowp != 0)) return MPGEO_E_ARG;   // a third tier needs its format
     return MPGEO_OK;
 }
@@ -373,6 +442,7 @@ TileMap tile_map(const mpgeo_dataset *ds) {
     m.pool64 = ds->pool64.as<double>();
     m.pool32 = ds->pool32.as<float>();
     m.band = L.band;
+    m.fp64tab = L.distance_map() ? ds->fp64tab.as<signed char>() : nullptr;
     m.nbp = L.nbp;
     m.nb = L.nb;
     m.p = L.p;
@@ -388,8 +458,34 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     const int band_eff = Layout::effective_band(p_new, pl.band64, pl.band0);
     const int edge_eff = Layout::effective_edge(p_new, pl.band64, pl.band32, pl.band0);
     const int lowp_eff = (edge_eff < std::min<int64_t>(zband_eff, p_new - 1)) ? pl.lowp : 0;
-    if (L.same(ds->n, pl.tile, band_eff, edge_eff, zband_eff, lowp_eff) && ds->off.ptr) return MPGEO_OK;
-    L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp, pl.band0);
+    const bool dmap = pl.dist64 > 0.0;
+    if (!dmap && !L.distance_map() && L.same(ds->n, pl.tile, band_eff, edge_eff, zband_eff, lowp_eff) &&
+        ds->off.ptr)
+        return MPGEO_OK;
+    if (dmap && L.distance_map() && L.n == ds->n && L.nb == pl.tile && L.dist64 == pl.dist64 &&
+        L.dist32 == pl.dist32 && L.lowp_req == pl.lowp && ds->off.ptr)
+        return MPGEO_OK;
+    std::vector<double> boxes;
+    if (dmap) {
+        // bounding box of each tile row's (ordered) sites, from a host copy of the locations
+        if (!ds->locs.ptr) return MPGEO_E_ARG;
+        std::vector<double> xy((size_t)ds->n * 2);
+        MPGEO_HIP(hipMemcpy(xy.data(), ds->locs.ptr, xy.size() * sizeof(double), hipMemcpyDeviceToHost));
+        const int64_t p = (ds->n + pl.tile - 1) / pl.tile;
+        boxes.assign((size_t)p * 4, 0.0);
+        for (int64_t i = 0; i < p; ++i) {
+            double b[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+            for (int64_t a = i * pl.tile; a < std::min<int64_t>(ds->n, (i + 1) * pl.tile); ++a) {
+                b[0] = std::min(b[0], xy[2 * a]);
+                b[1] = std::max(b[1], xy[2 * a]);
+                b[2] = std::min(b[2], xy[2 * a + 1]);
+                b[3] = std::max(b[3], xy[2 * a + 1]);
+            }
+            std::copy(b, b + 4, boxes.begin() + 4 * i);
+        }
+    }
+    L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp, pl.band0, dmap ? &boxes : nullptr,
+            pl.dist64, pl.dist32);
     ds->has_factor = false;
     const size_t te = (size_t)L.nbp * L.nbp;
     const size_t tiles32 = (size_t)L.n32 + (L.has_zero_tile ? 1 : 0);
@@ -416,6 +512,20 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     MPGEO_TRY(ds->info.ensure(sizeof(unsigned long long)));
     MPGEO_TRY(ds->result.ensure(4 * sizeof(double)));
     hipStream_t s = ds->ctx->stream;
+    if (L.distance_map()) {
+        MPGEO_TRY(ds->fp64tab.ensure(L.tierv.size()));
+        std::vector<signed char> flag(L.tierv.size());
+        for (size_t q = 0; q < flag.size(); ++q) flag[q] = L.tierv[q] == 64 ? 1 : 0;
+        MPGEO_HIP(hipMemcpy(ds->fp64tab.ptr, flag.data(), flag.size(), hipMemcpyHostToDevice));
+        MPGEO_TRY(ds->trsm64l.ensure(std::max<size_t>(1, L.trsm64.size()) * sizeof(TileIJ)));
+        MPGEO_TRY(ds->trsm32l.ensure(std::max<size_t>(1, L.trsm32.size()) * sizeof(TileIJ)));
+        if (!L.trsm64.empty())
+            MPGEO_HIP(hipMemcpy(ds->trsm64l.ptr, L.trsm64.data(), L.trsm64.size() * sizeof(TileIJ),
+                                hipMemcpyHostToDevice));
+        if (!L.trsm32.empty())
+            MPGEO_HIP(hipMemcpy(ds->trsm32l.ptr, L.trsm32.data(), L.trsm32.size() * sizeof(TileIJ),
+                                hipMemcpyHostToDevice));
+    }
     if (L.has_zero_tile)   // the shared tile every dropped tile maps to: zero, never written
         MPGEO_HIP(hipMemsetAsync(ds->pool32.as<float>() + (size_t)L.n32 * te, 0, te * sizeof(float), s));
     MPGEO_HIP(hipMemcpyAsync(ds->off.ptr, L.off.data(), L.off.size() * sizeof(int64_t),
@@ -570,15 +680,30 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         const bool quant = L.lowp_step(k);
         unsigned *amax = quant ? qmax(k) : nullptr;
         if (quant) (void)hipMemsetAsync(amax, 0, (size_t)p * sizeof(unsigned), s1);
-        if (n64 > 0)
-            ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
-                launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, amax, s1,
-                            /*narrow=*/true);
-            });
-        if (n32 > 0)
-            ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
-                launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, amax, s1);
-            });
+        if (L.distance_map()) {   // panel tiles of each precision as lists
+            const int64_t b64 = L.trsm64_b[k], c64 = L.trsm64_b[k + 1] - b64;
+            const int64_t b32 = L.trsm32_b[k], c32 = L.trsm32_b[k + 1] - b32;
+            if (c64 > 0)
+                ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)c64 * nbd * nbd * 8.0 * 2.0, [&] {
+                    launch_trsm(map, k, 0, (int)c64, true, pa.linv, pa.linv32, p64, p32, amax, s1,
+                                /*narrow=*/c64 <= 4, ds->trsm64l.as<TileIJ>() + b64);
+                });
+            if (c32 > 0)
+                ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)c32 * nbd * nbd * 4.0 * 2.0, [&] {
+                    launch_trsm(map, k, 0, (int)c32, false, pa.linv, pa.linv32, p64, p32, amax, s1,
+                                false, ds->trsm32l.as<TileIJ>() + b32);
+                });
+        } else {
+            if (n64 > 0)
+                ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
+                    launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, amax, s1,
+                                /*narrow=*/true);
+                });
+            if (n32 > 0)
+                ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
+                    launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, amax, s1);
+                });
+        }
         if (quant)   // 16-bit panel copy with per-tile power-of-two scales
             ctx->timed_on(s1, kStatQuant, 0.0, (double)npanel * nbd * nbd * 6.0, [&] {
                 launch_quantize(map, k + 1, npanel, p32, amax, qpanel(k), qscale(k), L.lowp, s1);
@@ -740,6 +865,7 @@ const char *mpgeo_status_string(int status) {
 size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
     if (n < 1 || check_plan(plan) != MPGEO_OK) return 0;
     Layout L;
+    if (plan.dist64 > 0.0) plan.band64 = -1;   // the map needs the sites: bound it by all-FP64
     L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp, plan.band0);
     const size_t te = (size_t)L.nbp * L.nbp;
     return (size_t)L.n64 * te * sizeof(double) +
@@ -774,7 +900,7 @@ static void create_bulk_stream(mpgeo_ctx *c) {
 }
 
 int mpgeo_plan_tiers(int64_t n, mpgeo_plan plan, mpgeo_tier_summary *out) {
-    if (!out || n < 1 || check_plan(plan) != MPGEO_OK) return MPGEO_E_ARG;
+    if (!out || n < 1 || check_plan(plan) != MPGEO_OK || plan.dist64 > 0.0) return MPGEO_E_ARG;
     Layout L;
     L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp, plan.band0);
     mpgeo_tier_summary info{};
@@ -844,6 +970,9 @@ int mpgeo_ctx_destroy(mpgeo_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch_ds) mpgeo_dataset_destroy(ctx->scratch_ds);
+    for (auto *d : ctx->lane_ds) mpgeo_dataset_destroy(d);
+    for (auto *c : ctx->lanes) mpgeo_ctx_destroy(c);
+    ctx->batch_res.release();
     ctx->collect();
     for (auto e : ctx->spare) (void)hipEventDestroy(e);
     for (auto e : ctx->sync_events) (void)hipEventDestroy(e);
@@ -898,7 +1027,8 @@ int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
                       &ds->pool64, &ds->pool32, &ds->off, &ds->all, &ds->list64, &ds->list32,
                       &ds->list16, &ds->q16, &ds->qscale, &ds->qmax,
                       &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
-                      &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c})
+                      &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c, &ds->fp64tab,
+                      &ds->trsm64l, &ds->trsm32l})
         b->release();
     delete ds;
     return MPGEO_OK;
@@ -1298,6 +1428,393 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
                       &ds.tmp_a, &ds.z})
         b->release();
     return st;
+}
+
+// ---- batched evaluation of independent instances ------------------------------------------
+// Lanes are private contexts (own stream pair, events and workspace); instances are dealt to
+// them largest first so that each lane's buffers reach their final size early, and every
+// evaluation is enqueued without a host synchronisation.  The tile size of an instance is the
+// plan's, or, with plan.tile = 0, the autotuner's choice for its half-octave of n.
+
+static int batch_lanes(mpgeo_ctx *ctx, int want) {
+    while ((int)ctx->lanes.size() < want) {
+        mpgeo_ctx *c = nullptr;
+        MPGEO_TRY(mpgeo_ctx_create(&c, ctx->device, nullptr));
+        ctx->lanes.push_back(c);
+        mpgeo_dataset *d = new mpgeo_dataset();
+        d->ctx = c;
+        ctx->lane_ds.push_back(d);
+    }
+    return MPGEO_OK;
+}
+
+// One evaluation enqueued on a lane; {loglik, logdet, quad, info bits} land in res_slot.  The
+// lane's previous evaluation is waited for first: its work lists were uploaded from the host
+// copy of the layout that this one rebuilds (so at most one evaluation per lane is in flight,
+// and the lanes keep the device busy together).
+static int batch_enqueue(mpgeo_dataset *ds, const mpgeo_instance &in, const mpgeo_plan &pl,
+                         double *res_slot) {
+    MPGEO_HIP(hipStreamSynchronize(ds->ctx->side));
+    MPGEO_HIP(hipStreamSynchronize(ds->ctx->stream));
+    ds->n = in.n;
+    ds->flags = pl.flags | MPGEO_ORDER_MORTON;
+    MPGEO_TRY(load_inputs(ds, in.locs, in.z, ds->flags));
+    MPGEO_TRY(prepare_layout(ds, pl));
+    ds->profile = (pl.flags & MPGEO_PROFILE) != 0;
+    mpgeo_theta th = in.theta;
+    if (ds->profile) th.sigma2 = 1.0;
+    MPGEO_TRY(run_covgen(ds, th));
+    MPGEO_TRY(run_factor(ds, nullptr));
+    hipStream_t s = ds->ctx->stream;
+    MPGEO_HIP(hipMemcpyAsync(res_slot, ds->result.ptr, 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MPGEO_HIP(hipMemcpyAsync(res_slot + 3, ds->info.ptr, sizeof(double), hipMemcpyDeviceToDevice, s));
+    ds->has_factor = false;   // the lane's workspace is reused by the next instance
+    return MPGEO_OK;
+}
+
+static void batch_sync(mpgeo_ctx *ctx) {
+    for (auto *c : ctx->lanes) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamSynchronize(c->stream);
+    }
+}
+
+// Tile size for an instance: the plan's, else the fastest of the candidates measured on the
+// first instance of its (half-octave of n, precision plan) class.  Candidates: one tile
+// covering the problem when it fits, and 128, 256, 384, 512 below n.
+static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, double *scratch,
+                      int *tile_out) {
+    if (pl.tile > 0) {
+        *tile_out = pl.tile;
+        return MPGEO_OK;
+    }
+    const int bucket = (int)std::floor(2.0 * std::log2((double)in.n));
+    const std::string key = std::to_string(bucket) + "/" + std::to_string(pl.band64) + "/" +
+                            std::to_string(pl.band32) + "/" + std::to_string(pl.lowp) + "/" +
+                            std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD)) + "/" +
+                            std::to_string(pl.band0);
+    auto it = ctx->tuned_tile.find(key);
+    if (it != ctx->tuned_tile.end()) {
+        *tile_out = it->second;
+        return MPGEO_OK;
+    }
+    std::vector<int> cand;
+    cand.push_back((int)std::min<int64_t>(in.n, kMaxTile));
+    for (int t : {128, 256, 384, 512})
+        if (t < in.n && t != cand[0]) cand.push_back(t);
+    mpgeo_dataset *ds = ctx->lane_ds[0];
+    hipStream_t st = ctx->lanes[0]->stream;
+    EventSet ev;
+    int best = cand[0];
+    double best_s = INFINITY;
+    for (int t : cand) {
+        mpgeo_plan q = pl;
+        q.tile = t;
+        MPGEO_TRY(batch_enqueue(ds, in, q, scratch));   // warm-up (allocations, layout)
+        batch_sync(ctx);
+        if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[0], st));
+        MPGEO_TRY(batch_enqueue(ds, in, q, scratch));
+        if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[1], st));
+        batch_sync(ctx);
+        const double sec = ev.secs(0, 1);
+        if (sec < best_s) {
+            best_s = sec;
+            best = t;
+        }
+    }
+    ctx->tuned_tile[key] = best;
+    *tile_out = best;
+    return MPGEO_OK;
+}
+
+int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
+                       mpgeo_result *out, int32_t *tiles) {
+    if (!ctx || count < 0 || (count > 0 && (!inst || !out))) return MPGEO_E_ARG;
+    if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
+    mpgeo_plan chk = plan;
+    if (chk.tile == 0) chk.tile = 1;
+    MPGEO_TRY(check_plan(chk));
+    for (int64_t i = 0; i < count; ++i) {
+        if (inst[i].n < 1 || inst[i].n > (int64_t)0xFFFFFFFF || !inst[i].locs || !inst[i].z)
+            return MPGEO_E_ARG;
+        MPGEO_TRY(check_theta(inst[i].theta));
+        out[i].info = -1;
+    }
+    if (count == 0) return MPGEO_OK;
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    int nlanes = 4;
+    if (const char *env = std::getenv("MPGEO_BATCH_LANES")) nlanes = std::max(1, std::atoi(env));
+    nlanes = (int)std::min<int64_t>(nlanes, count);
+    MPGEO_TRY(batch_lanes(ctx, nlanes));
+    MPGEO_TRY(ctx->batch_res.ensure((size_t)(count + 1) * 4 * sizeof(double)));
+    double *res = ctx->batch_res.as<double>();
+    std::vector<int> tile((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        const int st = batch_tile(ctx, inst[i], plan, res + 4 * count, &tile[(size_t)i]);
+        if (st != MPGEO_OK) {
+            batch_sync(ctx);
+            return st;
+        }
+    }
+    std::vector<int64_t> order((size_t)count);
+    for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return inst[a].n > inst[b].n; });
+    int status = MPGEO_OK;
+    for (int64_t q = 0; q < count && status == MPGEO_OK; ++q) {
+        const int64_t i = order[(size_t)q];
+        mpgeo_plan pl = plan;
+        pl.tile = tile[(size_t)i];
+        status = batch_enqueue(ctx->lane_ds[(size_t)(q % nlanes)], inst[i], pl, res + 4 * i);
+    }
+    batch_sync(ctx);
+    if (status != MPGEO_OK) return status;
+    std::vector<double> host((size_t)count * 4);
+    MPGEO_HIP(hipMemcpy(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count; ++i) {
+        const double *r = host.data() + 4 * i;
+        unsigned long long info;
+        std::memcpy(&info, r + 3, sizeof(info));
+        out[i] = mpgeo_result{};
+        out[i].loglik = r[0];
+        out[i].logdet = r[1];
+        out[i].quad = r[2];
+        out[i].info = (info == ~0ull) ? -1 : (int64_t)info;
+        if (out[i].info >= 0) status = MPGEO_E_NOT_SPD;
+        if (tiles) tiles[i] = tile[(size_t)i];
+    }
+    return status;
+}
+
+// ---- serving loop ---------------------------------------------------------------------------
+// Requests (dataset, theta) arrive over time; datasets keep their tiles resident on the device
+// while they fit in the HBM budget (admission by their tile footprint, least recently used
+// eviction of idle datasets); a dispatcher hands each ready request to a free lane as soon as
+// its dataset is resident and not busy, without waiting for the others (continuous batching
+// over the lanes), and records when each evaluation was dispatched and finished.
+
+struct ServedDataset {
+    int64_t n = 0;
+    std::vector<double> locs, z;       // host copies (re-uploaded after an eviction)
+    mpgeo_plan plan{};
+    size_t footprint = 0;
+    mpgeo_dataset *ds = nullptr;       // resident device state, or nullptr
+    bool busy = false;
+    double last_used = -1.0;
+};
+
+struct ServedRequest {
+    int32_t dataset;
+    mpgeo_theta theta;
+    double arrival;
+};
+
+struct mpgeo_server {
+    mpgeo_ctx *ctx = nullptr;
+    size_t budget = 0;
+    int nlanes = 0;
+    std::vector<ServedDataset> sets;
+    std::vector<ServedRequest> reqs;
+    size_t resident_bytes = 0;
+};
+
+int mpgeo_server_create(mpgeo_ctx *ctx, uint64_t hbm_budget_bytes, int32_t lanes, mpgeo_server **out) {
+    if (!ctx || !out || lanes < 1 || lanes > 64) return MPGEO_E_ARG;
+    *out = nullptr;
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    MPGEO_TRY(batch_lanes(ctx, lanes));
+    mpgeo_server *srv = new mpgeo_server();
+    srv->ctx = ctx;
+    srv->budget = hbm_budget_bytes;
+    srv->nlanes = lanes;
+    *out = srv;
+    return MPGEO_OK;
+}
+
+int mpgeo_server_add_dataset(mpgeo_server *srv, int64_t n, const double *locs, const double *z,
+                             mpgeo_plan plan, int32_t *id) {
+    if (!srv || !locs || !z || !id || n < 1 || n > (int64_t)0xFFFFFFFF) return MPGEO_E_ARG;
+    if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
+    MPGEO_TRY(check_plan(plan));
+    ServedDataset d;
+    d.n = n;
+    d.locs.assign(locs, locs + 2 * n);
+    d.z.assign(z, z + n);
+    d.plan = plan;
+    d.footprint = mpgeo_footprint_bytes(n, plan);
+    if (d.footprint > srv->budget) return MPGEO_E_NOMEM;   // could never be admitted
+    srv->sets.push_back(std::move(d));
+    *id = (int32_t)(srv->sets.size() - 1);
+    return MPGEO_OK;
+}
+
+int mpgeo_server_submit(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, double arrival_s,
+                        int64_t *ticket) {
+    if (!srv || dataset < 0 || dataset >= (int32_t)srv->sets.size() || !(arrival_s >= 0.0))
+        return MPGEO_E_ARG;
+    MPGEO_TRY(check_theta(theta));
+    srv->reqs.push_back({dataset, theta, arrival_s});
+    if (ticket) *ticket = (int64_t)srv->reqs.size() - 1;
+    return MPGEO_OK;
+}
+
+// release the device state of an idle dataset
+static void server_evict(mpgeo_server *srv, ServedDataset &d) {
+    if (!d.ds) return;
+    mpgeo_dataset_destroy(d.ds);   // synchronises the lane stream it last ran on
+    d.ds = nullptr;
+    srv->resident_bytes -= d.footprint;
+}
+
+// make room for `need` bytes by evicting idle datasets, least recently used first
+static bool server_admit(mpgeo_server *srv, size_t need) {
+    while (srv->resident_bytes + need > srv->budget) {
+        ServedDataset *victim = nullptr;
+        for (auto &d : srv->sets)
+            if (d.ds && !d.busy && (!victim || d.last_used < victim->last_used)) victim = &d;
+        if (!victim) return false;
+        server_evict(srv, *victim);
+    }
+    return true;
+}
+
+int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
+    if (!srv || (!srv->reqs.empty() && !out)) return MPGEO_E_ARG;
+    mpgeo_ctx *ctx = srv->ctx;
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    const int64_t nreq = (int64_t)srv->reqs.size();
+    if (nreq == 0) return MPGEO_OK;
+    MPGEO_TRY(ctx->batch_res.ensure((size_t)nreq * 4 * sizeof(double)));
+    double *res = ctx->batch_res.as<double>();
+    std::vector<int64_t> order((size_t)nreq);
+    for (int64_t i = 0; i < nreq; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return srv->reqs[a].arrival < srv->reqs[b].arrival; });
+    struct LaneState {
+        int64_t req = -1;
+        hipEvent_t done = nullptr;
+    };
+    std::vector<LaneState> lanes((size_t)srv->nlanes);
+    for (auto &l : lanes)
+        if (hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            for (auto &m : lanes)
+                if (m.done) (void)hipEventDestroy(m.done);
+            return MPGEO_E_DEVICE;
+        }
+    for (int64_t i = 0; i < nreq; ++i) out[i] = mpgeo_served{};
+    std::deque<int64_t> ready;
+    size_t next = 0;
+    int64_t finished = 0;
+    int status = MPGEO_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    while (finished < nreq && status == MPGEO_OK) {
+        const double t = now();
+        while (next < order.size() && srv->reqs[order[next]].arrival <= t) ready.push_back(order[next++]);
+        bool progressed = false;
+        // completions
+        for (auto &l : lanes) {
+            if (l.req < 0) continue;
+            const hipError_t q = hipEventQuery(l.done);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                (void)hipGetLastError();
+                status = MPGEO_E_DEVICE;
+                break;
+            }
+            out[l.req].finish_s = now();
+            srv->sets[srv->reqs[l.req].dataset].busy = false;
+            l.req = -1;
+            ++finished;
+            progressed = true;
+        }
+        // dispatch: oldest ready request whose dataset is idle (and resident or admissible)
+        for (int li = 0; li < srv->nlanes && status == MPGEO_OK; ++li) {
+            LaneState &l = lanes[(size_t)li];
+            if (l.req >= 0) continue;
+            auto it = ready.begin();
+            for (; it != ready.end(); ++it) {
+                ServedDataset &d = srv->sets[srv->reqs[*it].dataset];
+                if (d.busy) continue;
+                if (d.ds || server_admit(srv, d.footprint)) break;
+            }
+            if (it == ready.end()) break;
+            const int64_t r = *it;
+            ready.erase(it);
+            ServedRequest &rq = srv->reqs[r];
+            ServedDataset &d = srv->sets[rq.dataset];
+            mpgeo_ctx *lc = ctx->lanes[(size_t)li];
+            if (!d.ds) {   // admission: resident device copy of the ordered inputs
+                d.ds = new mpgeo_dataset();
+                d.ds->ctx = lc;
+                d.ds->n = d.n;
+                d.ds->flags = d.plan.flags | MPGEO_ORDER_MORTON;
+                srv->resident_bytes += d.footprint;
+                status = load_inputs(d.ds, d.locs.data(), d.z.data(), d.ds->flags);
+                if (status != MPGEO_OK) break;
+            }
+            if (d.ds->ctx != lc) {   // the dataset moves to this lane: order after its last use
+                MPGEO_HIP(hipStreamSynchronize(d.ds->ctx->stream));
+                d.ds->ctx = lc;
+            }
+            d.busy = true;
+            d.last_used = now();
+            out[r].start_s = d.last_used;
+            mpgeo_plan pl = d.plan;
+            status = prepare_layout(d.ds, pl);
+            if (status != MPGEO_OK) break;
+            d.ds->profile = (pl.flags & MPGEO_PROFILE) != 0;
+            mpgeo_theta th = rq.theta;
+            if (d.ds->profile) th.sigma2 = 1.0;
+            status = run_covgen(d.ds, th);
+            if (status == MPGEO_OK) status = run_factor(d.ds, nullptr);
+            if (status != MPGEO_OK) break;
+            double *slot = res + 4 * r;
+            MPGEO_HIP(hipMemcpyAsync(slot, d.ds->result.ptr, 3 * sizeof(double), hipMemcpyDeviceToDevice, lc->stream));
+            MPGEO_HIP(hipMemcpyAsync(slot + 3, d.ds->info.ptr, sizeof(double), hipMemcpyDeviceToDevice, lc->stream));
+            MPGEO_HIP(hipEventRecord(l.done, lc->stream));
+            l.req = r;
+            progressed = true;
+        }
+        if (!progressed) {
+            // idle until the next arrival or a completion: short sleeps, no busy spin
+            const double wake = next < order.size() ? srv->reqs[order[next]].arrival : INFINITY;
+            const double dt = std::min(2e-4, std::max(0.0, wake - now()));
+            if (dt > 0) std::this_thread::sleep_for(std::chrono::duration<double>(dt));
+        }
+    }
+    for (auto *c : ctx->lanes) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    for (auto &l : lanes) (void)hipEventDestroy(l.done);
+    if (status != MPGEO_OK) return status;
+    std::vector<double> host((size_t)nreq * 4);
+    MPGEO_HIP(hipMemcpy(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nreq; ++i) {
+        const double *rr = host.data() + 4 * i;
+        unsigned long long info;
+        std::memcpy(&info, rr + 3, sizeof(info));
+        out[i].loglik = rr[0];
+        out[i].logdet = rr[1];
+        out[i].quad = rr[2];
+        out[i].info = (info == ~0ull) ? -1 : (int64_t)info;
+        out[i].arrival_s = srv->reqs[(size_t)i].arrival;
+        if (out[i].info >= 0) status = MPGEO_E_NOT_SPD;
+    }
+    srv->reqs.clear();
+    return status;
+}
+
+int mpgeo_server_destroy(mpgeo_server *srv) {
+    if (!srv) return MPGEO_OK;
+    Device dev(srv->ctx->device);
+    for (auto &d : srv->sets) server_evict(srv, d);
+    delete srv;
+    return MPGEO_OK;
 }
 
 }  // extern "C"

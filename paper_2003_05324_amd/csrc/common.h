@@ -27,7 +27,8 @@ __host__ __device__ inline int64_t tri_index(int64_t i, int64_t j) {
 }
 
 // Where the tiles live: one pool per precision; off[tri_index(i, j)] is the element
-// offset of tile (i, j) inside the pool of its precision (FP64 iff i - j <= band).
+// offset of tile (i, j) inside the pool of its precision (FP64 iff i - j <= band, or, for a
+// precision map drawn from distances, iff fp64tab[tri_index(i, j)] is non-zero).
 struct TileMap {
     const int64_t *off;
     double *pool64;
@@ -37,10 +38,11 @@ struct TileMap {
     int nb;     // logical tile size
     int p;      // tiles per side
     int64_t n;  // logical matrix order
+    const signed char *fp64tab = nullptr;   // per-tile FP64 flag (distance map), or nullptr
 };
 
 __host__ __device__ inline bool tile_is_fp64(const TileMap &m, int i, int j) {
-    return (i - j) <= m.band;
+    return m.fp64tab ? m.fp64tab[tri_index(i, j)] != 0 : (i - j) <= m.band;
 }
 
 // ---- launchers (host functions; every kernel is enqueued on `stream`) -------------
@@ -105,10 +107,12 @@ void launch_potrf(const PotrfArgs &a, hipStream_t stream);
 // Panel TRSM of step k through the explicit inverse: X_i = A_ik L_kk^-T for
 // i in [i_begin, i_begin + count); writes the staging panels P64[i], P32[i] and, when absmax
 // is not null, raises absmax[i] (float bits) to max |P32[i]| (for the third tier's scales).
+// Panel TRSM of step k for panel tiles i_begin .. i_begin+count-1, or, when `list` is not
+// null, for the tiles list[0 .. count-1] (their .i; a precision map drawn from distances).
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64,
                  const double *linv, const float *linv32, double *p64, float *p32,
-                 unsigned *absmax, hipStream_t stream,
-                 bool narrow = false);
+                 unsigned *absmax, hipStream_t stream, bool narrow = false,
+                 const TileIJ *list = nullptr);
 
 // Trailing update of step k: A_ij -= P_i P_j^T over list[0, count) (tiles all of one
 // precision), with P the staging panel of that precision.

@@ -49,7 +49,7 @@ enum Epilogue { kUpdate = 0, kTrsm = 1 };
 struct GemmArgs {
     TileMap map;
     int64_t ntiles;       // output tiles in this launch
-    const TileIJ *list;   // update: output tiles (i, j)
+    const TileIJ *list;   // update: output tiles (i, j); trsm: panel tiles (i, k), or null for a range
     int k;                // step (trsm: panel column; output rows i = i_begin + tile)
     int i_begin;
     const void *panel;    // update: staging panel of the kernel's precision (tile i at i*nbp^2)
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(S::kThreads) void tile_gemm_kernel(GemmArgs g) {
         R = panel + (int64_t)ti * nbp * nbp;
         Q = panel + (int64_t)tj * nbp * nbp;
     } else {
-        ti = g.i_begin + tile;
+        ti = g.list ? g.list[tile].i : g.i_begin + tile;
         tj = g.k;
         const int64_t off = g.map.off[tri_index(ti, tj)];
         R = (sizeof(T) == 8) ? reinterpret_cast<const T *>(g.map.pool64 + off)
@@ -298,12 +298,13 @@ void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream, bool nar
 
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, const double *linv,
                  const float *linv32, double *p64, float *p32, unsigned *absmax,
-                 hipStream_t stream, bool narrow) {
+                 hipStream_t stream, bool narrow, const TileIJ *list) {
     if (count <= 0) return;
     GemmArgs g{};
     g.map = map;
     g.k = k;
     g.i_begin = i_begin;
+    g.list = list;
     g.p64 = p64;
     g.p32 = p32;
     g.absmax = absmax;

@@ -123,3 +123,20 @@ SWEEP = [sweep_field(b, v, i) for i, (b, v) in
 # 2,000 held-out prediction sites.
 LARGE = Workload("matern-n99856-nb512-band2", m=316, theta=(1.0, 0.1, 0.5), tile=512,
                  band64=2, loc_seed=301, z_seed=302, heldout_seed=303, heldout=2000)
+
+
+def batch_instances(count: int, seed: int, n_min: int = 500, n_max: int = 8000):
+    """Independent problems for the batched path: n log-uniform in [n_min, n_max], sites the
+    first n points of a jittered ceil(sqrt(n))-side grid, z standard normal, theta with
+    sigma2 ~ U[0.5, 2], beta ~ U[0.02, 0.3], nu in {0.5, 1.5}.  Returns (locs, z, theta) tuples."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+        m = int(np.ceil(np.sqrt(n)))
+        locs = jittered_grid(m, seed * 1000 + q)[:n].copy()
+        z = normals(n, seed * 1000 + 500 + q)
+        theta = (float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.02, 0.3)),
+                 float(rng.choice([0.5, 1.5])))
+        out.append((locs, z, theta))
+    return out

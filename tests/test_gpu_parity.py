@@ -8,6 +8,7 @@ Tolerances:
     sides elementary) and 5e-13 for general nu (the oracle's Bessel routine itself is good
     to about 1e-13 near x = 2); FP32 tiles within one FP32 ulp of the oracle value.
 """
+import ctypes
 import functools
 import json
 import math
@@ -489,3 +490,83 @@ def test_dropped_tiles_match_the_truncated_matrix(small_ds, theta, band0, band, 
     if band0 < 2:
         far = small_ds.entries(np.array([len(z) - 1]), np.array([0]))
         assert far[0] == 0.0
+
+
+# ---- precision map drawn from distances -----------------------------------------------------
+def _tile_box_distances(ordered, tile):
+    p = -(-len(ordered) // tile)
+    boxes = []
+    for i in range(p):
+        blk = ordered[i * tile:(i + 1) * tile]
+        boxes.append((blk[:, 0].min(), blk[:, 0].max(), blk[:, 1].min(), blk[:, 1].max()))
+    d = np.zeros((p, p))
+    for i in range(p):
+        for j in range(p):
+            a, b = boxes[i], boxes[j]
+            dx = max(0.0, a[0] - b[1], b[0] - a[1])
+            dy = max(0.0, a[2] - b[3], b[2] - a[3])
+            d[i, j] = math.hypot(dx, dy)
+    return d
+
+
+@pytest.mark.parametrize("dist64", [0.02, 0.1, 0.3])
+def test_distance_map_tiers_follow_tile_distances(small_ds, dist64):
+    locs, z = small_case()
+    perm = small_ds.perm()
+    x = locs[perm]
+    tile = SMALL.tile
+    got = small_ds.covariance(SMALL.theta, tile, -1, dist64=dist64)
+    want = oracle.matern_matrix(x, SMALL.theta)
+    d = _tile_box_distances(x, tile)
+    p = d.shape[0]
+    n64 = 0
+    for i in range(p):
+        for j in range(i + 1):
+            g = got[i * tile:(i + 1) * tile, j * tile:(j + 1) * tile]
+            w = want[i * tile:(i + 1) * tile, j * tile:(j + 1) * tile]
+            if i == j:
+                g, w = np.tril(g), np.tril(w)
+            if i == j or d[i, j] <= dist64:
+                n64 += 1
+                np.testing.assert_allclose(g, w, rtol=1e-13, atol=0)
+            else:
+                np.testing.assert_array_equal(g, w.astype(np.float32).astype(np.float64))
+    assert n64 >= p
+
+
+@pytest.mark.parametrize("dist64,tol", [(0.05, 1e-5), (0.2, 1e-5), (10.0, 1e-10)])
+def test_distance_map_matches_oracle(small_ds, dist64, tol):
+    want = small_oracle(SMALL.theta)
+    got = small_ds.loglik(SMALL.theta, SMALL.tile, -1, dist64=dist64)
+    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n) <= tol
+    if dist64 >= 10.0:   # every tile FP64: the all-FP64 path
+        full = small_ds.loglik(SMALL.theta, SMALL.tile, -1)
+        assert rel(got["loglik"], full["loglik"]) <= 1e-12
+
+
+@pytest.mark.parametrize("lowp", ["fp16", "bf16"])
+def test_distance_map_three_tiers(small_ds, lowp):
+    want = small_oracle(SMALL.theta)
+    got = small_ds.loglik(SMALL.theta, SMALL.tile, -1, lowp=lowp, dist64=0.05, dist32=0.2)
+    err = abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n)
+    assert err <= LOWP_TOL[lowp], err
+
+
+def test_distance_map_plan_validation(lib, ctx, small_ds):
+    bad = [dict(dist64=0.1, band0=2), dict(dist64=-1.0), dict(dist64=0.1, dist32=0.2),
+           dict(dist64=0.2, dist32=0.1, lowp="fp16"), dict(dist32=0.1)]
+    for kw in bad:
+        res = lib.Result()
+        plan = lib.make_plan(SMALL.tile, -1, 0, -1, kw.get("lowp"), kw.get("band0", -1),
+                             kw.get("dist64", 0.0), kw.get("dist32", 0.0))
+        st = lib.LIB.mpgeo_dataset_loglik(small_ds.handle, lib.Theta(*SMALL.theta), plan,
+                                          ctypes.byref(res))
+        assert st == lib.MPGEO_E_ARG, kw
+    # the map needs sites: not available for a caller's matrix
+    from synthetic import random_spd
+    a = np.asfortranarray(random_spd(64, 1))
+    res = lib.Result()
+    st = lib.LIB.mpgeo_factor_dense(ctx.handle, 64, a.ctypes.data, 64, None,
+                                    lib.make_plan(32, -1, 0, -1, None, -1, 0.1, 0.0),
+                                    ctypes.byref(res))
+    assert st == lib.MPGEO_E_ARG

@@ -1,0 +1,45 @@
+"""Serving loop: every result equals the same evaluation done alone, whatever the mix, the
+lane it ran on or an eviction and re-admission of its dataset in between."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import jittered_grid, normals
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_isolated_evaluations(lib):
+    ctx = lib.Context(0)
+    sizes = [300, 700, 1100, 1500]
+    data = [(jittered_grid(int(np.ceil(np.sqrt(n))), 40 + q)[:n].copy(), normals(n, 50 + q))
+            for q, n in enumerate(sizes)]
+    foot = sorted(lib.mpgeo_footprint_bytes(n, 128, 1) for n in sizes)
+    srv = lib.Server(ctx, hbm_budget_bytes=foot[-1] + foot[-2], lanes=3)   # two resident at most
+    ids = [srv.add_dataset(locs, z, 128, 1) for locs, z in data]
+    rng = np.random.default_rng(3)
+    reqs = []
+    for q in range(14):
+        d = int(rng.integers(0, len(sizes)))
+        theta = (float(np.exp(rng.normal(0, 0.2))), float(0.1 * np.exp(rng.normal(0, 0.2))), 0.5)
+        t = srv.submit(ids[d], theta, 0.02 * q)
+        reqs.append((t, d, theta))
+    st, out = srv.run()
+    assert st == 0
+    for t, d, theta in reqs:
+        r = out[t]
+        assert r["info"] == -1
+        assert r["arrival_s"] <= r["start_s"] + 1e-9 and r["start_s"] <= r["finish_s"]
+        ds = lib.Dataset(ctx, *data[d])
+        alone = ds.loglik(theta, 128, 1)
+        ds.close()
+        assert r["loglik"] == alone["loglik"] and r["logdet"] == alone["logdet"], (t, d)
+        want = oracle.loglik(data[d][0], data[d][1], theta)["loglik"]
+        assert abs(r["loglik"] - want) / max(abs(want), sizes[d]) <= 1e-5
+    # a dataset larger than the whole budget is refused up front
+    with pytest.raises(lib.MpgeoError) as e:
+        big = jittered_grid(60, 9)
+        srv.add_dataset(big, normals(len(big), 9), 128, -1)
+    assert e.value.status == lib.MPGEO_E_NOMEM
+    srv.close()
+    ctx.close()
