@@ -96,11 +96,16 @@ struct Layout {
     std::vector<TileIJ> all, list64, list32, list16;
     // per step k and tier (0: FP64, 1: FP32, 2: 16-bit operands): the list ranges of the bulk
     // update (tile columns j >= k+2) and of the lookahead column j = k+1, with their flops
+    // The 16-bit tier is left-looking: bulk[2][k] is column k+2's 16-bit tiles, which take
+    // panels 0 .. k in one pass (rows i > zband + k' skip the dropped panels k' < i - zband);
+    // col[2][k] gives column k+1 its last panel k.  Tiles of later columns wait untouched.
     struct Range {
         int64_t b = 0, e = 0;
         double flops = 0.0;
+        double panels = 0.0;   // bulk[2] only: 16-bit operand tiles read (rows i and row j)
     };
     std::vector<Range> bulk[3], col[3];
+    std::vector<char> needq;                  // panel k has a 16-bit copy (some later use)
     std::vector<double> trsm64_flops, trsm32_flops;
     int64_t n64 = 0, n32 = 0;                 // tiles per storage precision (FP32 holds tier 16)
     bool has_zero_tile = false;               // dropped tiles share one zero FP32 tile (index n32)
@@ -256,6 +261,10 @@ struct Layout {
                         col[q][k].flops += update_flops(i, k + 1, k);
                     }
                     col[q][k].e = bulk[q][k].b = (int64_t)lists[q]->size();
+                    if (q == 2) {   // the 16-bit tier's bulk is set below (left-looking)
+                        bulk[q][k].e = bulk[q][k].b;
+                        continue;
+                    }
                     for (int j = last; j >= k + 2; --j)
                         for (int i = j; i <= last; ++i) {
                             const int t = tier(i, j);
@@ -267,6 +276,33 @@ struct Layout {
                 }
             }
         }
+        // left-looking 16-bit tier: step k's bulk is column k+2, panels [max(0, i - zband), k]
+        needq.assign(p, 0);
+        std::vector<int> kmin_at(p, p);   // first panel any tile of step k's bulk takes
+        for (int k = 0; k + 1 < p; ++k) {
+            Range agg;
+            if (k + 2 < p) {
+                agg.b = col[2][k + 1].b;
+                agg.e = col[2][k + 1].e;
+                int kmin = k + 1;
+                for (int64_t t = agg.b; t < agg.e; ++t) {
+                    const TileIJ ij = list16[(size_t)t];
+                    const int k0 = std::max(0, ij.i - zband);
+                    for (int kk = k0; kk <= k; ++kk) agg.flops += update_flops(ij.i, ij.j, kk);
+                    agg.panels += std::max(0, k + 1 - k0);
+                    kmin = std::min(kmin, k0);
+                }
+                if (agg.e > agg.b) agg.panels += std::max(0, k + 1 - kmin);   // row j's tiles
+                if (agg.e > agg.b) kmin_at[k] = kmin;
+            }
+            bulk[2][k] = agg;
+        }
+        // panel k is an operand of the column update of step k or of a bulk pass of a later step
+        int suffix_min = p;
+        for (int k = p - 2; k >= 0; --k) {
+            suffix_min = std::min(suffix_min, kmin_at[k]);
+            needq[k] = lowp && (col[2][k].e > col[2][k].b || suffix_min <= k);
+        }
         trsm64_flops.assign(p, 0.0);
         trsm32_flops.assign(p, 0.0);
         for (int k = 0; k < p; ++k)
@@ -276,10 +312,8 @@ struct Layout {
                 else trsm32_flops[k] += f;
             }
     }
-    // step k has updates in the 16-bit tier
-    bool lowp_step(int k) const {
-        return lowp && k + 1 < p && (bulk[2][k].e > bulk[2][k].b || col[2][k].e > col[2][k].b);
-    }
+    // panel k is quantised to the 16-bit factor copy
+    bool lowp_step(int k) const { return lowp && k + 1 < p && needq[k]; }
 };
 
 enum StatClass {
@@ -497,9 +531,11 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     MPGEO_TRY(ds->list32.ensure(std::max<size_t>(1, L.list32.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list16.ensure(std::max<size_t>(1, L.list16.size()) * sizeof(TileIJ)));
     if (L.lowp) {
-        MPGEO_TRY(ds->q16.ensure(2 * (size_t)L.p * te * 2));                 // two steps in flight
-        MPGEO_TRY(ds->qscale.ensure(2 * (size_t)L.p * sizeof(float)));
-        MPGEO_TRY(ds->qmax.ensure(2 * (size_t)L.p * sizeof(unsigned)));
+        // 16-bit copy of the factor's tiles (slot tri_index(i, k)) and their scales
+        const size_t slots = (size_t)L.p * (L.p + 1) / 2;
+        MPGEO_TRY(ds->q16.ensure(slots * te * 2));
+        MPGEO_TRY(ds->qscale.ensure(slots * sizeof(float)));
+        MPGEO_TRY(ds->qmax.ensure(2 * (size_t)L.p * sizeof(unsigned)));   // two steps in flight
     }
     MPGEO_TRY(ds->p64.ensure(2 * (size_t)L.p * te * sizeof(double)));   // two steps in flight
     MPGEO_TRY(ds->p32.ensure(2 * (size_t)L.p * te * sizeof(float)));
@@ -618,6 +654,8 @@ int run_covgen(mpgeo_dataset *ds, const mpgeo_theta &th) {
 //   F(k)        = POTRF + TRSM + panel solve of step k            (side stream)
 //   U_col(k)    = update of column k+1 with panel k               (side; after U_bulk(k-1))
 //   U_bulk(k)   = update of columns >= k+2 with panel k           (main; after F(k))
+// except in the 16-bit tier, whose tiles wait: U_bulk(k) gives column k+2's 16-bit tiles
+// panels 0 .. k at once from the 16-bit factor copy, and U_col(k+1) adds panel k+1.
 int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     mpgeo_ctx *ctx = ds->ctx;
     hipStream_t s0 = ctx->stream;
@@ -645,8 +683,8 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     const TileIJ *l64 = ds->list64.as<TileIJ>();
     const TileIJ *l32 = ds->list32.as<TileIJ>();
     const TileIJ *l16 = ds->list16.as<TileIJ>();
-    auto qpanel = [&](int k) { return static_cast<void *>(ds->q16.as<char>() + (size_t)(k & 1) * p * te * 2); };
-    auto qscale = [&](int k) { return ds->qscale.as<float>() + (size_t)(k & 1) * p; };
+    void *q16 = ds->q16.ptr;                    // 16-bit factor copy, tile (i, k) at tri_index(i, k)
+    float *qscale = ds->qscale.as<float>();
     auto qmax = [&](int k) { return ds->qmax.as<unsigned>() + (size_t)(k & 1) * p; };
 
     auto panel64 = [&](int k) { return ds->p64.as<double>() + (size_t)(k & 1) * p * te; };
@@ -706,22 +744,27 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         }
         if (quant)   // 16-bit panel copy with per-tile power-of-two scales
             ctx->timed_on(s1, kStatQuant, 0.0, (double)npanel * nbd * nbd * 6.0, [&] {
-                launch_quantize(map, k + 1, npanel, p32, amax, qpanel(k), qscale(k), L.lowp, s1);
+                launch_quantize(map, k, k + 1, npanel, p32, amax, q16, qscale, L.lowp, s1);
             });
         ctx->timed_on(s1, kStatPanel, 2.0 * npanel * nbd * nbd, (double)npanel * nbd * nbd * 16.0,
                       [&] { launch_panel_solve(map, k, npanel, p64, pa.y, r, s1); });
     };
-    // update of list entries [b, e) of each tier with panel k on stream st.  Algorithmic
-    // bytes: every output tile read and written once, every panel tile it needs read once
-    // (at most p - 1 - k distinct panel tiles, at most two per output tile).
+    // update of list entries [b, e) of each tier with panel k on stream st; the 16-bit entries
+    // take panels [kbeg16, k] (the bulk pass: kbeg16 = 0; the lookahead column: kbeg16 = k).
+    // Algorithmic bytes: every output tile read and written once, every operand tile it needs
+    // read once (FP64/FP32: at most p - 1 - k distinct panel tiles, at most two per output
+    // tile; 16-bit bulk: the operand tiles counted by the layout).
     auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, int64_t b16,
-                            int64_t e16, double f64, double f32, double f16, hipStream_t st) {
+                            int64_t e16, double f64, double f32, double f16, int kbeg16,
+                            double panels16, hipStream_t st) {
         const double tile_elems = (double)nbd * nbd;
         auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(L.panel_count(k), 2 * count); };
         if (e16 > b16)
             ctx->timed_on(st, kStatUpdate16, f16,
-                          tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 + panel_tiles(e16 - b16) * 2.0), [&] {
-                launch_update_lowp(map, l16 + b16, e16 - b16, qpanel(k), qscale(k), L.lowp, st);
+                          tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 +
+                                        (kbeg16 == k ? panel_tiles(e16 - b16) : panels16) * 2.0), [&] {
+                launch_update_lowp(map, l16 + b16, e16 - b16, kbeg16, k + 1, L.zband, q16, qscale,
+                                   L.lowp, st);
             });
         if (e64 > b64)
             ctx->timed_on(st, kStatUpdate64, f64,
@@ -744,14 +787,14 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         if (k + 1 < p)
             update_range(k, L.bulk[0][k].b, L.bulk[0][k].e, L.bulk[1][k].b, L.bulk[1][k].e,
                          L.bulk[2][k].b, L.bulk[2][k].e, L.bulk[0][k].flops, L.bulk[1][k].flops,
-                         L.bulk[2][k].flops, sb);
+                         L.bulk[2][k].flops, 0, L.bulk[2][k].panels, sb);
         MPGEO_HIP(hipEventRecord(ev_bulk[k], sb));
         if (k + 1 < p) {
             // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
             update_range(k, L.col[0][k].b, L.col[0][k].e, L.col[1][k].b, L.col[1][k].e,
                          L.col[2][k].b, L.col[2][k].e, L.col[0][k].flops, L.col[1][k].flops,
-                         L.col[2][k].flops, s1);
+                         L.col[2][k].flops, k, 0.0, s1);
             factor_step(k + 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
@@ -868,8 +911,9 @@ size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
     if (plan.dist64 > 0.0) plan.band64 = -1;   // the map needs the sites: bound it by all-FP64
     L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp, plan.band0);
     const size_t te = (size_t)L.nbp * L.nbp;
+    const size_t q16 = L.lowp ? (size_t)L.p * (L.p + 1) / 2 * te * 2 : 0;   // 16-bit factor copy
     return (size_t)L.n64 * te * sizeof(double) +
-           ((size_t)L.n32 + (L.has_zero_tile ? 1 : 0)) * te * sizeof(float);
+           ((size_t)L.n32 + (L.has_zero_tile ? 1 : 0)) * te * sizeof(float) + q16;
 }
 
 // Reserved compute units for the critical path: MPGEO_RESERVED_CUS (default 0: none),

@@ -120,14 +120,16 @@ void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool f
                    const double *p64, const float *p32, hipStream_t stream,
                    bool narrow = false);
 
-// Third tier: quantise panel tiles i in [first, first + count) of the FP32 staging panel to
-// 16-bit (lowp 1: FP16, 2: BF16), row-major, with the power-of-two scale of each tile
-// derived from absmax[i] (float bits of max |P32[i]|); scale[i] receives it.
-void launch_quantize(const TileMap &map, int first, int count, const float *p32,
+// Third tier: quantise panel tiles (i, k), i in [first, first + count), of the FP32 staging
+// panel (tile i at p32 + i * nbp^2) to 16-bit (lowp 1: FP16, 2: BF16), row-major, into the
+// 16-bit factor copy q at slot tri_index(i, k), with the power-of-two scale of each tile
+// derived from absmax[i] (float bits of max |P32[i]|) stored at scale[tri_index(i, k)].
+void launch_quantize(const TileMap &map, int k, int first, int count, const float *p32,
                      const unsigned *absmax, void *q, float *scale, int lowp, hipStream_t stream);
-// Third tier: A_ij -= s_i s_j Q_i Q_j^T over list[0, count) (FP32-stored tiles).
-void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
-                        const float *scale, int lowp, hipStream_t stream);
+// Third tier: A_ij -= sum_k s_ik s_jk Q_ik Q_jk^T over list[0, count) (FP32-stored tiles), for
+// panels k in [max(kbeg, i - zband), kend), ascending, from the 16-bit factor copy.
+void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
+                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream);
 
 // Panel step of the fused forward solve: r_i -= P64_i y_k for i = k+1 .. k+count, and copy
 // the finished panel tile (i, k) from staging into its storage precision.

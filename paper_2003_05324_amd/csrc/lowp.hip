@@ -2,12 +2,18 @@
 // the matrix cores (the paper's future work, Section IX: more than two precision layers).
 //
 // Tiles with i - j > band64 + band32 keep FP32 storage and FP32 accumulation; only the
-// operands of their update A_ij -= L_ik L_jk^T drop to a 16-bit format.  After the panel of
-// step k is solved, every panel tile L_ik is quantised once:
-//   s_i = 2^ceil(log2 max|L_ik|)   (a power of two, so the scaling is exact),
-//   Q_i = round_to_nearest_even(L_ik / s_i)   in FP16 or BF16,
-// stored row-major (K contiguous) for 16-byte operand loads.  The update is then
-//   A_ij -= (s_i s_j) * (Q_i Q_j^T)   with v_mfma_f32_16x16x32_{f16,bf16} accumulating in FP32.
+// operands of their update A_ij -= sum_k L_ik L_jk^T drop to a 16-bit format.  After the
+// panel of step k is solved, every panel tile L_ik is quantised once into a 16-bit copy of
+// the factor that lives for the whole factorization:
+//   s_ik = 2^ceil(log2 max|L_ik|)   (a power of two, so the scaling is exact),
+//   Q_ik = round_to_nearest_even(L_ik / s_ik)   in FP16 or BF16,
+// stored row-major (K contiguous) at tile slot tri_index(i, k).  A far tile then takes all
+// its panels in one pass (left-looking):
+//   A_ij <- A_ij - sum_k (s_ik s_jk) (Q_ik Q_jk^T)
+// where each panel's product comes from v_mfma_f32_16x16x32_{f16,bf16} accumulating in FP32
+// and is folded into the FP32 running value of A_ij by one fused multiply-add per element,
+// panel by panel in ascending k.  That is the same sequence of FP32 roundings as applying the
+// panels one step at a time, but A_ij is read and written once instead of once per panel.
 #include "common.h"
 
 namespace mpgeo {
@@ -35,12 +41,13 @@ template <> struct Lowp<__bf16> {
 constexpr int kXcds = 8;
 constexpr int kQThreads = 256;
 
-// One workgroup per 64 x 64 block of a panel tile: scale by the tile's power of two
+// One workgroup per 64 x 64 block of panel tile (i, k): scale by the tile's power of two
 // s = 2^e with 2^(e-1) < max|x| <= 2^e (s = 1 for an all-zero tile), round to the 16-bit
-// format (nearest even) and store transposed (row-major, K contiguous).
+// format (nearest even) and store transposed (row-major, K contiguous) at slot tri_index(i, k).
 template <typename T, int QB>
 __global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, const unsigned *absmax,
-                                                             T *q, float *scale, int first, int nbp) {
+                                                             T *q, float *scale, int k, int first,
+                                                             int nbp) {
     __shared__ float blk[QB][QB + 1];
     const int per_side = nbp / QB;
     const int i = first + blockIdx.x / (per_side * per_side);
@@ -53,9 +60,10 @@ __global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, c
         if (fr == 0.5f) ex -= 1;            // an exact power of two maps to 1
     }
     const float inv = ldexpf(1.0f, -ex);
-    if (b == 0 && threadIdx.x == 0) scale[i] = ldexpf(1.0f, ex);
+    const int64_t slot = tri_index(i, k);
+    if (b == 0 && threadIdx.x == 0) scale[slot] = ldexpf(1.0f, ex);
     const float *src = p32 + (int64_t)i * nbp * nbp;
-    T *dst = q + (int64_t)i * nbp * nbp;
+    T *dst = q + slot * nbp * nbp;
     for (int e = threadIdx.x; e < QB * QB; e += kQThreads) {
         const int rr = e % QB, tt = e / QB;
         blk[rr][tt] = src[(r0 + rr) + (int64_t)(t0 + tt) * nbp] * inv;   // exact (power of two)
@@ -71,21 +79,24 @@ struct LowpArgs {
     TileMap map;
     int64_t ntiles;
     const TileIJ *list;
-    const void *q;        // quantised panel, tile i at i * nbp^2, row-major
-    const float *scale;   // per panel tile
+    const void *q;        // 16-bit factor copy: tile (i, k) at tri_index(i, k) * nbp^2, row-major
+    const float *scale;   // power-of-two scale of tile (i, k) at tri_index(i, k)
+    int kbeg, kend;       // target (i, j) takes panels k in [max(kbeg, i - zband), kend)
+    int zband;            // tiles (i, k) with i - k > zband are dropped (zero)
 };
 
 // BM x BN output block, WM x WN waves, K chunk KC, DEPTH chunks of operands in flight;
-// CPRE: load the C block into registers before the K loop (its latency hides behind it);
 // PAD: 16-bit elements of padding per LDS row (spreads the rows over the banks).
-template <int BM_, int BN_, int WM_, int WN_, int KC_, int DEPTH_ = 1, int CPRE_ = 0, int PAD_ = 8>
+template <int BM_, int BN_, int WM_, int WN_, int KC_, int DEPTH_ = 1, int PAD_ = 8>
 struct LShape {
     static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = KC_, DEPTH = DEPTH_, PAD = PAD_;
-    static constexpr bool CPRE = CPRE_ != 0;
     static constexpr int kThreads = 64 * WM * WN;
 };
 
-// C[rows, cols] -= s_i s_j * sum_t Q_i[row][t] Q_j[col][t] on one BM x BN block of a tile.
+// One BM x BN block of target tile (i, j):
+//   C <- C - sum over panels k of (s_ik s_jk) * sum_t Q_ik[row][t] Q_jk[col][t].
+// The C block is held in registers for the whole K loop (its load latency hides behind the
+// first chunks); each panel's product is accumulated from zero and folded in at the panel's end.
 template <typename T, typename S>
 __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     using L = Lowp<T>;
@@ -112,10 +123,17 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     const int row0 = (macro % rows_per) * BM;
     const int col0 = (macro / rows_per) * BN;
     const TileIJ tij = g.list[tile];
+    const int kfirst = max(g.kbeg, tij.i - g.zband);
+    if (kfirst >= g.kend) return;
+    const int cpp = nbp / KC;                           // chunks per panel
+    const int nchunks = (g.kend - kfirst) * cpp;
+    const int64_t te = (int64_t)nbp * nbp;
     const T *qbase = static_cast<const T *>(g.q);
-    const T *R = qbase + (int64_t)tij.i * nbp * nbp + (int64_t)row0 * nbp;
-    const T *Q = qbase + (int64_t)tij.j * nbp * nbp + (int64_t)col0 * nbp;
-    const float factor = -g.scale[tij.i] * g.scale[tij.j];
+    // panel k's operands: tile (i, k) = tile (i, 0) + k
+    const T *R0 = qbase + tri_index(tij.i, kfirst) * te + (int64_t)row0 * nbp;
+    const T *Q0 = qbase + tri_index(tij.j, kfirst) * te + (int64_t)col0 * nbp;
+    const float *si = g.scale + tri_index(tij.i, 0);
+    const float *sj = g.scale + tri_index(tij.j, 0);
     float *C = g.map.pool32 + g.map.off[tri_index(tij.i, tij.j)];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -123,17 +141,15 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     const int wcol = (wave / S::WM) * (BN / S::WN);
     const int lr = lane & 15, lg = lane >> 4;
 
-    f32x4 acc[NBC][NBR];
-    f32x4 cpre[S::CPRE ? NBC : 1][S::CPRE ? NBR : 1];
+    f32x4 acc[NBC][NBR], cv[NBC][NBR];
 #pragma unroll
     for (int a = 0; a < NBC; ++a)
 #pragma unroll
         for (int b = 0; b < NBR; ++b) {
             acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (S::CPRE)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    cpre[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp];
+            for (int q = 0; q < 4; ++q)
+                cv[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp];
         }
 
     // Operand chunks stream global -> registers -> LDS.  Chunk x waits in register set
@@ -141,21 +157,22 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     // (the 16-bit MFMAs consume a chunk far faster than memory returns one).
     constexpr int D = S::DEPTH;
     vec8 rq[D][VPQ], rr[D][VPR];
-    auto load_chunk = [&](vec8 (&sq)[VPQ], vec8 (&sr)[VPR], int k0) {
+    auto load_chunk = [&](vec8 (&sq)[VPQ], vec8 (&sr)[VPR], int c) {
+        const int64_t off = (int64_t)(c / cpp) * te + (c % cpp) * KC;
 #pragma unroll
         for (int v = 0; v < VPQ; ++v) {
             const int idx = v * NT + tid;
             if (NVQ % NT == 0 || idx < NVQ) {
-                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                sq[v] = *reinterpret_cast<const vec8 *>(Q + (int64_t)row * nbp + k0 + cv * 8);
+                const int row = idx / VPR_ROW, col = idx % VPR_ROW;
+                sq[v] = *reinterpret_cast<const vec8 *>(Q0 + off + (int64_t)row * nbp + col * 8);
             }
         }
 #pragma unroll
         for (int v = 0; v < VPR; ++v) {
             const int idx = v * NT + tid;
             if (NVR % NT == 0 || idx < NVR) {
-                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                sr[v] = *reinterpret_cast<const vec8 *>(R + (int64_t)row * nbp + k0 + cv * 8);
+                const int row = idx / VPR_ROW, col = idx % VPR_ROW;
+                sr[v] = *reinterpret_cast<const vec8 *>(R0 + off + (int64_t)row * nbp + col * 8);
             }
         }
     };
@@ -164,16 +181,16 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
         for (int v = 0; v < VPQ; ++v) {
             const int idx = v * NT + tid;
             if (NVQ % NT == 0 || idx < NVQ) {
-                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                *reinterpret_cast<vec8 *>(&ldsq[buf][row * LD + cv * 8]) = sq[v];
+                const int row = idx / VPR_ROW, col = idx % VPR_ROW;
+                *reinterpret_cast<vec8 *>(&ldsq[buf][row * LD + col * 8]) = sq[v];
             }
         }
 #pragma unroll
         for (int v = 0; v < VPR; ++v) {
             const int idx = v * NT + tid;
             if (NVR % NT == 0 || idx < NVR) {
-                const int row = idx / VPR_ROW, cv = idx % VPR_ROW;
-                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + cv * 8]) = sr[v];
+                const int row = idx / VPR_ROW, col = idx % VPR_ROW;
+                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + col * 8]) = sr[v];
             }
         }
     };
@@ -194,13 +211,26 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
                 for (int b = 0; b < NBR; ++b) acc[a][b] = L::mac(qa[a], rb[b], acc[a][b]);
         }
     };
+    // end of panel kfirst + c / cpp: C += (-s_ik s_jk) * product, then restart the product
+    auto fold = [&](int c) {
+        const int k = kfirst + c / cpp;
+        const float factor = -si[k] * sj[k];
+#pragma unroll
+        for (int a = 0; a < NBC; ++a)
+#pragma unroll
+            for (int b = 0; b < NBR; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    cv[a][b][q] = cv[a][b][q] + factor * acc[a][b][q];
+                    acc[a][b][q] = 0.f;
+                }
+    };
 
-    const int nchunks = nbp / KC;
 #pragma unroll
     for (int j = 0; j < D; ++j)
-        if (j < nchunks) load_chunk(rq[j], rr[j], j * KC);
+        if (j < nchunks) load_chunk(rq[j], rr[j], j);
     store_chunk(rq[0], rr[0], 0);
-    if (D < nchunks) load_chunk(rq[0], rr[0], D * KC);
+    if (D < nchunks) load_chunk(rq[0], rr[0], D);
     __syncthreads();
     for (int c0 = 0; c0 < nchunks; c0 += D) {
 #pragma unroll
@@ -208,9 +238,10 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             const int c = c0 + j;
             if (c < nchunks) {
                 compute(c & 1);
+                if (c % cpp == cpp - 1) fold(c);
                 const int nxt = (j + 1) % D;   // register set of chunk c + 1
                 if (c + 1 < nchunks) store_chunk(rq[nxt], rr[nxt], (c + 1) & 1);
-                if (c + 1 + D < nchunks) load_chunk(rq[nxt], rr[nxt], (c + 1 + D) * KC);
+                if (c + 1 + D < nchunks) load_chunk(rq[nxt], rr[nxt], c + 1 + D);
                 __syncthreads();
             }
         }
@@ -224,9 +255,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             for (int q = 0; q < 4; ++q) {
                 const int row = row0 + wrow + b * 16 + lr;
                 const int col = col0 + wcol + a * 16 + 4 * lg + q;
-                float *pc = C + row + (int64_t)col * nbp;
-                const float c0v = S::CPRE ? cpre[S::CPRE ? a : 0][S::CPRE ? b : 0][q] : *pc;
-                *pc = c0v + factor * acc[a][b][q];
+                C[row + (int64_t)col * nbp] = cv[a][b][q];
             }
 }
 
@@ -244,25 +273,34 @@ void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
 template <typename T>
 void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
     const int nbp = g.map.nbp;
-    // 128 x 64 blocks, K chunks of 64 with two in flight, C loaded up front, LDS rows padded by
-    // 16 elements (no bank conflicts): measured best on the n ~ 1e5 step-0 list (402 TFLOP/s;
-    // K chunks of 32: 373, and padding 8 showed 5 conflict cycles per LDS instruction)
-    if (nbp % 128 == 0) launch_lowp_shape<T, LShape<128, 64, 2, 2, 64, 2, 1, 16>>(g, ntiles, stream);
-    else if (nbp % 64 == 0) launch_lowp_shape<T, LShape<64, 64, 2, 2, 64, 2, 1, 16>>(g, ntiles, stream);
-    else launch_lowp_shape<T, LShape<32, 32, 2, 2, 32, 1, 0>>(g, ntiles, stream);
+    if (g.kend - g.kbeg > 1 && nbp % 256 == 0) {
+        // many panels (the left-looking pass, long K): 256 x 128 blocks of 8 waves with 64 x 64
+        // each, K chunks of 64 (measured 680-740 TFLOP/s at n ~ 1e5, 128 x 64 blocks: 555)
+        launch_lowp_shape<T, LShape<256, 128, 4, 2, 64, 1, 16>>(g, ntiles, stream);
+    } else if (g.kend - g.kbeg > 1 && nbp % 128 == 0) {
+        launch_lowp_shape<T, LShape<128, 128, 2, 2, 32, 1, 16>>(g, ntiles, stream);
+    } else if (nbp % 128 == 0) {
+        // one panel (the lookahead column, K = nbp): 128 x 64 blocks, K chunks of 64 with two in
+        // flight, LDS rows padded by 16 elements (no bank conflicts)
+        launch_lowp_shape<T, LShape<128, 64, 2, 2, 64, 2, 16>>(g, ntiles, stream);
+    } else if (nbp % 64 == 0) {
+        launch_lowp_shape<T, LShape<64, 64, 2, 2, 64, 2, 16>>(g, ntiles, stream);
+    } else {
+        launch_lowp_shape<T, LShape<32, 32, 2, 2, 32, 1>>(g, ntiles, stream);
+    }
 }
 
 }  // namespace
 
-void launch_quantize(const TileMap &map, int first, int count, const float *p32, const unsigned *absmax,
-                     void *q, float *scale, int lowp, hipStream_t stream) {
+void launch_quantize(const TileMap &map, int k, int first, int count, const float *p32,
+                     const unsigned *absmax, void *q, float *scale, int lowp, hipStream_t stream) {
     if (count <= 0) return;
     const int qb = (map.nbp % 64 == 0) ? 64 : 32;   // transpose block (nbp is a multiple of 32)
     const int per_side = map.nbp / qb;
     const unsigned blocks = (unsigned)((int64_t)count * per_side * per_side);
 #define MPGEO_QUANT(T, QB)                                                                          \
     hipLaunchKernelGGL((quantize_kernel<T, QB>), dim3(blocks), dim3(kQThreads), 0, stream, p32, absmax, \
-                       static_cast<T *>(q), scale, first, map.nbp)
+                       static_cast<T *>(q), scale, k, first, map.nbp)
     if (lowp == 1) {
         if (qb == 64) MPGEO_QUANT(_Float16, 64);
         else MPGEO_QUANT(_Float16, 32);
@@ -273,14 +311,17 @@ void launch_quantize(const TileMap &map, int first, int count, const float *p32,
 #undef MPGEO_QUANT
 }
 
-void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, const void *q,
-                        const float *scale, int lowp, hipStream_t stream) {
-    if (count <= 0) return;
+void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
+                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream) {
+    if (count <= 0 || kend <= kbeg) return;
     LowpArgs g{};
     g.map = map;
     g.list = list;
     g.q = q;
     g.scale = scale;
+    g.kbeg = kbeg;
+    g.kend = kend;
+    g.zband = zband;
     if (lowp == 1) launch_lowp<_Float16>(g, count, stream);
     else launch_lowp<__bf16>(g, count, stream);
 }

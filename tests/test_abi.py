@@ -114,9 +114,12 @@ def test_plan_tiers_match_a_tile_by_tile_enumeration(n, nb, b, c, z):
     np.testing.assert_allclose(got["update_flops"], upd, rtol=1e-12)
     np.testing.assert_allclose(got["trsm_flops"], trsm, rtol=1e-12)
     assert got["potrf_flops"] == pytest.approx(potrf, rel=1e-12)
-    # storage: FP64 tiers at 8 bytes, FP32 and 16-bit-operand tiers at 4, one shared zero tile
+    # storage: FP64 tiers at 8 bytes, FP32 and 16-bit-operand tiers at 4, one shared zero tile,
+    # and with a 16-bit tier the 16-bit copy of the factor (one 2-byte slot per lower tile)
     nbp = -(-nb // 32) * 32
-    want_bytes = (tiles[0] * 8 + (tiles[1] + tiles[2] + (1 if tiles[3] else 0)) * 4) * nbp * nbp
+    p = -(-n // nb)
+    q16 = p * (p + 1) // 2 * 2 if tiles[2] else 0
+    want_bytes = (tiles[0] * 8 + (tiles[1] + tiles[2] + (1 if tiles[3] else 0)) * 4 + q16) * nbp * nbp
     assert got["footprint_bytes"] == want_bytes
 
 
