@@ -318,11 +318,11 @@ struct Layout {
 
 enum StatClass {
     kStatCovgen, kStatOrder, kStatPotrf, kStatTrsm64, kStatTrsm32, kStatPanel, kStatUpdate64,
-    kStatUpdate32, kStatFinal, kStatQuant, kStatUpdate16, kStatCount
+    kStatUpdate32, kStatFinal, kStatQuant, kStatUpdate16, kStatUpdate16Col, kStatCount
 };
 const char *kStatNames[kStatCount] = {"covgen", "morton_order", "potrf_tile", "trsm_fp64",
                                       "trsm_fp32", "panel_solve", "update_fp64", "update_fp32",
-                                      "finalize", "quantize", "update_lowp"};
+                                      "finalize", "quantize", "update_lowp", "update_lowp_col"};
 
 }  // namespace
 
@@ -760,7 +760,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         const double tile_elems = (double)nbd * nbd;
         auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(L.panel_count(k), 2 * count); };
         if (e16 > b16)
-            ctx->timed_on(st, kStatUpdate16, f16,
+            ctx->timed_on(st, kbeg16 == k ? kStatUpdate16Col : kStatUpdate16, f16,
                           tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 +
                                         (kbeg16 == k ? panel_tiles(e16 - b16) : panels16) * 2.0), [&] {
                 launch_update_lowp(map, l16 + b16, e16 - b16, kbeg16, k + 1, L.zband, q16, qscale,
