@@ -284,11 +284,20 @@ void launch_shape(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
 // K chunks of 16 columns.  `narrow` (the few-tile FP64 launches of the critical path, which
 // run beside the wide trailing updates): 64 x 64 blocks with K chunks of 8, 20 KB of LDS
 // instead of 72 KB, so a workgroup fits where one of the concurrent update workgroups ends.
+// Trailing updates measured alone on the n ~ 1e5 step-0 lists: FP64 band lists (a third of
+// them diagonal tiles) 56.5 TFLOP/s with 64 x 64 blocks of 4 waves (128 x 128: 51.7; the
+// diagonal tiles' skipped upper blocks waste less), while the long all-FP64 lists run faster
+// on 128 x 128 blocks; FP32 128 x 128 blocks of 8 waves (32 x 64 each) 130 TFLOP/s (4 waves: 124).
+constexpr int64_t kShortFp64List = 1024;
 template <typename T, int EPI>
 void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream, bool narrow = false) {
     const int nbp = g.map.nbp;
     if (ntiles <= 0) return;
     if (narrow && nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 8>, EPI>(g, ntiles, stream);
+    else if (EPI == kUpdate && sizeof(T) == 8 && nbp % 64 == 0 && ntiles <= kShortFp64List)
+        launch_shape<T, Shape<64, 64, 2, 2, 16>, EPI>(g, ntiles, stream);
+    else if (EPI == kUpdate && sizeof(T) == 4 && nbp % 128 == 0)
+        launch_shape<T, Shape<128, 128, 4, 2, 16>, EPI>(g, ntiles, stream);
     else if (nbp % 128 == 0) launch_shape<T, Shape<128, 128, 2, 2, 16>, EPI>(g, ntiles, stream);
     else if (nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 16>, EPI>(g, ntiles, stream);
     else launch_shape<T, Shape<32, 32, 2, 2, 16>, EPI>(g, ntiles, stream);
