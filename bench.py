@@ -275,6 +275,16 @@ def batch_bench(args):
         walls.append(time.perf_counter() - t0)
     wall = statistics.median(walls)
     print(f"[batch] batched: {wall:.3f} s (tuning pass {t_tune:.2f} s)", file=sys.stderr, flush=True)
+    # the same batch as one persistent kernel over a device task queue (tile 128)
+    st_q, res_q, _ = ctx.batch_loglik(probs, tile=0, band64=-1, queue=True)   # warm-up
+    walls_q = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_q, res_q, _ = ctx.batch_loglik(probs, tile=0, band64=-1, queue=True)
+        walls_q.append(time.perf_counter() - t0)
+    wall_q = statistics.median(walls_q)
+    print(f"[batch] task queue: {wall_q:.3f} s", file=sys.stderr, flush=True)
     for locs, z, theta in probs[:2]:
         ctx.loglik(locs, z, theta, 512, -1)                              # warm-up
     torch.cuda.synchronize()
@@ -284,10 +294,13 @@ def batch_bench(args):
     print(f"[batch] one at a time: {t_seq:.3f} s", file=sys.stderr, flush=True)
     dev = max(abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), len(p[1]))
               for a, b, p in zip(res, seq, probs))
+    dev_q = max(abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), len(p[1]))
+                for a, b, p in zip(res_q, seq, probs))
     # oracle spot check on the three smallest problems
     small = np.argsort(ns)[:3]
-    orc = max(abs(res[q]["loglik"] - oracle.loglik(*probs[q])["loglik"]) /
-              abs(oracle.loglik(*probs[q])["loglik"]) for q in small)
+    want = {q: oracle.loglik(*probs[q])["loglik"] for q in small}
+    orc = max(abs(res[q]["loglik"] - want[q]) / abs(want[q]) for q in small)
+    orc_q = max(abs(res_q[q]["loglik"] - want[q]) / abs(want[q]) for q in small)
     hist = {}
     for t in tiles:
         hist[str(t)] = hist.get(str(t), 0) + 1
@@ -300,7 +313,12 @@ def batch_bench(args):
         "sequential_s": t_seq, "sequential_evals_per_s": len(probs) / t_seq,
         "speedup": t_seq / wall, "tuning_pass_s": t_tune, "tiles": hist,
         "max_dloglik_batched_vs_sequential": dev, "max_rel_dloglik_vs_oracle_3_smallest": orc,
-        "lanes": int(os.environ.get("MPGEO_BATCH_LANES", "4"))}), flush=True)
+        "lanes": int(os.environ.get("MPGEO_BATCH_LANES", "4")),
+        "queue": {"status": st_q, "seconds": wall_q, "evals_per_s": len(probs) / wall_q,
+                  "tflops": flops / wall_q / 1e12, "speedup_vs_lanes": wall / wall_q,
+                  "speedup_vs_sequential": t_seq / wall_q, "tile": 128,
+                  "max_dloglik_vs_sequential": dev_q,
+                  "max_rel_dloglik_vs_oracle_3_smallest": orc_q}}), flush=True)
 
 
 def serve_bench(args):

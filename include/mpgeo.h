@@ -79,6 +79,17 @@ typedef enum {
  * The Z-order key is then taken of ((lon + 180)/360, (lat + 90)/180).  A dataset flag (and
  * a one-shot plan flag); kriging sites use the same convention. */
 #define MPGEO_DIST_GCD    16u
+/* Batched evaluation (mpgeo_batch_loglik) as one persistent kernel over a device task queue
+ * instead of per-problem launch sequences: every problem is cut into 128 x 128 FP64 tiles and
+ * factored left-looking, one task per lower tile (covariance block, the products with its
+ * earlier panels, then the diagonal Cholesky fused with the forward solve or the panel solve
+ * through the diagonal inverse), workgroups taking tasks in dependency order from an atomic
+ * counter and waiting on per-tile done flags.  For small problems, whose launch sequences
+ * leave the device idle.  Needs an all-FP64 plan (band64 = -1, band32 = -1, lowp = 0,
+ * band0 = -1, dist64 = 0), tile 128 or 0 (then 128), and n <= 16384 per problem; otherwise
+ * MPGEO_E_UNSUPPORTED.  Results agree with mpgeo_loglik to rounding (the products are summed
+ * in another order), not bit for bit. */
+#define MPGEO_BATCH_QUEUE 32u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
  * (smoothness); all must be finite and > 0. */
@@ -95,7 +106,7 @@ typedef struct {
  *          -1: FP32 from band64 + 1 to the edge of the matrix (two tiers).
  *  lowp:   0 with band32 = -1; 1 (FP16) or 2 (BF16) with band32 >= 0.
  *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING | MPGEO_PROFILE |
- *          MPGEO_DIST_GCD.
+ *          MPGEO_DIST_GCD | MPGEO_BATCH_QUEUE (mpgeo_batch_loglik only).
  *  band0:  z >= 0: tiles with i - j > z are dropped (taken as zero, never stored, generated or
  *          updated: the diagonal-super-tile approximation the paper compares against, which
  *          factors the block-banded matrix exactly because the Cholesky factor of a matrix of
@@ -256,7 +267,9 @@ typedef struct {
  * tile covering it and with 128, 256, 384, 512 below n, and the fastest is kept in the context
  * for later batches.  out[i] receives loglik, logdet, quad and info (times are 0); tiles, if
  * not NULL, the tile size used.  Inputs are host memory (MPGEO_INPUT_DEVICE and MPGEO_TIMING
- * are rejected).  Returns MPGEO_E_NOT_SPD if any instance failed (see out[i].info). */
+ * are rejected).  With MPGEO_BATCH_QUEUE the batch runs as one persistent kernel instead
+ * (see the flag); a wait in it that exceeds about two seconds aborts the kernel and returns
+ * MPGEO_E_DEVICE.  Returns MPGEO_E_NOT_SPD if any instance failed (see out[i].info). */
 int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
                        mpgeo_result *out, int32_t *tiles);
 

@@ -368,6 +368,9 @@ struct mpgeo_ctx {
     std::vector<mpgeo_dataset *> lane_ds;
     std::map<std::string, int> tuned_tile;
     DevBuf batch_res;                         // per-instance {loglik, logdet, quad, info}
+    // the persistent task-queue batch: inputs, tiles, vectors and control words
+    DevBuf q_in_locs, q_in_z, q_locs, q_vec, q_tiles, q_linv, q_parts, q_flags, q_ctrl,
+        q_insts, q_tasks, q_res, q_info;
 
     hipEvent_t take_event() {
         if (!spare.empty()) {
@@ -1571,6 +1574,142 @@ static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, d
     return MPGEO_OK;
 }
 
+// The persistent task-queue batch (MPGEO_BATCH_QUEUE): problems are packed into shared buffers
+// in groups that fit in device memory, each group one ordering launch and one queue launch.
+static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
+                       mpgeo_result *out, int32_t *tiles) {
+    const int64_t te = (int64_t)kQueueTile * kQueueTile;
+    auto tiles_of = [&](int64_t q) {
+        const int64_t p = (inst[q].n + kQueueTile - 1) / kQueueTile;
+        return p * (p + 1) / 2;
+    };
+    size_t free_b = 0, total_b = 0;
+    MPGEO_HIP(hipMemGetInfo(&free_b, &total_b));
+    // tiles dominate: keep a group's tiles within half of the free memory (the buffers of an
+    // earlier, larger group are reused)
+    const size_t budget = std::max<size_t>(free_b / 2 + ctx->q_tiles.bytes, (size_t)te * 8 * 64);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    hipStream_t s = ctx->stream;
+    int status = MPGEO_OK;
+    for (int64_t g0 = 0; g0 < count;) {
+        // ---- group [g0, g1) and its layout -------------------------------------------------------
+        int64_t g1 = g0, ntiles = 0;
+        while (g1 < count && (g1 == g0 || (size_t)(ntiles + tiles_of(g1)) * te * 8 <= budget)) ntiles += tiles_of(g1++);
+        const int64_t gc = g1 - g0;
+        std::vector<BatchInst> bi((size_t)gc);
+        int64_t pts = 0, tl = 0, lv = 0, vec = 0, prt = 0;
+        int max_n = 1, max_p = 1;
+        for (int64_t q = 0; q < gc; ++q) {
+            const mpgeo_instance &x = inst[g0 + q];
+            BatchInst &b = bi[(size_t)q];
+            b.n = x.n;
+            b.p = (int32_t)((x.n + kQueueTile - 1) / kQueueTile);
+            b.in0 = pts;
+            b.tile0 = tl;
+            b.flag0 = tl;
+            b.linv0 = lv;
+            b.vec0 = vec;
+            b.part0 = prt;
+            b.mp = make_matern_params((plan.flags & MPGEO_PROFILE) ? 1.0 : x.theta.sigma2, x.theta.beta, x.theta.nu);
+            b.mp.gcd = (plan.flags & MPGEO_DIST_GCD) ? 1 : 0;
+            pts += x.n;
+            tl += (int64_t)b.p * (b.p + 1) / 2;
+            lv += b.p;
+            vec += (int64_t)b.p * kQueueTile;
+            prt += 2 * (int64_t)b.p;
+            max_n = std::max<int>(max_n, (int)x.n);
+            max_p = std::max<int>(max_p, b.p);
+        }
+        // tasks: column by column; in a column the diagonal tiles of every problem, then the rest
+        std::vector<BatchTask> tasks;
+        tasks.reserve((size_t)tl);
+        for (int j = 0; j < max_p; ++j) {
+            for (int64_t q = 0; q < gc; ++q)
+                if (j < bi[(size_t)q].p) tasks.push_back({(int32_t)q, j, j, 0});
+            for (int64_t q = 0; q < gc; ++q)
+                for (int i = j + 1; i < bi[(size_t)q].p; ++i) tasks.push_back({(int32_t)q, i, j, 0});
+        }
+        std::vector<double> hl((size_t)pts * 2), hz((size_t)pts);
+        for (int64_t q = 0; q < gc; ++q) {
+            const mpgeo_instance &x = inst[g0 + q];
+            std::memcpy(hl.data() + 2 * bi[(size_t)q].in0, x.locs, (size_t)x.n * 2 * sizeof(double));
+            std::memcpy(hz.data() + bi[(size_t)q].in0, x.z, (size_t)x.n * sizeof(double));
+        }
+        // ---- buffers (grow only; growing waits for the device) ------------------------------
+        MPGEO_TRY(ctx->q_in_locs.ensure(hl.size() * sizeof(double)));
+        MPGEO_TRY(ctx->q_in_z.ensure(hz.size() * sizeof(double)));
+        MPGEO_TRY(ctx->q_locs.ensure(hl.size() * sizeof(double)));
+        MPGEO_TRY(ctx->q_vec.ensure(3 * (size_t)vec * sizeof(double)));
+        MPGEO_TRY(ctx->q_tiles.ensure((size_t)tl * te * sizeof(double)));
+        MPGEO_TRY(ctx->q_linv.ensure((size_t)lv * te * sizeof(double)));
+        MPGEO_TRY(ctx->q_parts.ensure((size_t)prt * sizeof(double)));
+        MPGEO_TRY(ctx->q_flags.ensure((size_t)tl * sizeof(int)));
+        MPGEO_TRY(ctx->q_ctrl.ensure(2 * sizeof(int)));
+        MPGEO_TRY(ctx->q_insts.ensure((size_t)gc * sizeof(BatchInst)));
+        MPGEO_TRY(ctx->q_tasks.ensure(tasks.size() * sizeof(BatchTask)));
+        MPGEO_TRY(ctx->q_res.ensure((size_t)gc * 3 * sizeof(double)));
+        MPGEO_TRY(ctx->q_info.ensure((size_t)gc * sizeof(unsigned long long)));
+        MPGEO_HIP(hipMemcpyAsync(ctx->q_in_locs.ptr, hl.data(), hl.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(ctx->q_in_z.ptr, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(ctx->q_insts.ptr, bi.data(), bi.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(ctx->q_tasks.ptr, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemsetAsync(ctx->q_flags.ptr, 0, (size_t)tl * sizeof(int), s));
+        MPGEO_HIP(hipMemsetAsync(ctx->q_ctrl.ptr, 0, 2 * sizeof(int), s));
+        MPGEO_HIP(hipMemsetAsync(ctx->q_info.ptr, 0xFF, (size_t)gc * sizeof(unsigned long long), s));
+        double *vz = ctx->q_vec.as<double>();
+        launch_batch_order(ctx->q_insts.as<BatchInst>(), gc, max_n, ctx->q_in_locs.as<double>(),
+                           ctx->q_in_z.as<double>(), ctx->q_locs.as<double>(), vz,
+                           true, (plan.flags & MPGEO_DIST_GCD) != 0, s);   // always ordered, as a lane would
+        MPGEO_HIP(hipGetLastError());
+        QueueArgs qa{};
+        qa.tasks = ctx->q_tasks.as<BatchTask>();
+        qa.ntasks = (int64_t)tasks.size();
+        qa.insts = ctx->q_insts.as<BatchInst>();
+        qa.locs = ctx->q_locs.as<double>();
+        qa.z = vz;
+        qa.r = vz + vec;
+        qa.y = vz + 2 * vec;
+        qa.tiles = ctx->q_tiles.as<double>();
+        qa.linv = ctx->q_linv.as<double>();
+        qa.parts = ctx->q_parts.as<double>();
+        qa.flags = ctx->q_flags.as<int>();
+        qa.head = ctx->q_ctrl.as<unsigned>();
+        qa.abort_flag = ctx->q_ctrl.as<int>() + 1;
+        qa.info = ctx->q_info.as<unsigned long long>();
+        qa.result = ctx->q_res.as<double>();
+        qa.profile = (plan.flags & MPGEO_PROFILE) ? 1 : 0;
+        qa.spin_limit = 8 << 20;   // about 2 s of sleeps per wait
+        const int wgs = (int)std::min<int64_t>((int64_t)tasks.size(), (int64_t)cus);
+        launch_batch_queue(qa, wgs, s);
+        MPGEO_HIP(hipGetLastError());
+        std::vector<double> res((size_t)gc * 3);
+        std::vector<unsigned long long> info((size_t)gc);
+        int ctrl[2] = {0, 0};
+        MPGEO_HIP(hipMemcpyAsync(res.data(), ctx->q_res.ptr, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipMemcpyAsync(info.data(), ctx->q_info.ptr, info.size() * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipMemcpyAsync(ctrl, ctx->q_ctrl.ptr, sizeof(ctrl), hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipStreamSynchronize(s));
+        if (ctrl[1] != 0) return MPGEO_E_DEVICE;   // a wait timed out
+        for (int64_t q = 0; q < gc; ++q) {
+            mpgeo_result &o = out[g0 + q];
+            o = mpgeo_result{};
+            o.loglik = res[(size_t)q * 3];
+            o.logdet = res[(size_t)q * 3 + 1];
+            o.quad = res[(size_t)q * 3 + 2];
+            o.info = (info[(size_t)q] == ~0ull) ? -1 : (int64_t)info[(size_t)q];
+            if (o.info >= 0) status = MPGEO_E_NOT_SPD;
+            if (tiles) tiles[g0 + q] = kQueueTile;
+        }
+        g0 = g1;
+    }
+    return status;
+}
+
 int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
                        mpgeo_result *out, int32_t *tiles) {
     if (!ctx || count < 0 || (count > 0 && (!inst || !out))) return MPGEO_E_ARG;
@@ -1583,6 +1722,17 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
             return MPGEO_E_ARG;
         MPGEO_TRY(check_theta(inst[i].theta));
         out[i].info = -1;
+    }
+    if (plan.flags & MPGEO_BATCH_QUEUE) {
+        const bool fp64 = plan.band64 == -1 && plan.band32 == -1 && plan.lowp == 0 && plan.band0 == -1 &&
+                          plan.dist64 == 0.0 && (plan.tile == 0 || plan.tile == kQueueTile);
+        if (!fp64) return MPGEO_E_UNSUPPORTED;
+        for (int64_t i = 0; i < count; ++i)
+            if (inst[i].n > kQueueMaxN) return MPGEO_E_UNSUPPORTED;
+        if (count == 0) return MPGEO_OK;
+        Device dev(ctx->device);
+        if (!dev.ok) return MPGEO_E_DEVICE;
+        return batch_queue(ctx, count, inst, plan, out, tiles);
     }
     if (count == 0) return MPGEO_OK;
     Device dev(ctx->device);

@@ -167,4 +167,45 @@ void launch_forward_multi(const TileMap &map, const double *linv_all, double *c,
 void launch_column_var(const double *c, int64_t ldc, int64_t rows, int64_t m, double sigma2,
                        double scale, double *var, hipStream_t stream);
 
+// ---- batched evaluation as one persistent kernel over a device task queue -------------------
+constexpr int kQueueTile = 128;        // tile size of the queue path
+constexpr int kQueueMaxN = 16384;      // largest problem (its sort runs in one workgroup's LDS)
+
+// One problem of a queued batch; all offsets are in elements of the shared buffers.
+struct BatchInst {
+    int64_t n;
+    int64_t in0;     // first site / datum in the packed inputs and ordered sites (sites 2 in0)
+    int64_t tile0;   // tile (i, j) at tile0 + tri_index(i, j), kQueueTile^2 doubles each
+    int64_t linv0;   // L_jj^-1 at linv0 + j
+    int64_t vec0;    // padded vectors z, r, y: element e at vec0 + e (p * kQueueTile long)
+    int64_t flag0;   // done flag of tile (i, j) at flag0 + tri_index(i, j)
+    int64_t part0;   // logdet parts at part0 + j, quadratic-form parts at part0 + p + j
+    int32_t p;
+    int32_t pad_;
+    MaternParams mp;
+};
+struct BatchTask {
+    int32_t inst, i, j, pad_;
+};
+struct QueueArgs {
+    const BatchTask *tasks;
+    int64_t ntasks;
+    const BatchInst *insts;
+    const double *locs;        // ordered sites
+    const double *z;           // ordered, padded data
+    double *tiles, *linv, *r, *y, *parts;
+    int *flags;                // zero on entry
+    unsigned *head;            // zero on entry
+    int *abort_flag;           // zero on entry; non-zero on exit: a wait timed out
+    unsigned long long *info;  // per problem: all ones on entry, else the failing column
+    double *result;            // per problem: loglik, logdet, quad
+    int profile;
+    int spin_limit;            // sleeps of ~0.25 us per wait before giving up
+};
+// Sites and data of every problem Morton-ordered (order) into locs / zpad; max_n <= kQueueMaxN.
+void launch_batch_order(const BatchInst *insts, int64_t count, int max_n, const double *locs_in,
+                        const double *z_in, double *locs, double *zpad, bool order, bool lonlat,
+                        hipStream_t stream);
+void launch_batch_queue(const QueueArgs &args, int workgroups, hipStream_t stream);
+
 }  // namespace mpgeo

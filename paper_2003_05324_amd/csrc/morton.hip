@@ -7,7 +7,7 @@
 // (key << 32) | index ascending gives the stable order by key (ties keep input order).
 // The sort is a bitonic network over the padded power-of-two array: stages whose
 // partner distance fits in a workgroup run in LDS, the others as global passes.
-#include "common.h"
+#include "morton_dev.h"
 
 namespace mpgeo {
 
@@ -15,21 +15,6 @@ namespace {
 
 constexpr int kSortThreads = 512;
 constexpr int kSortLocal = 2 * kSortThreads;   // elements held in LDS per workgroup
-
-__device__ inline uint32_t spread_bits(uint32_t v) {
-    v &= 0xFFFFu;
-    v = (v | (v << 8)) & 0x00FF00FFu;
-    v = (v | (v << 4)) & 0x0F0F0F0Fu;
-    v = (v | (v << 2)) & 0x33333333u;
-    v = (v | (v << 1)) & 0x55555555u;
-    return v;
-}
-
-__device__ inline uint32_t quantise(double c) {
-    c = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
-    const double q = floor(c * 65536.0);
-    return q > 65535.0 ? 65535u : (uint32_t)q;
-}
 
 __global__ void morton_keys_kernel(const double *locs, int64_t n, int64_t n2, int lonlat,
                                    uint64_t *keys) {
@@ -39,12 +24,7 @@ __global__ void morton_keys_kernel(const double *locs, int64_t n, int64_t n2, in
         keys[e] = ~0ull;
         return;
     }
-    double x = locs[2 * e], y = locs[2 * e + 1];
-    if (lonlat) {
-        x = (x + 180.0) / 360.0;
-        y = (y + 90.0) / 180.0;
-    }
-    const uint32_t key = spread_bits(quantise(x)) | (spread_bits(quantise(y)) << 1);
+    const uint32_t key = morton_key(locs[2 * e], locs[2 * e + 1], lonlat);
     keys[e] = ((uint64_t)key << 32) | (uint64_t)e;
 }
 

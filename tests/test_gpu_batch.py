@@ -84,3 +84,62 @@ def test_empty_and_invalid_batches(lib, ctx):
     assert ctx.batch_loglik([], tile=64)[0] == 0
     with pytest.raises(lib.MpgeoError):
         ctx.batch_loglik([(jittered_grid(4, 1), normals(16, 1), (1.0, -0.1, 0.5))], tile=64)
+
+
+# ---- one persistent kernel over a device task queue (MPGEO_BATCH_QUEUE) ----------------------
+def test_queue_matches_oracle_and_lanes(lib, ctx, problems):
+    st, res, tiles = ctx.batch_loglik(problems, tile=0, band64=-1, queue=True)
+    assert st == 0 and tiles == [128] * len(problems)
+    _, lanes, _ = ctx.batch_loglik(problems, tile=128, band64=-1)
+    for (locs, z, theta), r, l in zip(problems, res, lanes):
+        want = oracle.loglik(locs, z, theta)
+        assert _rel(r["loglik"], want["loglik"]) <= 1e-10, (len(z), theta)
+        assert _rel(r["logdet"], want["logdet"]) <= 1e-10
+        assert _rel(r["quad"], want["quad"]) <= 1e-10
+        assert r["info"] == -1
+        # same tiles and operations, products summed in another order
+        assert _rel(r["loglik"], l["loglik"]) <= 1e-11
+    # deterministic: every task's arithmetic has a fixed order
+    st2, res2, _ = ctx.batch_loglik(problems, tile=128, band64=-1, queue=True)
+    assert st2 == 0 and [r["loglik"] for r in res2] == [r["loglik"] for r in res]
+
+
+def test_queue_medium_problems_and_groups(lib, ctx):
+    # n up to 6,000 (47 tile rows): long left-looking chains, many tasks per column
+    probs = []
+    for locs, eps, theta in batch_instances(12, 23, n_min=2000, n_max=6000):
+        probs.append((locs, oracle.simulate_field(locs, theta, eps), theta))
+    st, res, _ = ctx.batch_loglik(probs, tile=0, band64=-1, queue=True)
+    assert st == 0
+    _, lanes, _ = ctx.batch_loglik(probs, tile=128, band64=-1)
+    for r, l in zip(res, lanes):
+        assert _rel(r["loglik"], l["loglik"]) <= 1e-11
+    q = int(np.argmin([len(z) for _, z, _ in probs]))
+    assert _rel(res[q]["loglik"], oracle.loglik(*probs[q])["loglik"]) <= 1e-10
+
+
+def test_queue_profile_and_great_circle(lib, ctx):
+    from synthetic import lonlat_grid
+    locs = jittered_grid(30, 5)
+    theta = (1.0, 0.1, 1.5)
+    z = oracle.simulate_field(locs, theta, normals(len(locs), 6))
+    st, res, _ = ctx.batch_loglik([(locs, z, (7.0, 0.1, 1.5))], tile=0, profile=True, queue=True)
+    want = oracle.profile_loglik(locs, z, theta[1], theta[2])
+    assert st == 0 and _rel(res[0]["loglik"], want["loglik"]) <= 1e-10
+    ll = lonlat_grid(25, 8)
+    th = (1.0, 300.0, 0.5)
+    zz = oracle.simulate_field(ll, th, normals(len(ll), 9), metric="gcd")
+    st, res, _ = ctx.batch_loglik([(ll, zz, th)], tile=0, gcd=True, queue=True)
+    assert st == 0 and _rel(res[0]["loglik"], oracle.loglik(ll, zz, th, metric="gcd")["loglik"]) <= 1e-10
+
+
+def test_queue_rejects_what_it_does_not_cover(lib, ctx, problems):
+    assert ctx.batch_loglik([], tile=0, queue=True)[0] == 0
+    for kw in (dict(band64=1), dict(tile=256), dict(band0=2)):
+        args = dict(tile=0, band64=-1)
+        args.update(kw)
+        with pytest.raises(lib.MpgeoError):
+            ctx.batch_loglik(problems[:2], queue=True, **args)
+    big = jittered_grid(129, 2)                      # n = 16,641 > 16,384
+    with pytest.raises(lib.MpgeoError):
+        ctx.batch_loglik([(big, normals(len(big), 1), (1.0, 0.1, 0.5))], tile=0, queue=True)

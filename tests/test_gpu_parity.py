@@ -492,6 +492,25 @@ def test_dropped_tiles_match_the_truncated_matrix(small_ds, theta, band0, band, 
         assert far[0] == 0.0
 
 
+@pytest.mark.parametrize("lowp", ["fp16", "bf16"])
+@pytest.mark.parametrize("band0", [4, 6])
+def test_dropped_tiles_with_a_16bit_tier(small_ds, lowp, band0):
+    # three tiers under a dropped band: FP64 for i - j <= 1, FP32 for 2, 16-bit operands for
+    # 3 .. band0, zero beyond.  The 16-bit tiles take their earlier panels in one pass that
+    # skips the dropped panels (k < i - band0); the truncated matrix of the oracle decides.
+    theta = (1.0, 0.03, 0.5)
+    locs, z = small_case()
+    perm = oracle.morton_order(locs)
+    sig = oracle.matern_matrix(locs[perm], theta)
+    ti = np.arange(len(z)) // SMALL.tile
+    sig[np.abs(ti[:, None] - ti[None, :]) > band0] = 0.0
+    want = oracle.likelihood.loglik_parts(sig, z[perm])   # positive definite at this range
+    got = small_ds.loglik(theta, SMALL.tile, 1, band32=1, lowp=lowp, band0=band0)
+    err = abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), len(z))
+    print(f"dropped tiles beyond {band0}, three tiers {lowp}: |dl|/max(|l|,n) = {err:.3e}")
+    assert err <= LOWP_TOL[lowp]
+
+
 # ---- precision map drawn from distances -----------------------------------------------------
 def _tile_box_distances(ordered, tile):
     p = -(-len(ordered) // tile)
