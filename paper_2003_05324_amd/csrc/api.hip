@@ -758,14 +758,15 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     // read once (FP64/FP32: at most p - 1 - k distinct panel tiles, at most two per output
     // tile; 16-bit bulk: the operand tiles counted by the layout).
     auto update_range = [&](int k, int64_t b64, int64_t e64, int64_t b32, int64_t e32, int64_t b16,
-                            int64_t e16, double f64, double f32, double f16, int kbeg16,
+                            int64_t e16, double f64, double f32, double f16, bool lookahead,
                             double panels16, hipStream_t st) {
         const double tile_elems = (double)nbd * nbd;
         auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(L.panel_count(k), 2 * count); };
+        const int kbeg16 = lookahead ? k : 0;
         if (e16 > b16)
-            ctx->timed_on(st, kbeg16 == k ? kStatUpdate16Col : kStatUpdate16, f16,
+            ctx->timed_on(st, lookahead ? kStatUpdate16Col : kStatUpdate16, f16,
                           tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 +
-                                        (kbeg16 == k ? panel_tiles(e16 - b16) : panels16) * 2.0), [&] {
+                                        (lookahead ? panel_tiles(e16 - b16) : panels16) * 2.0), [&] {
                 launch_update_lowp(map, l16 + b16, e16 - b16, kbeg16, k + 1, L.zband, q16, qscale,
                                    L.lowp, st);
             });
@@ -773,7 +774,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
             ctx->timed_on(st, kStatUpdate64, f64,
                           tile_elems * ((double)(e64 - b64) * 8.0 * 2.0 + panel_tiles(e64 - b64) * 8.0), [&] {
                 launch_update(map, l64 + b64, e64 - b64, true, panel64(k), panel32(k), st,
-                              /*narrow=*/st == s1);   // the lookahead column
+                              /*narrow=*/lookahead);   // the lookahead column
             });
         if (e32 > b32)
             ctx->timed_on(st, kStatUpdate32, f32,
@@ -790,14 +791,14 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         if (k + 1 < p)
             update_range(k, L.bulk[0][k].b, L.bulk[0][k].e, L.bulk[1][k].b, L.bulk[1][k].e,
                          L.bulk[2][k].b, L.bulk[2][k].e, L.bulk[0][k].flops, L.bulk[1][k].flops,
-                         L.bulk[2][k].flops, 0, L.bulk[2][k].panels, sb);
+                         L.bulk[2][k].flops, false, L.bulk[2][k].panels, sb);
         MPGEO_HIP(hipEventRecord(ev_bulk[k], sb));
         if (k + 1 < p) {
             // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
             update_range(k, L.col[0][k].b, L.col[0][k].e, L.col[1][k].b, L.col[1][k].e,
                          L.col[2][k].b, L.col[2][k].e, L.col[0][k].flops, L.col[1][k].flops,
-                         L.col[2][k].flops, k, 0.0, s1);
+                         L.col[2][k].flops, true, 0.0, s1);
             factor_step(k + 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
