@@ -17,8 +17,10 @@
  * Optional third tier (more precision layers, the paper's future work in Section IX):
  * with band32 = c >= 0 and lowp = 1 (FP16) or 2 (BF16), tiles with i - j > band64 + c stay
  * FP32-stored but their trailing updates take 16-bit operands: each finished panel tile
- * L_ik is scaled by s_i = 2^ceil(log2 max|L_ik|) and rounded to nearest-even once, and
- * A_ij -= s_i s_j (Q_i Q_j^T) runs on the matrix cores with FP32 accumulation.
+ * L_ik is scaled by s_ik = 2^ceil(log2 max|L_ik|) and rounded to nearest-even once into a
+ * 16-bit copy of the factor, and A_ij -= s_ik s_jk (Q_ik Q_jk^T) runs on the matrix cores with
+ * FP32 accumulation, panel by panel in ascending k (a far tile takes all its earlier panels
+ * in one pass two steps before it is solved).
  *
  * Conventions for every entry point:
  *  - Return value: an mpgeo_status code; MPGEO_OK (0) on success.
@@ -301,8 +303,10 @@ int mpgeo_server_submit(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, d
 int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out);
 int mpgeo_server_destroy(mpgeo_server *srv);
 
-/* HBM bytes of the lower-triangle tiles for n and plan (admission control; for a map drawn
- * from distances, which needs the sites, the all-FP64 bound). */
+/* HBM bytes of the lower-triangle tiles for n and plan, plus, with a 16-bit tier, the 16-bit
+ * copy of the factor that its left-looking updates read (2 bytes per entry of every lower
+ * tile); admission control.  For a map drawn from distances, which needs the sites, the
+ * all-FP64 bound. */
 size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan);
 
 /* The precision map of Algorithm 1 for n and plan, computed on the host (no device call):
