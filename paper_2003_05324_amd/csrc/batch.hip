@@ -27,7 +27,7 @@ namespace {
 
 constexpr int kQThreads = 256;          // 4 waves, each a 64 x 64 quarter of the tile
 constexpr int kQTile = kQueueTile;      // 128
-constexpr int kQKc = 8;                 // K chunk staged through LDS
+constexpr int kQKc = 16;                // K chunk staged through LDS
 constexpr int kQLd = kQTile + 16;       // padded LDS row
 constexpr int kOrderThreads = 1024;
 constexpr double kQLog2Pi = 1.8378770664093454836;
