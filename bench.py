@@ -332,12 +332,13 @@ def batch_bench(args):
 
 def serve_bench(args):
     """Serving loop: Poisson arrivals of likelihood requests (theta drawn around (1, 0.1, 0.5) as
-    an optimiser's trajectory would visit it) for 16 datasets, HBM budget 96 GB, 4 lanes; the same
-    trace with the two-tier plan (FP64 band 2, tile 512) and with the all-FP64 plan."""
+    an optimiser's trajectory would visit it) for 16 datasets, every fourth a kriging request
+    (predictions and variances at 500 new sites), HBM budget 96 GB, 4 lanes; the same trace with
+    the two-tier plan (FP64 band 2, tile 512) and with the all-FP64 plan."""
     import numpy as np
 
     import paper_2003_05324_amd as mp
-    from synthetic import jittered_grid, normals
+    from synthetic import jittered_grid, normals, uniform_sites
     rng = np.random.default_rng(21)
     sizes = [int(round(np.exp(rng.uniform(np.log(2000), np.log(60000))))) for _ in range(16)]
     data = []
@@ -349,6 +350,8 @@ def serve_bench(args):
     thetas = [(float(np.exp(rng.normal(0, 0.15))), float(0.1 * np.exp(rng.normal(0, 0.15))), 0.5)
               for _ in range(args.serve)]
     flops = float(sum(sizes[d] ** 3 / 3.0 for d in picks))
+    kriging = [q % 4 == 3 for q in range(args.serve)]
+    new_sites = [uniform_sites(500, 950 + q) for q in range(len(sizes))]
     ctx = mp.Context(0)
     out = {"serve": f"matern-serve{args.serve}-16sets-n2000-60000", "requests": args.serve,
            "rate_per_s": args.serve_rate, "dataset_sizes": sizes, "sum_n3_over_3": flops}
@@ -356,15 +359,22 @@ def serve_bench(args):
         srv = mp.Server(ctx, 96 * 2 ** 30, 4)
         ids = [srv.add_dataset(locs, z, 512, band) for locs, z in data]
         for q in range(args.serve):
-            srv.submit(ids[picks[q]], thetas[q], float(arrivals[q]))
+            if kriging[q]:
+                srv.submit_krige(ids[picks[q]], thetas[q], new_sites[picks[q]], float(arrivals[q]),
+                                 variance=True)
+            else:
+                srv.submit(ids[picks[q]], thetas[q], float(arrivals[q]))
         print(f"[serve] {name}: {args.serve} requests over {arrivals[-1]:.1f} s", file=sys.stderr, flush=True)
         st, res = srv.run()
         srv.close()
         lat = np.array([r["finish_s"] - r["arrival_s"] for r in res])
+        klat = np.array([r["finish_s"] - r["arrival_s"] for r, k in zip(res, kriging) if k])
         wait = np.array([r["start_s"] - r["arrival_s"] for r in res])
         span = max(r["finish_s"] for r in res)
         out[name] = {"status": st, "p50_latency_s": float(np.percentile(lat, 50)),
                      "p99_latency_s": float(np.percentile(lat, 99)),
+                     "kriging_requests": int(sum(kriging)),
+                     "kriging_p50_latency_s": float(np.percentile(klat, 50)) if len(klat) else None,
                      "mean_wait_s": float(wait.mean()), "makespan_s": span,
                      "evals_per_s": args.serve / span, "tflops": flops / span / 1e12,
                      "loglik_first": res[0]["loglik"]}

@@ -299,6 +299,16 @@ int mpgeo_server_add_dataset(mpgeo_server *srv, int64_t n, const double *locs, c
                              mpgeo_plan plan, int32_t *id);
 int mpgeo_server_submit(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, double arrival_s,
                         int64_t *ticket);
+/* A kriging request (the prediction experiment, Section VIII-D): the factor of (dataset, theta)
+ * as for mpgeo_server_submit (its loglik, logdet and quad are reported alike), then simple
+ * kriging from it on the same lane: predictions at m >= 1 new sites (m x 2, host memory, copied
+ * at submission) into pred (m doubles, host) and, when var is not NULL (m <= 65535), the
+ * prediction variances into var.  The outputs are written when mpgeo_server_run returns and
+ * must stay valid until then.  Results equal mpgeo_dataset_krige after mpgeo_dataset_loglik of
+ * the same dataset and theta. */
+int mpgeo_server_submit_krige(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, int64_t m,
+                              const double *new_locs, double *pred, double *var, double arrival_s,
+                              int64_t *ticket);
 /* out: one entry per submitted request, in submission (ticket) order. */
 int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out);
 int mpgeo_server_destroy(mpgeo_server *srv);

@@ -34,7 +34,8 @@ EXPORTED = (
     "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
     "mpgeo_footprint_bytes", "mpgeo_plan_tiers", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
     "mpgeo_dataset_simulate", "mpgeo_batch_loglik", "mpgeo_server_create",
-    "mpgeo_server_add_dataset", "mpgeo_server_submit", "mpgeo_server_run", "mpgeo_server_destroy",
+    "mpgeo_server_add_dataset", "mpgeo_server_submit", "mpgeo_server_submit_krige", "mpgeo_server_run",
+    "mpgeo_server_destroy",
 )
 
 
@@ -127,6 +128,7 @@ def _load() -> ctypes.CDLL:
         "mpgeo_server_create": ([P, ctypes.c_uint64, I32, ctypes.POINTER(P)], ctypes.c_int),
         "mpgeo_server_add_dataset": ([P, I64, P, P, Plan, ctypes.POINTER(I32)], ctypes.c_int),
         "mpgeo_server_submit": ([P, I32, Theta, D, ctypes.POINTER(I64)], ctypes.c_int),
+        "mpgeo_server_submit_krige": ([P, I32, Theta, I64, P, P, P, D, ctypes.POINTER(I64)], ctypes.c_int),
         "mpgeo_server_run": ([P, ctypes.POINTER(Served)], ctypes.c_int),
         "mpgeo_server_destroy": ([P], ctypes.c_int),
     }
@@ -415,6 +417,7 @@ class Server:
                "mpgeo_server_create")
         self.handle = h
         self.count = 0
+        self._krige = {}   # ticket -> (sites, pred, var) kept alive until run
 
     def add_dataset(self, locs, z, tile: int, band64: int, band32: int = -1, lowp=None) -> int:
         locs, z = _host_f64(locs), _host_f64(z)
@@ -431,13 +434,36 @@ class Server:
         self.count += 1
         return t.value
 
+    def submit_krige(self, dataset: int, theta: Sequence[float], new_locs, arrival_s: float,
+                     variance: bool = False) -> int:
+        """A kriging request: the factor of (dataset, theta), then predictions (and variances)
+        at new_locs (m x 2); they appear as "pred" (and "var") in run()'s result."""
+        sites = _host_f64(new_locs)
+        m = int(sites.shape[0])
+        pred = np.empty(m, dtype=np.float64)
+        var = np.empty(m, dtype=np.float64) if variance else None
+        t = ctypes.c_int64()
+        _check(LIB.mpgeo_server_submit_krige(self.handle, dataset, Theta(*theta), m, sites.ctypes.data,
+                                             pred.ctypes.data, var.ctypes.data if variance else None,
+                                             float(arrival_s), ctypes.byref(t)),
+               "mpgeo_server_submit_krige")
+        self._krige[t.value] = (sites, pred, var)
+        self.count += 1
+        return t.value
+
     def run(self) -> tuple:
         """Replays the submitted requests; returns (status, per-request dicts in ticket order)."""
         out = (Served * max(1, self.count))()
         st = LIB.mpgeo_server_run(self.handle, out)
         if st not in (MPGEO_OK, MPGEO_E_NOT_SPD):
+            self._krige = {}
             _check(st, "mpgeo_server_run")
         res = [out[q].as_dict() for q in range(self.count)]
+        for t, (_, pred, var) in self._krige.items():
+            res[t]["pred"] = pred
+            if var is not None:
+                res[t]["var"] = var
+        self._krige = {}
         self.count = 0
         return st, res
 

@@ -893,6 +893,36 @@ struct Device {
     bool ok;
 };
 
+// Simple kriging from the resident factor, enqueued on the dataset's stream without waiting:
+// w = L^-T y (backward solve), pred_j = sum_a C(s0_j, s_a) w_a, and with var the prediction
+// variances var_scale * (theta1 - |L^-1 c_j|^2).  New sites and outputs are device buffers.
+int krige_enqueue(mpgeo_dataset *ds, int64_t m, const double *dnew, double *dpred, double *dvar,
+                  double var_scale) {
+    const Layout &L = ds->layout;
+    hipStream_t s = ds->ctx->stream;
+    const size_t vec = (size_t)L.p * L.nbp;
+    MPGEO_TRY(ds->tmp_a.ensure(2 * vec * sizeof(double)));
+    double *t = ds->tmp_a.as<double>();
+    double *w = t + vec;
+    launch_backward_solve(tile_map(ds), ds->linv.as<double>(), ds->y.as<double>(), t, w, s);
+    MPGEO_HIP(hipGetLastError());
+    MaternParams mp = make_matern_params(ds->theta.sigma2, ds->theta.beta, ds->theta.nu);
+    mp.gcd = (ds->flags & MPGEO_DIST_GCD) ? 1 : 0;
+    launch_krige_predict(ds->locs.as<double>(), L.n, L.nb, L.nbp, dnew, m, w, mp, dpred, s);
+    MPGEO_HIP(hipGetLastError());
+    if (dvar) {
+        const int64_t ldc = (int64_t)vec;
+        MPGEO_TRY(ds->tmp_c.ensure((size_t)ldc * m * sizeof(double) + (size_t)L.nbp * m * sizeof(double)));
+        double *c = ds->tmp_c.as<double>();
+        double *tmp = c + (size_t)ldc * m;
+        launch_cross_cov(ds->locs.as<double>(), L.n, L.nb, L.nbp, L.p, dnew, m, mp, c, ldc, s);
+        launch_forward_multi(tile_map(ds), ds->linv.as<double>(), c, ldc, m, tmp, s);
+        launch_column_var(c, ldc, ldc, m, ds->theta.sigma2, var_scale, dvar, s);
+        MPGEO_HIP(hipGetLastError());
+    }
+    return MPGEO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1185,15 +1215,8 @@ int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs, do
     if (var && m > 65535) return MPGEO_E_ARG;
     if (m == 0) return MPGEO_OK;
     Device dev(ds->ctx->device);
-    const Layout &L = ds->layout;
     hipStream_t s = ds->ctx->stream;
     const bool on_dev = (ds->flags & MPGEO_INPUT_DEVICE) != 0;
-    const size_t vec = (size_t)L.p * L.nbp;
-    MPGEO_TRY(ds->tmp_a.ensure(2 * vec * sizeof(double)));
-    double *t = ds->tmp_a.as<double>();
-    double *w = t + vec;
-    launch_backward_solve(tile_map(ds), ds->linv.as<double>(), ds->y.as<double>(), t, w, s);
-    MPGEO_HIP(hipGetLastError());
     // new sites and outputs on the device
     const size_t need = (size_t)m * 2 * sizeof(double) + 2 * (size_t)m * sizeof(double);
     MPGEO_TRY(ds->tmp_b.ensure(need));
@@ -1202,20 +1225,7 @@ int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs, do
     double *dvar = dpred + m;
     if (on_dev) MPGEO_HIP(hipMemcpyAsync(dnew, new_locs, (size_t)m * 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
     else MPGEO_HIP(hipMemcpyAsync(dnew, new_locs, (size_t)m * 2 * sizeof(double), hipMemcpyHostToDevice, s));
-    MaternParams mp = make_matern_params(ds->theta.sigma2, ds->theta.beta, ds->theta.nu);
-    mp.gcd = (ds->flags & MPGEO_DIST_GCD) ? 1 : 0;
-    launch_krige_predict(ds->locs.as<double>(), L.n, L.nb, L.nbp, dnew, m, w, mp, dpred, s);
-    MPGEO_HIP(hipGetLastError());
-    if (var) {
-        const int64_t ldc = (int64_t)vec;
-        MPGEO_TRY(ds->tmp_c.ensure((size_t)ldc * m * sizeof(double) + (size_t)L.nbp * m * sizeof(double)));
-        double *c = ds->tmp_c.as<double>();
-        double *tmp = c + (size_t)ldc * m;
-        launch_cross_cov(ds->locs.as<double>(), L.n, L.nb, L.nbp, L.p, dnew, m, mp, c, ldc, s);
-        launch_forward_multi(tile_map(ds), ds->linv.as<double>(), c, ldc, m, tmp, s);
-        launch_column_var(c, ldc, ldc, m, ds->theta.sigma2, ds->var_scale, dvar, s);
-        MPGEO_HIP(hipGetLastError());
-    }
+    MPGEO_TRY(krige_enqueue(ds, m, dnew, dpred, var ? dvar : nullptr, ds->var_scale));
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     MPGEO_HIP(hipMemcpyAsync(pred, dpred, (size_t)m * sizeof(double), kind, s));
     if (var) MPGEO_HIP(hipMemcpyAsync(var, dvar, (size_t)m * sizeof(double), kind, s));
@@ -1802,6 +1812,11 @@ struct ServedRequest {
     int32_t dataset;
     mpgeo_theta theta;
     double arrival;
+    // kriging request: new sites (host copy), the caller's outputs, offset in the device arena
+    int64_t m = 0;
+    std::vector<double> sites;
+    double *pred = nullptr, *var = nullptr;
+    size_t arena = 0;
 };
 
 struct mpgeo_server {
@@ -1811,6 +1826,7 @@ struct mpgeo_server {
     std::vector<ServedDataset> sets;
     std::vector<ServedRequest> reqs;
     size_t resident_bytes = 0;
+    DevBuf krige_arena;                // new sites, predictions and variances of kriging requests
 };
 
 int mpgeo_server_create(mpgeo_ctx *ctx, uint64_t hbm_budget_bytes, int32_t lanes, mpgeo_server **out) {
@@ -1849,7 +1865,31 @@ int mpgeo_server_submit(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, d
     if (!srv || dataset < 0 || dataset >= (int32_t)srv->sets.size() || !(arrival_s >= 0.0))
         return MPGEO_E_ARG;
     MPGEO_TRY(check_theta(theta));
-    srv->reqs.push_back({dataset, theta, arrival_s});
+    ServedRequest rq;
+    rq.dataset = dataset;
+    rq.theta = theta;
+    rq.arrival = arrival_s;
+    srv->reqs.push_back(std::move(rq));
+    if (ticket) *ticket = (int64_t)srv->reqs.size() - 1;
+    return MPGEO_OK;
+}
+
+int mpgeo_server_submit_krige(mpgeo_server *srv, int32_t dataset, mpgeo_theta theta, int64_t m,
+                              const double *new_locs, double *pred, double *var, double arrival_s,
+                              int64_t *ticket) {
+    if (!srv || dataset < 0 || dataset >= (int32_t)srv->sets.size() || !(arrival_s >= 0.0) || m < 1 ||
+        !new_locs || !pred || (var && m > 65535))
+        return MPGEO_E_ARG;
+    MPGEO_TRY(check_theta(theta));
+    ServedRequest rq;
+    rq.dataset = dataset;
+    rq.theta = theta;
+    rq.arrival = arrival_s;
+    rq.m = m;
+    rq.sites.assign(new_locs, new_locs + 2 * m);
+    rq.pred = pred;
+    rq.var = var;
+    srv->reqs.push_back(std::move(rq));
     if (ticket) *ticket = (int64_t)srv->reqs.size() - 1;
     return MPGEO_OK;
 }
@@ -1883,6 +1923,19 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
     if (nreq == 0) return MPGEO_OK;
     MPGEO_TRY(ctx->batch_res.ensure((size_t)nreq * 4 * sizeof(double)));
     double *res = ctx->batch_res.as<double>();
+    // kriging requests: sites, predictions and variances in one device arena, sites uploaded now
+    size_t arena = 0;
+    for (auto &rq : srv->reqs) {
+        rq.arena = arena;
+        arena += 4 * (size_t)rq.m;
+    }
+    if (arena > 0) {
+        MPGEO_TRY(srv->krige_arena.ensure(arena * sizeof(double)));
+        for (auto &rq : srv->reqs)
+            if (rq.m > 0)
+                MPGEO_HIP(hipMemcpy(srv->krige_arena.as<double>() + rq.arena, rq.sites.data(),
+                                    (size_t)rq.m * 2 * sizeof(double), hipMemcpyHostToDevice));
+    }
     std::vector<int64_t> order((size_t)nreq);
     for (int64_t i = 0; i < nreq; ++i) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -1966,6 +2019,11 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
             if (d.ds->profile) th.sigma2 = 1.0;
             status = run_covgen(d.ds, th);
             if (status == MPGEO_OK) status = run_factor(d.ds, nullptr);
+            if (status == MPGEO_OK && rq.m > 0) {   // kriging from this factor, same lane
+                d.ds->theta = th;
+                double *a = srv->krige_arena.as<double>() + rq.arena;
+                status = krige_enqueue(d.ds, rq.m, a, a + 2 * rq.m, rq.var ? a + 3 * rq.m : nullptr, 1.0);
+            }
             if (status != MPGEO_OK) break;
             double *slot = res + 4 * r;
             MPGEO_HIP(hipMemcpyAsync(slot, d.ds->result.ptr, 3 * sizeof(double), hipMemcpyDeviceToDevice, lc->stream));
@@ -1999,6 +2057,18 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
         out[i].info = (info == ~0ull) ? -1 : (int64_t)info;
         out[i].arrival_s = srv->reqs[(size_t)i].arrival;
         if (out[i].info >= 0) status = MPGEO_E_NOT_SPD;
+        const ServedRequest &rq = srv->reqs[(size_t)i];
+        if (rq.m > 0) {   // kriging outputs; a profile plan's variances take theta1 = q~ / n
+            const double *a = srv->krige_arena.as<double>() + rq.arena;
+            MPGEO_HIP(hipMemcpy(rq.pred, a + 2 * rq.m, (size_t)rq.m * sizeof(double), hipMemcpyDeviceToHost));
+            if (rq.var) {
+                MPGEO_HIP(hipMemcpy(rq.var, a + 3 * rq.m, (size_t)rq.m * sizeof(double), hipMemcpyDeviceToHost));
+                if (srv->sets[(size_t)rq.dataset].plan.flags & MPGEO_PROFILE) {
+                    const double scale = out[i].quad / (double)srv->sets[(size_t)rq.dataset].n;
+                    for (int64_t j = 0; j < rq.m; ++j) rq.var[j] *= scale;
+                }
+            }
+        }
     }
     srv->reqs.clear();
     return status;
@@ -2008,6 +2078,7 @@ int mpgeo_server_destroy(mpgeo_server *srv) {
     if (!srv) return MPGEO_OK;
     Device dev(srv->ctx->device);
     for (auto &d : srv->sets) server_evict(srv, d);
+    srv->krige_arena.release();
     delete srv;
     return MPGEO_OK;
 }

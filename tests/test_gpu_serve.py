@@ -43,3 +43,47 @@ def test_served_results_equal_isolated_evaluations(lib):
     assert e.value.status == lib.MPGEO_E_NOMEM
     srv.close()
     ctx.close()
+
+
+def test_kriging_requests_in_the_mix(lib):
+    # likelihood and kriging requests of different sizes interleaved: every kriging request's
+    # predictions and variances equal a dataset's own evaluation followed by kriging, bit for
+    # bit, and match the oracle's simple kriging
+    ctx = lib.Context(0)
+    sizes = [400, 900, 1300]
+    data = [(jittered_grid(int(np.ceil(np.sqrt(n))), 60 + q)[:n].copy(), normals(n, 70 + q))
+            for q, n in enumerate(sizes)]
+    srv = lib.Server(ctx, hbm_budget_bytes=1 << 34, lanes=2)
+    ids = [srv.add_dataset(locs, z, 128, -1) for locs, z in data]
+    new = [jittered_grid(7, 80 + q) * 0.9 + 0.05 for q in range(len(sizes))]   # 49 new sites
+    rng = np.random.default_rng(5)
+    reqs = []
+    for q in range(9):
+        d = q % len(sizes)
+        theta = (float(np.exp(rng.normal(0, 0.2))), float(0.1 * np.exp(rng.normal(0, 0.2))), 0.5)
+        if q % 2 == 0:
+            t = srv.submit_krige(ids[d], theta, new[d], 0.01 * q, variance=(q % 4 == 0))
+        else:
+            t = srv.submit(ids[d], theta, 0.01 * q)
+        reqs.append((t, d, theta, q % 2 == 0, q % 4 == 0))
+    st, out = srv.run()
+    assert st == 0
+    for t, d, theta, kriging, variance in reqs:
+        r = out[t]
+        ds = lib.Dataset(ctx, *data[d])
+        alone = ds.loglik(theta, 128, -1)
+        assert r["loglik"] == alone["loglik"]
+        if kriging:
+            got = ds.krige(new[d], variance=variance)
+            pred, var = got if variance else (got, None)
+            assert np.array_equal(r["pred"], pred), t
+            want = oracle.krige(data[d][0], data[d][1], theta, new[d])
+            assert np.max(np.abs(r["pred"] - want["pred"])) <= 1e-9 * max(1.0, np.max(np.abs(want["pred"])))
+            if variance:
+                assert np.array_equal(r["var"], var), t
+                assert np.max(np.abs(r["var"] - want["var"])) <= 1e-9 * theta[0]
+        else:
+            assert "pred" not in r
+        ds.close()
+    srv.close()
+    ctx.close()
