@@ -105,6 +105,15 @@ struct Layout {
         double panels = 0.0;   // bulk[2] only: 16-bit operand tiles read (rows i and row j)
     };
     std::vector<Range> bulk[3], col[3];
+    // FP64 and FP32 bulk ranges end with column k+2's tiles: they start at next_b[q][k] and
+    // take next_f[q][k] of the flops (the next lookahead column needs them first)
+    std::vector<int64_t> next_b[2];
+    std::vector<double> next_f[2];
+    // bulk[2][k] indexes these: the 16-bit tiles step k's bulk pass updates and, per entry,
+    // the first panel it takes (the pass takes panels first .. k)
+    std::vector<TileIJ> bulk16;
+    std::vector<int32_t> bulk16_k0;
+    int wave16 = 0;                           // 16-bit bulk tiles that run at once (0: unknown)
     std::vector<char> needq;                  // panel k has a 16-bit copy (some later use)
     std::vector<double> trsm64_flops, trsm32_flops;
     int64_t n64 = 0, n32 = 0;                 // tiles per storage precision (FP32 holds tier 16)
@@ -148,8 +157,10 @@ struct Layout {
 
     // boxes: per tile row, {xmin, xmax, ymin, ymax} of its sites (distance map only)
     void build(int64_t n_, int nb_, int band64, int band32 = -1, int lowp_ = 0, int band0 = -1,
-               const std::vector<double> *boxes = nullptr, double d64 = 0.0, double d32 = 0.0) {
+               const std::vector<double> *boxes = nullptr, double d64 = 0.0, double d32 = 0.0,
+               int wave16_ = 0) {
         n = n_;
+        wave16 = wave16_;
         nb = nb_;
         nbp = (nb + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
         p = (int)((n + nb - 1) / nb);
@@ -276,23 +287,58 @@ struct Layout {
                 }
             }
         }
-        // left-looking 16-bit tier: step k's bulk is column k+2, panels [max(0, i - zband), k]
+        // left-looking 16-bit tier: step k's bulk pass brings column k+2 up to panel k (panels
+        // [max(0, i - zband), k]).  All of its workgroups take equally long (k + 1 panels), so a
+        // launch costs whole waves of them; when the last wave would run part-empty it is
+        // filled with tiles of column k+3, which take panels 0 .. k now and only panel k+1 at
+        // the next step (the tiles of one column then come first, taking one panel each).
+        // Every tile still takes its panels one at a time in ascending order.
+        bulk16.clear();
+        bulk16_k0.clear();
         needq.assign(p, 0);
         std::vector<int> kmin_at(p, p);   // first panel any tile of step k's bulk takes
+        std::vector<std::vector<int>> rows16(p), next16(p);   // per column: rows, next panel
+        for (int64_t t = 0; t < (int64_t)list16.size(); ++t) rows16[list16[(size_t)t].j].push_back(list16[(size_t)t].i);
+        for (int j = 0; j < p; ++j) {
+            std::sort(rows16[j].begin(), rows16[j].end());
+            next16[j].assign(rows16[j].size(), 0);
+        }
+        const bool fill = wave16 > 0 && zband >= p;
         for (int k = 0; k + 1 < p; ++k) {
             Range agg;
-            if (k + 2 < p) {
-                agg.b = col[2][k + 1].b;
-                agg.e = col[2][k + 1].e;
-                int kmin = k + 1;
+            agg.b = agg.e = (int64_t)bulk16.size();
+            const int c = k + 2;
+            if (c < p) {
+                int64_t longs = 0;
+                for (int pass = 0; pass < 2; ++pass)   // tiles begun at an earlier step first
+                    for (size_t a = 0; a < rows16[c].size(); ++a) {
+                        const int k0 = next16[c][a];
+                        if ((pass == 0) != (k0 > 0)) continue;
+                        bulk16.push_back({rows16[c][a], c});
+                        bulk16_k0.push_back(k0);
+                        next16[c][a] = k + 1;
+                        if (k0 == 0) ++longs;
+                    }
+                if (fill && c + 1 < p && longs % wave16 != 0) {
+                    const int64_t want = wave16 - longs % wave16;
+                    for (size_t a = 0; a < rows16[c + 1].size() && (int64_t)a < want; ++a) {
+                        bulk16.push_back({rows16[c + 1][a], c + 1});
+                        bulk16_k0.push_back(0);
+                        next16[c + 1][a] = k + 1;
+                    }
+                }
+                agg.e = (int64_t)bulk16.size();
+                int kmin = k + 1, kmin_col[2] = {k + 1, k + 1};
                 for (int64_t t = agg.b; t < agg.e; ++t) {
-                    const TileIJ ij = list16[(size_t)t];
-                    const int k0 = std::max(0, ij.i - zband);
+                    const TileIJ ij = bulk16[(size_t)t];
+                    const int k0 = std::max(bulk16_k0[(size_t)t], ij.i - zband);
                     for (int kk = k0; kk <= k; ++kk) agg.flops += update_flops(ij.i, ij.j, kk);
                     agg.panels += std::max(0, k + 1 - k0);
                     kmin = std::min(kmin, k0);
+                    int &km = kmin_col[ij.j - c];
+                    km = std::min(km, k0);
                 }
-                if (agg.e > agg.b) agg.panels += std::max(0, k + 1 - kmin);   // row j's tiles
+                for (int q = 0; q < 2; ++q) agg.panels += std::max(0, k + 1 - kmin_col[q]);   // rows j
                 if (agg.e > agg.b) kmin_at[k] = kmin;
             }
             bulk[2][k] = agg;
@@ -302,6 +348,18 @@ struct Layout {
         for (int k = p - 2; k >= 0; --k) {
             suffix_min = std::min(suffix_min, kmin_at[k]);
             needq[k] = lowp && (col[2][k].e > col[2][k].b || suffix_min <= k);
+        }
+        for (int q = 0; q < 2; ++q) {
+            const std::vector<TileIJ> &lst = *lists[q];
+            next_b[q].assign(p, 0);
+            next_f[q].assign(p, 0.0);
+            for (int k = 0; k + 1 < p; ++k) {
+                int64_t a = bulk[q][k].e;
+                while (a > bulk[q][k].b && lst[(size_t)a - 1].j == k + 2) --a;
+                next_b[q][k] = a;
+                for (int64_t t = a; t < bulk[q][k].e; ++t)
+                    next_f[q][k] += update_flops(lst[(size_t)t].i, lst[(size_t)t].j, k);
+            }
         }
         trsm64_flops.assign(p, 0.0);
         trsm32_flops.assign(p, 0.0);
@@ -336,7 +394,11 @@ struct mpgeo_ctx {
     // critical path then never wait for the wide update kernels to drain.  nullptr: the bulk
     // runs on `stream` with every CU.
     hipStream_t bulk = nullptr;
+    // column k+2's FP64 and FP32 updates of each step, beside the rest of the bulk (nullptr:
+    // on the bulk stream)
+    hipStream_t next = nullptr;
     int reserved_cus = 0;
+    int cus = 0;                           // compute units of the device
     std::vector<hipEvent_t> sync_events;   // dependency events between the two streams
 
     // at least `count` timing-free events for stream dependencies
@@ -436,7 +498,7 @@ struct mpgeo_dataset {
     // ordered inputs
     DevBuf locs, z, perm, keys, locs_in, z_in;
     // tiles and work buffers
-    DevBuf pool64, pool32, off, all, list64, list32, list16;
+    DevBuf pool64, pool32, off, all, list64, list32, list16, bulk16, bulk16k0;
     DevBuf p64, p32, linv, linv32, q16, qscale, qmax;
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
@@ -521,8 +583,10 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
             std::copy(b, b + 4, boxes.begin() + 4 * i);
         }
     }
+    const int nbp_new = (pl.tile + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
+    const int wave16 = pl.lowp ? lowp_wave_tiles(nbp_new, pl.lowp, ds->ctx->cus - ds->ctx->reserved_cus) : 0;
     L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp, pl.band0, dmap ? &boxes : nullptr,
-            pl.dist64, pl.dist32);
+            pl.dist64, pl.dist32, wave16);
     ds->has_factor = false;
     const size_t te = (size_t)L.nbp * L.nbp;
     const size_t tiles32 = (size_t)L.n32 + (L.has_zero_tile ? 1 : 0);
@@ -533,6 +597,8 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     MPGEO_TRY(ds->list64.ensure(std::max<size_t>(1, L.list64.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list32.ensure(std::max<size_t>(1, L.list32.size()) * sizeof(TileIJ)));
     MPGEO_TRY(ds->list16.ensure(std::max<size_t>(1, L.list16.size()) * sizeof(TileIJ)));
+    MPGEO_TRY(ds->bulk16.ensure(std::max<size_t>(1, L.bulk16.size()) * sizeof(TileIJ)));
+    MPGEO_TRY(ds->bulk16k0.ensure(std::max<size_t>(1, L.bulk16_k0.size()) * sizeof(int32_t)));
     if (L.lowp) {
         // 16-bit copy of the factor's tiles (slot tri_index(i, k)) and their scales
         const size_t slots = (size_t)L.p * (L.p + 1) / 2;
@@ -580,6 +646,12 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     if (!L.list16.empty())
         MPGEO_HIP(hipMemcpyAsync(ds->list16.ptr, L.list16.data(), L.list16.size() * sizeof(TileIJ),
                                  hipMemcpyHostToDevice, s));
+    if (!L.bulk16.empty()) {
+        MPGEO_HIP(hipMemcpyAsync(ds->bulk16.ptr, L.bulk16.data(), L.bulk16.size() * sizeof(TileIJ),
+                                 hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(ds->bulk16k0.ptr, L.bulk16_k0.data(),
+                                 L.bulk16_k0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
     MPGEO_HIP(hipStreamSynchronize(s));   // host vectors may change with the next build
     return MPGEO_OK;
 }
@@ -664,6 +736,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     hipStream_t s0 = ctx->stream;
     hipStream_t s1 = ctx->side;
     hipStream_t sb = ctx->bulk ? ctx->bulk : s0;   // bulk trailing updates
+    hipStream_t sa = ctx->next ? ctx->next : sb;   // column k+2 of the FP64/FP32 bulk
     const Layout &L = ds->layout;
     const TileMap map = tile_map(ds);
     const int nbp = L.nbp, p = L.p;
@@ -673,19 +746,24 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     double *logdet_part = ds->parts.as<double>();
     double *quad_part = logdet_part + p;
     unsigned long long *info = ds->info.as<unsigned long long>();
-    if (!ctx->ensure_sync_events(2 * (size_t)p + 1)) return MPGEO_E_DEVICE;
+    if (!ctx->ensure_sync_events(4 * (size_t)p + 1)) return MPGEO_E_DEVICE;
     hipEvent_t ev_start = ctx->sync_events[0];
     hipEvent_t *ev_f = ctx->sync_events.data() + 1;       // F(k) done
     hipEvent_t *ev_bulk = ev_f + p;                        // U_bulk(k) done
+    hipEvent_t *ev_next = ev_bulk + p;                     // U_next(k) done
+    hipEvent_t *ev_low = ev_next + p;                      // step k's 16-bit bulk pass done
     MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s0));
     launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
     MPGEO_HIP(hipEventRecord(ev_start, s0));
     MPGEO_HIP(hipStreamWaitEvent(s1, ev_start, 0));
     if (sb != s0) MPGEO_HIP(hipStreamWaitEvent(sb, ev_start, 0));
+    if (sa != sb) MPGEO_HIP(hipStreamWaitEvent(sa, ev_start, 0));
     const double nbd = L.nb;
     const TileIJ *l64 = ds->list64.as<TileIJ>();
     const TileIJ *l32 = ds->list32.as<TileIJ>();
     const TileIJ *l16 = ds->list16.as<TileIJ>();
+    const TileIJ *b16list = ds->bulk16.as<TileIJ>();
+    const int32_t *b16k0 = ds->bulk16k0.as<int32_t>();
     void *q16 = ds->q16.ptr;                    // 16-bit factor copy, tile (i, k) at tri_index(i, k)
     float *qscale = ds->qscale.as<float>();
     auto qmax = [&](int k) { return ds->qmax.as<unsigned>() + (size_t)(k & 1) * p; };
@@ -693,8 +771,9 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     auto panel64 = [&](int k) { return ds->p64.as<double>() + (size_t)(k & 1) * p * te; };
     auto panel32 = [&](int k) { return ds->p32.as<float>() + (size_t)(k & 1) * p * te; };
 
-    // F(k): POTRF, TRSM of the panel into staging (k & 1), panel solve of the forward solve
-    auto factor_step = [&](int k) {
+    // F(k): POTRF, TRSM of the panel into staging (k & 1), panel solve of the forward solve;
+    // potrf_step is its first part, which touches no staging buffer
+    auto potrf_args = [&](int k) {
         PotrfArgs pa;
         pa.a = ds->pool64.as<double>() + L.off[tri_index(k, k)];
         pa.linv = ds->linv.as<double>() + (int64_t)k * te;
@@ -707,10 +786,17 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         pa.col_base = (int64_t)k * L.nb;
         pa.nb = L.nb;
         pa.nbp = nbp;
+        return pa;
+    };
+    auto potrf_step = [&](int k) {
+        const PotrfArgs pa = potrf_args(k);
         const double rk = (double)L.rows(k);
         ctx->timed_on(s1, kStatPotrf, rk * rk * rk / 3.0, rk * rk * 8.0 * 3.0,
                       [&] { launch_potrf(pa, s1); });
+    };
+    auto panel_step = [&](int k) {
         if (k + 1 >= p) return;
+        const PotrfArgs pa = potrf_args(k);
         const int npanel = L.panel_count(k);            // panel tiles that are not dropped
         const int n64 = std::min(L.band, npanel);
         const int first32 = k + n64 + 1;
@@ -753,7 +839,8 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
                       [&] { launch_panel_solve(map, k, npanel, p64, pa.y, r, s1); });
     };
     // update of list entries [b, e) of each tier with panel k on stream st; the 16-bit entries
-    // take panels [kbeg16, k] (the bulk pass: kbeg16 = 0; the lookahead column: kbeg16 = k).
+    // take panels [k0, k] (the bulk pass: entries of the bulk16 list, each with its own k0; the
+    // lookahead column: entries of list16, k0 = k).
     // Algorithmic bytes: every output tile read and written once, every operand tile it needs
     // read once (FP64/FP32: at most p - 1 - k distinct panel tiles, at most two per output
     // tile; 16-bit bulk: the operand tiles counted by the layout).
@@ -762,13 +849,16 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
                             double panels16, hipStream_t st) {
         const double tile_elems = (double)nbd * nbd;
         auto panel_tiles = [&](int64_t count) { return (double)std::min<int64_t>(L.panel_count(k), 2 * count); };
-        const int kbeg16 = lookahead ? k : 0;
         if (e16 > b16)
             ctx->timed_on(st, lookahead ? kStatUpdate16Col : kStatUpdate16, f16,
                           tile_elems * ((double)(e16 - b16) * 4.0 * 2.0 +
                                         (lookahead ? panel_tiles(e16 - b16) : panels16) * 2.0), [&] {
-                launch_update_lowp(map, l16 + b16, e16 - b16, kbeg16, k + 1, L.zband, q16, qscale,
-                                   L.lowp, st);
+                if (lookahead)
+                    launch_update_lowp(map, l16 + b16, e16 - b16, k, k + 1, L.zband, q16, qscale,
+                                       L.lowp, st);
+                else
+                    launch_update_lowp(map, b16list + b16, e16 - b16, 0, k + 1, L.zband, q16, qscale,
+                                       L.lowp, st, b16k0 + b16);
             });
         if (e64 > b64)
             ctx->timed_on(st, kStatUpdate64, f64,
@@ -783,29 +873,49 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
             });
     };
 
-    factor_step(0);
+    potrf_step(0);
+    panel_step(0);
     MPGEO_HIP(hipEventRecord(ev_f[0], s1));
     for (int k = 0; k < p; ++k) {
-        // bulk: tile columns >= k+2
+        // U_next(k): column k+2's FP64 and FP32 tiles, after F(k) and U_bulk(k-1)
+        MPGEO_HIP(hipStreamWaitEvent(sa, ev_f[k], 0));
+        if (sa != sb && k >= 1) MPGEO_HIP(hipStreamWaitEvent(sa, ev_bulk[k - 1], 0));
+        if (k + 1 < p)
+            update_range(k, L.next_b[0][k], L.bulk[0][k].e, L.next_b[1][k], L.bulk[1][k].e, 0, 0,
+                         L.next_f[0][k], L.next_f[1][k], 0.0, false, 0.0, sa);
+        MPGEO_HIP(hipEventRecord(ev_next[k], sa));
+        // U_bulk(k): the 16-bit pass (column k+2), then FP64 and FP32 columns >= k+3
         MPGEO_HIP(hipStreamWaitEvent(sb, ev_f[k], 0));
         if (k + 1 < p)
-            update_range(k, L.bulk[0][k].b, L.bulk[0][k].e, L.bulk[1][k].b, L.bulk[1][k].e,
-                         L.bulk[2][k].b, L.bulk[2][k].e, L.bulk[0][k].flops, L.bulk[1][k].flops,
+            update_range(k, 0, 0, 0, 0, L.bulk[2][k].b, L.bulk[2][k].e, 0.0, 0.0,
                          L.bulk[2][k].flops, false, L.bulk[2][k].panels, sb);
+        MPGEO_HIP(hipEventRecord(ev_low[k], sb));
+        if (k + 1 < p)
+            update_range(k, L.bulk[0][k].b, L.next_b[0][k], L.bulk[1][k].b, L.next_b[1][k], 0, 0,
+                         L.bulk[0][k].flops - L.next_f[0][k], L.bulk[1][k].flops - L.next_f[1][k],
+                         0.0, false, 0.0, sb);
         MPGEO_HIP(hipEventRecord(ev_bulk[k], sb));
         if (k + 1 < p) {
-            // critical path: column k+1 (list range [pre[k+1], pre[k])), then F(k+1)
-            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
+            // critical path: column k+1 (complete up to panel k-1 once U_next(k-1) and step
+            // k-1's 16-bit pass are done), POTRF(k+1), then the rest of F(k+1), which writes
+            // staging buffer (k+1) & 1 and so waits for U_bulk(k-1), its last reader
+            if (k >= 1) {
+                MPGEO_HIP(hipStreamWaitEvent(s1, ev_next[k - 1], 0));
+                MPGEO_HIP(hipStreamWaitEvent(s1, ev_low[k - 1], 0));
+            }
             update_range(k, L.col[0][k].b, L.col[0][k].e, L.col[1][k].b, L.col[1][k].e,
                          L.col[2][k].b, L.col[2][k].e, L.col[0][k].flops, L.col[1][k].flops,
                          L.col[2][k].flops, true, 0.0, s1);
-            factor_step(k + 1);
+            potrf_step(k + 1);
+            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
+            panel_step(k + 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
         MPGEO_HIP(hipGetLastError());
     }
     MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[p - 1], 0));
     if (sb != s0) MPGEO_HIP(hipStreamWaitEvent(s0, ev_bulk[p - 1], 0));
+    if (sa != s0) MPGEO_HIP(hipStreamWaitEvent(s0, ev_next[p - 1], 0));
     if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s0));
     ctx->timed(kStatFinal, 2.0 * p, 16.0 * p, [&] {
         launch_finalize(logdet_part, quad_part, p, L.n, ds->profile, ds->result.as<double>(), s0);
@@ -1035,7 +1145,15 @@ int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {
         delete c;
         return MPGEO_E_DEVICE;
     }
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        (void)hipGetLastError();
+        c->cus = 0;
+    }
     create_bulk_stream(c);
+    if (!c->bulk && hipStreamCreateWithFlags(&c->next, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        c->next = nullptr;
+    }
     c->reset_stats();
     *out = c;
     return MPGEO_OK;
@@ -1056,6 +1174,10 @@ int mpgeo_ctx_destroy(mpgeo_ctx *ctx) {
     for (auto e : ctx->sync_events) (void)hipEventDestroy(e);
     (void)hipStreamSynchronize(ctx->side);
     (void)hipStreamDestroy(ctx->side);
+    if (ctx->next) {
+        (void)hipStreamSynchronize(ctx->next);
+        (void)hipStreamDestroy(ctx->next);
+    }
     if (ctx->bulk) {
         (void)hipStreamSynchronize(ctx->bulk);
         (void)hipStreamDestroy(ctx->bulk);
@@ -1103,7 +1225,7 @@ int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
     (void)hipStreamSynchronize(ds->ctx->stream);
     for (DevBuf *b : {&ds->locs, &ds->z, &ds->perm, &ds->keys, &ds->locs_in, &ds->z_in,
                       &ds->pool64, &ds->pool32, &ds->off, &ds->all, &ds->list64, &ds->list32,
-                      &ds->list16, &ds->q16, &ds->qscale, &ds->qmax,
+                      &ds->list16, &ds->bulk16, &ds->bulk16k0, &ds->q16, &ds->qscale, &ds->qmax,
                       &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
                       &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c, &ds->fp64tab,
                       &ds->trsm64l, &ds->trsm32l})
@@ -1481,7 +1603,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
     }
     (void)hipStreamSynchronize(s);
     for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.list16,
-                      &ds.q16, &ds.qscale, &ds.qmax, &ds.p64,
+                      &ds.bulk16, &ds.bulk16k0, &ds.q16, &ds.qscale, &ds.qmax, &ds.p64,
                       &ds.p32, &ds.linv, &ds.linv32, &ds.r, &ds.y, &ds.parts, &ds.info, &ds.result,
                       &ds.tmp_a, &ds.z})
         b->release();

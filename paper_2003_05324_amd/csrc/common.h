@@ -127,9 +127,14 @@ void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool f
 void launch_quantize(const TileMap &map, int k, int first, int count, const float *p32,
                      const unsigned *absmax, void *q, float *scale, int lowp, hipStream_t stream);
 // Third tier: A_ij -= sum_k s_ik s_jk Q_ik Q_jk^T over list[0, count) (FP32-stored tiles), for
-// panels k in [max(kbeg, i - zband), kend), ascending, from the 16-bit factor copy.
+// panels k in [max(k0, i - zband), kend), ascending, from the 16-bit factor copy; k0 is
+// kstart[t] for entry t when kstart is given, else kbeg.
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
-                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream);
+                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream,
+                        const int32_t *kstart = nullptr);
+// Output tiles the many-panel 16-bit update runs at once on `cus` compute units (one wave of
+// workgroups), 0 when unknown.
+int lowp_wave_tiles(int nbp, int lowp, int cus);
 
 // Panel step of the fused forward solve: r_i -= P64_i y_k for i = k+1 .. k+count, and copy
 // the finished panel tile (i, k) from staging into its storage precision.

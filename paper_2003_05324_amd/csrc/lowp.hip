@@ -81,8 +81,9 @@ struct LowpArgs {
     const TileIJ *list;
     const void *q;        // 16-bit factor copy: tile (i, k) at tri_index(i, k) * nbp^2, row-major
     const float *scale;   // power-of-two scale of tile (i, k) at tri_index(i, k)
-    int kbeg, kend;       // target (i, j) takes panels k in [max(kbeg, i - zband), kend)
+    int kbeg, kend;       // target (i, j) takes panels k in [max(k0, i - zband), kend)
     int zband;            // tiles (i, k) with i - k > zband are dropped (zero)
+    const int32_t *kstart;   // per list entry: its k0 (null: k0 = kbeg for every entry)
 };
 
 // BM x BN output block, WM x WN waves, K chunk KC, DEPTH chunks of operands in flight;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     const int row0 = (macro % rows_per) * BM;
     const int col0 = (macro / rows_per) * BN;
     const TileIJ tij = g.list[tile];
-    const int kfirst = max(g.kbeg, tij.i - g.zband);
+    const int kfirst = max(g.kstart ? g.kstart[tile] : g.kbeg, tij.i - g.zband);
     if (kfirst >= g.kend) return;
     const int cpp = nbp / KC;                           // chunks per panel
     const int nchunks = (g.kend - kfirst) * cpp;
@@ -270,15 +271,21 @@ void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
                        ga);
 }
 
+// many panels (the left-looking pass): 256 x 128 blocks when the tile allows, else 128 x 128
+template <typename T, int BM> struct ManyPanel;
+template <typename T> struct ManyPanel<T, 256> { using S = LShape<256, 128, 4, 2, 64, 1, 16>; };
+template <typename T> struct ManyPanel<T, 128> { using S = LShape<128, 128, 2, 2, 32, 1, 16>; };
+
 template <typename T>
 void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
     const int nbp = g.map.nbp;
-    if (g.kend - g.kbeg > 1 && nbp % 256 == 0) {
+    const bool many = g.kstart != nullptr || g.kend - g.kbeg > 1;
+    if (many && nbp % 256 == 0) {
         // many panels (the left-looking pass, long K): 256 x 128 blocks of 8 waves with 64 x 64
         // each, K chunks of 64 (measured 680-740 TFLOP/s at n ~ 1e5, 128 x 64 blocks: 555)
-        launch_lowp_shape<T, LShape<256, 128, 4, 2, 64, 1, 16>>(g, ntiles, stream);
-    } else if (g.kend - g.kbeg > 1 && nbp % 128 == 0) {
-        launch_lowp_shape<T, LShape<128, 128, 2, 2, 32, 1, 16>>(g, ntiles, stream);
+        launch_lowp_shape<T, typename ManyPanel<T, 256>::S>(g, ntiles, stream);
+    } else if (many && nbp % 128 == 0) {
+        launch_lowp_shape<T, typename ManyPanel<T, 128>::S>(g, ntiles, stream);
     } else if (nbp % 128 == 0) {
         // one panel (the lookahead column, K = nbp): 128 x 64 blocks, K chunks of 64 with two in
         // flight, LDS rows padded by 16 elements (no bank conflicts)
@@ -312,8 +319,9 @@ void launch_quantize(const TileMap &map, int k, int first, int count, const floa
 }
 
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
-                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream) {
-    if (count <= 0 || kend <= kbeg) return;
+                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream,
+                        const int32_t *kstart) {
+    if (count <= 0 || (!kstart && kend <= kbeg)) return;
     LowpArgs g{};
     g.map = map;
     g.list = list;
@@ -322,8 +330,32 @@ void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, i
     g.kbeg = kbeg;
     g.kend = kend;
     g.zband = zband;
+    g.kstart = kstart;
     if (lowp == 1) launch_lowp<_Float16>(g, count, stream);
     else launch_lowp<__bf16>(g, count, stream);
+}
+
+namespace {
+template <typename T, int BM> int wave_tiles_of(int nbp, int cus) {
+    using S = typename ManyPanel<T, BM>::S;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lowp_update_kernel<T, S>, S::kThreads, 0) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int per_tile = (nbp / S::BM) * (nbp / S::BN);
+    return per_cu > 0 ? cus * per_cu / per_tile : 0;
+}
+}  // namespace
+
+int lowp_wave_tiles(int nbp, int lowp, int cus) {
+    if (cus <= 0 || lowp < 1 || lowp > 2) return 0;
+    if (nbp % 256 == 0)
+        return lowp == 1 ? wave_tiles_of<_Float16, 256>(nbp, cus) : wave_tiles_of<__bf16, 256>(nbp, cus);
+    if (nbp % 128 == 0)
+        return lowp == 1 ? wave_tiles_of<_Float16, 128>(nbp, cus) : wave_tiles_of<__bf16, 128>(nbp, cus);
+    return 0;
 }
 
 }  // namespace mpgeo

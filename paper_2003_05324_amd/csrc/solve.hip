@@ -11,29 +11,41 @@ namespace {
 
 constexpr double kLog2Pi = 1.8378770664093454836;
 
-// r_i -= P64_i y_k (one thread per row; columns walked in order), and the finished panel
-// tile (i, k) is copied from staging into its storage precision.
+// r_i -= P64_i y_k, and the finished panel tile (i, k) is copied from staging into its storage
+// precision.  A workgroup takes 64 rows of one tile; each of its four waves walks a quarter of
+// the columns (one coalesced 64-row read per column) with four running sums, and the sums are
+// added in a fixed order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void panel_solve_kernel(TileMap map, int k, const double *p64,
                                                           const double *yk, double *r) {
     __shared__ double ys[kMaxTile];
+    __shared__ double part[4][64];
     const int nbp = map.nbp;
     const int i = k + 1 + blockIdx.x;
-    const int row = blockIdx.y * 256 + threadIdx.x;
+    const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int row = blockIdx.y * 64 + rl;
     for (int c = threadIdx.x; c < nbp; c += 256) ys[c] = yk[c];
     __syncthreads();
-    if (row >= nbp) return;
-    const double *P = p64 + (int64_t)i * nbp * nbp;
-    const bool f64 = tile_is_fp64(map, i, k);
-    const int64_t off = map.off[tri_index(i, k)];
-    double s = 0.0;
-    for (int c = 0; c < nbp; ++c) {
-        const int64_t e = row + (int64_t)c * nbp;
-        const double v = P[e];
-        s += v * ys[c];
-        if (f64) map.pool64[off + e] = v;
-        else map.pool32[off + e] = (float)v;   // exact: v is an FP32 value promoted
+    const int quarter = nbp / 4;   // a multiple of 8 (nbp is a multiple of 32)
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (row < nbp) {
+        const double *P = p64 + (int64_t)i * nbp * nbp;
+        const bool f64 = tile_is_fp64(map, i, k);
+        const int64_t off = map.off[tri_index(i, k)];
+        for (int c = g * quarter; c < (g + 1) * quarter; c += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t e = row + (int64_t)(c + u) * nbp;
+                const double v = P[e];
+                s[u] += v * ys[c + u];
+                if (f64) map.pool64[off + e] = v;
+                else map.pool32[off + e] = (float)v;   // exact: v is an FP32 value promoted
+            }
+        }
     }
-    r[(int64_t)i * nbp + row] -= s;
+    part[g][rl] = (s[0] + s[1]) + (s[2] + s[3]);
+    __syncthreads();
+    if (g == 0 && row < nbp)
+        r[(int64_t)i * nbp + row] -= (part[0][rl] + part[1][rl]) + (part[2][rl] + part[3][rl]);
 }
 
 // eq. (2) from the per-tile parts; with `profile` the tiles held the correlation matrix and
@@ -190,7 +202,7 @@ void launch_permute(const double *src, double *dst, const int64_t *perm, int64_t
 void launch_panel_solve(const TileMap &map, int k, int count, const double *p64, const double *yk,
                         double *r, hipStream_t stream) {
     if (count <= 0) return;
-    dim3 grid((unsigned)count, (unsigned)((map.nbp + 255) / 256));
+    dim3 grid((unsigned)count, (unsigned)((map.nbp + 63) / 64));
     hipLaunchKernelGGL(panel_solve_kernel, grid, dim3(256), 0, stream, map, k, p64, yk, r);
 }
 
