@@ -499,7 +499,7 @@ struct mpgeo_dataset {
     DevBuf locs, z, perm, keys, locs_in, z_in;
     // tiles and work buffers
     DevBuf pool64, pool32, off, all, list64, list32, list16, bulk16, bulk16k0;
-    DevBuf p64, p32, linv, linv32, q16, qscale, qmax;
+    DevBuf p64, p32, linv, linv32, q16, qscale;
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
     DevBuf fp64tab, trsm64l, trsm32l;   // distance-drawn precision map
@@ -603,8 +603,7 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
         // 16-bit copy of the factor's tiles (slot tri_index(i, k)) and their scales
         const size_t slots = (size_t)L.p * (L.p + 1) / 2;
         MPGEO_TRY(ds->q16.ensure(slots * te * 2));
-        MPGEO_TRY(ds->qscale.ensure(slots * sizeof(float)));
-        MPGEO_TRY(ds->qmax.ensure(2 * (size_t)L.p * sizeof(unsigned)));   // two steps in flight
+        MPGEO_TRY(ds->qscale.ensure((size_t)L.p * sizeof(float)));   // power of two per tile row
     }
     MPGEO_TRY(ds->p64.ensure(2 * (size_t)L.p * te * sizeof(double)));   // two steps in flight
     MPGEO_TRY(ds->p32.ensure(2 * (size_t)L.p * te * sizeof(float)));
@@ -754,6 +753,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     hipEvent_t *ev_low = ev_next + p;                      // step k's 16-bit bulk pass done
     MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s0));
     launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
+    if (L.lowp) launch_row_scale(map, ds->qscale.as<float>(), s0);   // from Sigma's diagonal
     MPGEO_HIP(hipEventRecord(ev_start, s0));
     MPGEO_HIP(hipStreamWaitEvent(s1, ev_start, 0));
     if (sb != s0) MPGEO_HIP(hipStreamWaitEvent(sb, ev_start, 0));
@@ -765,8 +765,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     const TileIJ *b16list = ds->bulk16.as<TileIJ>();
     const int32_t *b16k0 = ds->bulk16k0.as<int32_t>();
     void *q16 = ds->q16.ptr;                    // 16-bit factor copy, tile (i, k) at tri_index(i, k)
-    float *qscale = ds->qscale.as<float>();
-    auto qmax = [&](int k) { return ds->qmax.as<unsigned>() + (size_t)(k & 1) * p; };
+    float *qscale = ds->qscale.as<float>();     // power of two of each tile row (third tier)
 
     auto panel64 = [&](int k) { return ds->p64.as<double>() + (size_t)(k & 1) * p * te; };
     auto panel32 = [&](int k) { return ds->p32.as<float>() + (size_t)(k & 1) * p * te; };
@@ -803,37 +802,34 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         const int n32 = npanel - n64;
         double *p64 = panel64(k);
         float *p32 = panel32(k);
-        // this step updates low-tier tiles: the TRSM also records each panel tile's max |x|
-        const bool quant = L.lowp_step(k);
-        unsigned *amax = quant ? qmax(k) : nullptr;
-        if (quant) (void)hipMemsetAsync(amax, 0, (size_t)p * sizeof(unsigned), s1);
+        const bool quant = L.lowp_step(k);   // panel k gets a 16-bit copy
         if (L.distance_map()) {   // panel tiles of each precision as lists
             const int64_t b64 = L.trsm64_b[k], c64 = L.trsm64_b[k + 1] - b64;
             const int64_t b32 = L.trsm32_b[k], c32 = L.trsm32_b[k + 1] - b32;
             if (c64 > 0)
                 ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)c64 * nbd * nbd * 8.0 * 2.0, [&] {
-                    launch_trsm(map, k, 0, (int)c64, true, pa.linv, pa.linv32, p64, p32, amax, s1,
+                    launch_trsm(map, k, 0, (int)c64, true, pa.linv, pa.linv32, p64, p32, s1,
                                 /*narrow=*/c64 <= 4, ds->trsm64l.as<TileIJ>() + b64);
                 });
             if (c32 > 0)
                 ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)c32 * nbd * nbd * 4.0 * 2.0, [&] {
-                    launch_trsm(map, k, 0, (int)c32, false, pa.linv, pa.linv32, p64, p32, amax, s1,
+                    launch_trsm(map, k, 0, (int)c32, false, pa.linv, pa.linv32, p64, p32, s1,
                                 false, ds->trsm32l.as<TileIJ>() + b32);
                 });
         } else {
             if (n64 > 0)
                 ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
-                    launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, amax, s1,
+                    launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, s1,
                                 /*narrow=*/true);
                 });
             if (n32 > 0)
                 ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
-                    launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, amax, s1);
+                    launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, s1);
                 });
         }
         if (quant)   // 16-bit panel copy with per-tile power-of-two scales
             ctx->timed_on(s1, kStatQuant, 0.0, (double)npanel * nbd * nbd * 6.0, [&] {
-                launch_quantize(map, k, k + 1, npanel, p32, amax, q16, qscale, L.lowp, s1);
+                launch_quantize(map, k, k + 1, npanel, p32, qscale, q16, L.lowp, s1);
             });
         ctx->timed_on(s1, kStatPanel, 2.0 * npanel * nbd * nbd, (double)npanel * nbd * nbd * 16.0,
                       [&] { launch_panel_solve(map, k, npanel, p64, pa.y, r, s1); });
@@ -896,17 +892,18 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
                          0.0, false, 0.0, sb);
         MPGEO_HIP(hipEventRecord(ev_bulk[k], sb));
         if (k + 1 < p) {
-            // critical path: column k+1 (complete up to panel k-1 once U_next(k-1) and step
-            // k-1's 16-bit pass are done), POTRF(k+1), then the rest of F(k+1), which writes
-            // staging buffer (k+1) & 1 and so waits for U_bulk(k-1), its last reader
-            if (k >= 1) {
-                MPGEO_HIP(hipStreamWaitEvent(s1, ev_next[k - 1], 0));
-                MPGEO_HIP(hipStreamWaitEvent(s1, ev_low[k - 1], 0));
-            }
-            update_range(k, L.col[0][k].b, L.col[0][k].e, L.col[1][k].b, L.col[1][k].e,
-                         L.col[2][k].b, L.col[2][k].e, L.col[0][k].flops, L.col[1][k].flops,
-                         L.col[2][k].flops, true, 0.0, s1);
+            // Critical path: column k+1 takes panel k (its FP64 tiles, the diagonal tile among
+            // them, once U_next(k-1) is done), then POTRF(k+1); then the column's FP32 tiles and
+            // its 16-bit tiles (once step k-1's 16-bit pass is done), which only the panel TRSM
+            // needs; then the rest of F(k+1), which writes staging buffer (k+1) & 1 and so waits
+            // for U_bulk(k-1), its last reader.
+            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_next[k - 1], 0));
+            update_range(k, L.col[0][k].b, L.col[0][k].e, 0, 0, 0, 0, L.col[0][k].flops, 0.0, 0.0,
+                         true, 0.0, s1);
             potrf_step(k + 1);
+            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_low[k - 1], 0));
+            update_range(k, 0, 0, L.col[1][k].b, L.col[1][k].e, L.col[2][k].b, L.col[2][k].e, 0.0,
+                         L.col[1][k].flops, L.col[2][k].flops, true, 0.0, s1);
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
             panel_step(k + 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
@@ -1225,7 +1222,7 @@ int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
     (void)hipStreamSynchronize(ds->ctx->stream);
     for (DevBuf *b : {&ds->locs, &ds->z, &ds->perm, &ds->keys, &ds->locs_in, &ds->z_in,
                       &ds->pool64, &ds->pool32, &ds->off, &ds->all, &ds->list64, &ds->list32,
-                      &ds->list16, &ds->bulk16, &ds->bulk16k0, &ds->q16, &ds->qscale, &ds->qmax,
+                      &ds->list16, &ds->bulk16, &ds->bulk16k0, &ds->q16, &ds->qscale,
                       &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
                       &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c, &ds->fp64tab,
                       &ds->trsm64l, &ds->trsm32l})
@@ -1603,7 +1600,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
     }
     (void)hipStreamSynchronize(s);
     for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.list16,
-                      &ds.bulk16, &ds.bulk16k0, &ds.q16, &ds.qscale, &ds.qmax, &ds.p64,
+                      &ds.bulk16, &ds.bulk16k0, &ds.q16, &ds.qscale, &ds.p64,
                       &ds.p32, &ds.linv, &ds.linv32, &ds.r, &ds.y, &ds.parts, &ds.info, &ds.result,
                       &ds.tmp_a, &ds.z})
         b->release();

@@ -105,14 +105,12 @@ struct PotrfArgs {
 void launch_potrf(const PotrfArgs &a, hipStream_t stream);
 
 // Panel TRSM of step k through the explicit inverse: X_i = A_ik L_kk^-T for
-// i in [i_begin, i_begin + count); writes the staging panels P64[i], P32[i] and, when absmax
-// is not null, raises absmax[i] (float bits) to max |P32[i]| (for the third tier's scales).
-// Panel TRSM of step k for panel tiles i_begin .. i_begin+count-1, or, when `list` is not
-// null, for the tiles list[0 .. count-1] (their .i; a precision map drawn from distances).
+// i in [i_begin, i_begin + count), or, when `list` is not null, for the tiles
+// list[0 .. count-1] (their .i; a precision map drawn from distances); writes the staging
+// panels P64[i], P32[i].
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64,
                  const double *linv, const float *linv32, double *p64, float *p32,
-                 unsigned *absmax, hipStream_t stream, bool narrow = false,
-                 const TileIJ *list = nullptr);
+                 hipStream_t stream, bool narrow = false, const TileIJ *list = nullptr);
 
 // Trailing update of step k: A_ij -= P_i P_j^T over list[0, count) (tiles all of one
 // precision), with P the staging panel of that precision.
@@ -120,17 +118,19 @@ void launch_update(const TileMap &map, const TileIJ *list, int64_t count, bool f
                    const double *p64, const float *p32, hipStream_t stream,
                    bool narrow = false);
 
+// Third tier: the power of two s_i of each tile row i from the diagonal tiles of Sigma (to be
+// called before the factorization overwrites them), into rscale[0 .. p).
+void launch_row_scale(const TileMap &map, float *rscale, hipStream_t stream);
 // Third tier: quantise panel tiles (i, k), i in [first, first + count), of the FP32 staging
-// panel (tile i at p32 + i * nbp^2) to 16-bit (lowp 1: FP16, 2: BF16), row-major, into the
-// 16-bit factor copy q at slot tri_index(i, k), with the power-of-two scale of each tile
-// derived from absmax[i] (float bits of max |P32[i]|) stored at scale[tri_index(i, k)].
+// panel (tile i at p32 + i * nbp^2) to 16-bit (lowp 1: FP16, 2: BF16) as L_ik / s_i, row-major,
+// into the 16-bit factor copy q at slot tri_index(i, k).
 void launch_quantize(const TileMap &map, int k, int first, int count, const float *p32,
-                     const unsigned *absmax, void *q, float *scale, int lowp, hipStream_t stream);
-// Third tier: A_ij -= sum_k s_ik s_jk Q_ik Q_jk^T over list[0, count) (FP32-stored tiles), for
-// panels k in [max(k0, i - zband), kend), ascending, from the 16-bit factor copy; k0 is
-// kstart[t] for entry t when kstart is given, else kbeg.
+                     const float *rscale, void *q, int lowp, hipStream_t stream);
+// Third tier: A_ij <- s_i s_j (A_ij / (s_i s_j) - sum_k Q_ik Q_jk^T) over list[0, count)
+// (FP32-stored tiles), for panels k in [max(k0, i - zband), kend), ascending, from the 16-bit
+// factor copy; k0 is kstart[t] for entry t when kstart is given, else kbeg.
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
-                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream,
+                        int zband, const void *q, const float *rscale, int lowp, hipStream_t stream,
                         const int32_t *kstart = nullptr);
 // Output tiles the many-panel 16-bit update runs at once on `cus` compute units (one wave of
 // workgroups), 0 when unknown.

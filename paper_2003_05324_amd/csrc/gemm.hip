@@ -56,7 +56,6 @@ struct GemmArgs {
     const void *linv;     // trsm: L_kk^-1 in the kernel's precision
     double *p64;          // trsm outputs
     float *p32;
-    unsigned *absmax;     // trsm, optional: per panel tile, max |FP32 output| as float bits
 };
 
 // Block shape: BM output rows x BN output columns per workgroup, WM x WN waves, K chunk KC.
@@ -246,7 +245,6 @@ __global__ __launch_bounds__(S::kThreads) void tile_gemm_kernel(GemmArgs g) {
     } else {
         double *o64 = g.p64 + (int64_t)ti * nbp * nbp;
         float *o32 = g.p32 + (int64_t)ti * nbp * nbp;
-        float amax = 0.0f;
 #pragma unroll
         for (int a = 0; a < NBC; ++a)
 #pragma unroll
@@ -257,15 +255,9 @@ __global__ __launch_bounds__(S::kThreads) void tile_gemm_kernel(GemmArgs g) {
                     const int col = col0 + wcol + a * 16 + M::m_index(lk, q);
                     const int64_t e = row + (int64_t)col * nbp;
                     const T v = acc[a][b][q];
-                    const float v32 = (float)v;   // FP64 result rounded to nearest even / FP32 kept
                     o64[e] = (double)v;
-                    o32[e] = v32;
-                    amax = fmaxf(amax, fabsf(v32));
+                    o32[e] = (float)v;   // FP64 result rounded to nearest even / FP32 kept
                 }
-        if (g.absmax) {   // tile-wide max |x| for the third tier's per-tile scale
-            for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_down(amax, off, 64));
-            if (lane == 0) atomicMax(g.absmax + ti, __float_as_uint(amax));
-        }
     }
 }
 
@@ -306,8 +298,8 @@ void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream, bool nar
 }  // namespace
 
 void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, const double *linv,
-                 const float *linv32, double *p64, float *p32, unsigned *absmax,
-                 hipStream_t stream, bool narrow, const TileIJ *list) {
+                 const float *linv32, double *p64, float *p32, hipStream_t stream, bool narrow,
+                 const TileIJ *list) {
     if (count <= 0) return;
     GemmArgs g{};
     g.map = map;
@@ -316,7 +308,6 @@ void launch_trsm(const TileMap &map, int k, int i_begin, int count, bool fp64, c
     g.list = list;
     g.p64 = p64;
     g.p32 = p32;
-    g.absmax = absmax;
     if (fp64) {
         g.linv = linv;
         launch_gemm<double, kTrsm>(g, count, stream, narrow);

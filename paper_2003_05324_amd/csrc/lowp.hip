@@ -2,18 +2,24 @@
 // the matrix cores (the paper's future work, Section IX: more than two precision layers).
 //
 // Tiles with i - j > band64 + band32 keep FP32 storage and FP32 accumulation; only the
-// operands of their update A_ij -= sum_k L_ik L_jk^T drop to a 16-bit format.  After the
-// panel of step k is solved, every panel tile L_ik is quantised once into a 16-bit copy of
-// the factor that lives for the whole factorization:
-//   s_ik = 2^ceil(log2 max|L_ik|)   (a power of two, so the scaling is exact),
-//   Q_ik = round_to_nearest_even(L_ik / s_ik)   in FP16 or BF16,
-// stored row-major (K contiguous) at tile slot tri_index(i, k).  A far tile then takes all
-// its panels in one pass (left-looking):
-//   A_ij <- A_ij - sum_k (s_ik s_jk) (Q_ik Q_jk^T)
-// where each panel's product comes from v_mfma_f32_16x16x32_{f16,bf16} accumulating in FP32
-// and is folded into the FP32 running value of A_ij by one fused multiply-add per element,
-// panel by panel in ascending k.  That is the same sequence of FP32 roundings as applying the
-// panels one step at a time, but A_ij is read and written once instead of once per panel.
+// operands of their update A_ij -= sum_k L_ik L_jk^T drop to a 16-bit format.
+//
+// Scaling.  Row r of the factor satisfies sum_k L_rk^2 = Sigma_rr, so |L_rk| <= sqrt(Sigma_rr).
+// Tile row i takes one power of two from the diagonal of Sigma before the factorization,
+//   s_i = 2^max(e_i - 14, -60),   e_i = ceil(log2 sqrt(max_{r in row block i} Sigma_rr)),
+// so every 16-bit operand Q_ik = round_to_nearest_even(L_ik / s_i) lies below 2^14 in magnitude
+// (FP16 holds up to 65504) and entries down to 2^-28 of the row's bound stay normal FP16
+// numbers.  After the panel of step k is solved, each panel tile is quantised once into a
+// 16-bit copy of the factor that lives for the whole factorization (tile (i, k) at slot
+// tri_index(i, k), row-major, K contiguous).
+//
+// Update.  A far tile takes its panels in one left-looking pass:
+//   A_ij <- s_i s_j (A_ij / (s_i s_j) - sum_k Q_ik Q_jk^T),
+// with the FP32 accumulator of each element starting at A_ij / (s_i s_j) (exact: a power of
+// two) and v_mfma_f32_16x16x32_{f16,bf16} adding -Q_ik Q_jk^T to it 32 products at a time,
+// panels in ascending k; the final product by s_i s_j is exact again.  Each element therefore
+// sees one fixed sequence of FP32 roundings, set by the panels it takes and not by how they
+// are split between launches.
 #include "common.h"
 
 namespace mpgeo {
@@ -41,32 +47,46 @@ template <> struct Lowp<__bf16> {
 constexpr int kXcds = 8;
 constexpr int kQThreads = 256;
 
-// One workgroup per 64 x 64 block of panel tile (i, k): scale by the tile's power of two
-// s = 2^e with 2^(e-1) < max|x| <= 2^e (s = 1 for an all-zero tile), round to the 16-bit
-// format (nearest even) and store transposed (row-major, K contiguous) at slot tri_index(i, k).
+// Power of two of each tile row from the diagonal tiles of Sigma (before factorization):
+// s_i = 2^max(e_i - 14, -60) with e_i = ceil(log2 sqrt(max Sigma_rr)) over the row block's
+// rows; s_i = 1 when that maximum is not positive (the factorization then fails anyway).
+__global__ __launch_bounds__(64) void row_scale_kernel(TileMap map, float *rscale) {
+    const int i = blockIdx.x;
+    const int rows = (int)min((int64_t)map.nb, map.n - (int64_t)i * map.nb);
+    const double *d = map.pool64 + map.off[tri_index(i, i)];
+    double mx = 0.0;
+    for (int r = threadIdx.x; r < rows; r += 64) mx = fmax(mx, d[r + (int64_t)r * map.nbp]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (threadIdx.x == 0) {
+        int es = 0;
+        if (mx > 0.0) {
+            int ex = 0;
+            const double fr = frexp(sqrt(mx), &ex);   // sqrt(mx) = fr * 2^ex, fr in [0.5, 1)
+            if (fr == 0.5) ex -= 1;                    // an exact power of two is its own bound
+            es = max(ex - 14, -60);
+        }
+        rscale[i] = ldexpf(1.0f, es);
+    }
+}
+
+// One workgroup per QB x QB block of panel tile (i, k): divide by the row's power of two
+// (exact), round to the 16-bit format (nearest even) and store transposed (row-major, K
+// contiguous) at slot tri_index(i, k).
 template <typename T, int QB>
-__global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, const unsigned *absmax,
-                                                             T *q, float *scale, int k, int first,
-                                                             int nbp) {
+__global__ __launch_bounds__(kQThreads) void quantize_kernel(const float *p32, const float *rscale,
+                                                             T *q, int k, int first, int nbp) {
     __shared__ float blk[QB][QB + 1];
     const int per_side = nbp / QB;
     const int i = first + blockIdx.x / (per_side * per_side);
     const int b = blockIdx.x % (per_side * per_side);
     const int r0 = (b % per_side) * QB, t0 = (b / per_side) * QB;
-    const float mx = __uint_as_float(absmax[i]);
-    int ex = 0;
-    if (mx > 0.0f) {
-        const float fr = frexpf(mx, &ex);   // mx = fr * 2^ex, fr in [0.5, 1)
-        if (fr == 0.5f) ex -= 1;            // an exact power of two maps to 1
-    }
-    const float inv = ldexpf(1.0f, -ex);
+    const float inv = 1.0f / rscale[i];   // a power of two
     const int64_t slot = tri_index(i, k);
-    if (b == 0 && threadIdx.x == 0) scale[slot] = ldexpf(1.0f, ex);
     const float *src = p32 + (int64_t)i * nbp * nbp;
     T *dst = q + slot * nbp * nbp;
     for (int e = threadIdx.x; e < QB * QB; e += kQThreads) {
         const int rr = e % QB, tt = e / QB;
-        blk[rr][tt] = src[(r0 + rr) + (int64_t)(t0 + tt) * nbp] * inv;   // exact (power of two)
+        blk[rr][tt] = src[(r0 + rr) + (int64_t)(t0 + tt) * nbp] * inv;   // exact
     }
     __syncthreads();
     for (int e = threadIdx.x; e < QB * QB; e += kQThreads) {
@@ -80,7 +100,7 @@ struct LowpArgs {
     int64_t ntiles;
     const TileIJ *list;
     const void *q;        // 16-bit factor copy: tile (i, k) at tri_index(i, k) * nbp^2, row-major
-    const float *scale;   // power-of-two scale of tile (i, k) at tri_index(i, k)
+    const float *rscale;  // power of two of each tile row
     int kbeg, kend;       // target (i, j) takes panels k in [max(k0, i - zband), kend)
     int zband;            // tiles (i, k) with i - k > zband are dropped (zero)
     const int32_t *kstart;   // per list entry: its k0 (null: k0 = kbeg for every entry)
@@ -95,13 +115,14 @@ struct LShape {
 };
 
 // One BM x BN block of target tile (i, j):
-//   C <- C - sum over panels k of (s_ik s_jk) * sum_t Q_ik[row][t] Q_jk[col][t].
-// The C block is held in registers for the whole K loop (its load latency hides behind the
-// first chunks); each panel's product is accumulated from zero and folded in at the panel's end.
+//   C <- s_i s_j (C / (s_i s_j) - sum over panels k of sum_t Q_ik[row][t] Q_jk[col][t]).
+// The block's accumulators are held in registers for the whole K loop (their load latency
+// hides behind the first chunks); the row operand is negated as it is staged into LDS.
 template <typename T, typename S>
 __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     using L = Lowp<T>;
     using vec8 = typename L::vec8;
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     constexpr int BM = S::BM, BN = S::BN, KC = S::KC, NT = S::kThreads;
     constexpr int NBR = BM / S::WM / 16;
     constexpr int NBC = BN / S::WN / 16;
@@ -133,8 +154,8 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     // panel k's operands: tile (i, k) = tile (i, 0) + k
     const T *R0 = qbase + tri_index(tij.i, kfirst) * te + (int64_t)row0 * nbp;
     const T *Q0 = qbase + tri_index(tij.j, kfirst) * te + (int64_t)col0 * nbp;
-    const float *si = g.scale + tri_index(tij.i, 0);
-    const float *sj = g.scale + tri_index(tij.j, 0);
+    const float f = g.rscale[tij.i] * g.rscale[tij.j];   // a power of two (at least 2^-120)
+    const float inv_f = 1.0f / f;
     float *C = g.map.pool32 + g.map.off[tri_index(tij.i, tij.j)];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -142,16 +163,14 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     const int wcol = (wave / S::WM) * (BN / S::WN);
     const int lr = lane & 15, lg = lane >> 4;
 
-    f32x4 acc[NBC][NBR], cv[NBC][NBR];
+    f32x4 acc[NBC][NBR];
 #pragma unroll
     for (int a = 0; a < NBC; ++a)
 #pragma unroll
-        for (int b = 0; b < NBR; ++b) {
-            acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NBR; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                cv[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp];
-        }
+                acc[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp] * inv_f;
 
     // Operand chunks stream global -> registers -> LDS.  Chunk x waits in register set
     // x % DEPTH; DEPTH chunks are in flight while the chunk in LDS feeds the matrix cores
@@ -191,7 +210,9 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             const int idx = v * NT + tid;
             if (NVR % NT == 0 || idx < NVR) {
                 const int row = idx / VPR_ROW, col = idx % VPR_ROW;
-                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + col * 8]) = sr[v];
+                // -Q_ik: flip the sign bit of each 16-bit value (exact)
+                const u32x4 neg = __builtin_bit_cast(u32x4, sr[v]) ^ 0x80008000u;
+                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + col * 8]) = __builtin_bit_cast(vec8, neg);
             }
         }
     };
@@ -212,20 +233,6 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
                 for (int b = 0; b < NBR; ++b) acc[a][b] = L::mac(qa[a], rb[b], acc[a][b]);
         }
     };
-    // end of panel kfirst + c / cpp: C += (-s_ik s_jk) * product, then restart the product
-    auto fold = [&](int c) {
-        const int k = kfirst + c / cpp;
-        const float factor = -si[k] * sj[k];
-#pragma unroll
-        for (int a = 0; a < NBC; ++a)
-#pragma unroll
-            for (int b = 0; b < NBR; ++b)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    cv[a][b][q] = cv[a][b][q] + factor * acc[a][b][q];
-                    acc[a][b][q] = 0.f;
-                }
-    };
 
 #pragma unroll
     for (int j = 0; j < D; ++j)
@@ -239,7 +246,6 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             const int c = c0 + j;
             if (c < nchunks) {
                 compute(c & 1);
-                if (c % cpp == cpp - 1) fold(c);
                 const int nxt = (j + 1) % D;   // register set of chunk c + 1
                 if (c + 1 < nchunks) store_chunk(rq[nxt], rr[nxt], (c + 1) & 1);
                 if (c + 1 + D < nchunks) load_chunk(rq[nxt], rr[nxt], c + 1 + D);
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             for (int q = 0; q < 4; ++q) {
                 const int row = row0 + wrow + b * 16 + lr;
                 const int col = col0 + wcol + a * 16 + 4 * lg + q;
-                C[row + (int64_t)col * nbp] = cv[a][b][q];
+                C[row + (int64_t)col * nbp] = acc[a][b][q] * f;
             }
 }
 
@@ -271,9 +277,9 @@ void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
                        ga);
 }
 
-// many panels (the left-looking pass): 256 x 128 blocks when the tile allows, else 128 x 128
+// many panels (the left-looking pass): 256 x 256 blocks when the tile allows, else 128 x 128
 template <typename T, int BM> struct ManyPanel;
-template <typename T> struct ManyPanel<T, 256> { using S = LShape<256, 128, 4, 2, 64, 1, 16>; };
+template <typename T> struct ManyPanel<T, 256> { using S = LShape<256, 256, 4, 4, 64, 1, 16>; };
 template <typename T> struct ManyPanel<T, 128> { using S = LShape<128, 128, 2, 2, 32, 1, 16>; };
 
 template <typename T>
@@ -281,8 +287,9 @@ void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
     const int nbp = g.map.nbp;
     const bool many = g.kstart != nullptr || g.kend - g.kbeg > 1;
     if (many && nbp % 256 == 0) {
-        // many panels (the left-looking pass, long K): 256 x 128 blocks of 8 waves with 64 x 64
-        // each, K chunks of 64 (measured 680-740 TFLOP/s at n ~ 1e5, 128 x 64 blocks: 555)
+        // many panels (the left-looking pass, long K): 256 x 256 blocks of 16 waves with 64 x 64
+        // each, K chunks of 64, all of the LDS (measured alone on n ~ 1e5 columns: 850-910
+        // TFLOP/s; 256 x 128 blocks of 8 waves: 705-770)
         launch_lowp_shape<T, typename ManyPanel<T, 256>::S>(g, ntiles, stream);
     } else if (many && nbp % 128 == 0) {
         launch_lowp_shape<T, typename ManyPanel<T, 128>::S>(g, ntiles, stream);
@@ -299,15 +306,19 @@ void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
 
 }  // namespace
 
+void launch_row_scale(const TileMap &map, float *rscale, hipStream_t stream) {
+    hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)map.p), dim3(64), 0, stream, map, rscale);
+}
+
 void launch_quantize(const TileMap &map, int k, int first, int count, const float *p32,
-                     const unsigned *absmax, void *q, float *scale, int lowp, hipStream_t stream) {
+                     const float *rscale, void *q, int lowp, hipStream_t stream) {
     if (count <= 0) return;
     const int qb = (map.nbp % 64 == 0) ? 64 : 32;   // transpose block (nbp is a multiple of 32)
     const int per_side = map.nbp / qb;
     const unsigned blocks = (unsigned)((int64_t)count * per_side * per_side);
 #define MPGEO_QUANT(T, QB)                                                                          \
-    hipLaunchKernelGGL((quantize_kernel<T, QB>), dim3(blocks), dim3(kQThreads), 0, stream, p32, absmax, \
-                       static_cast<T *>(q), scale, k, first, map.nbp)
+    hipLaunchKernelGGL((quantize_kernel<T, QB>), dim3(blocks), dim3(kQThreads), 0, stream, p32, rscale, \
+                       static_cast<T *>(q), k, first, map.nbp)
     if (lowp == 1) {
         if (qb == 64) MPGEO_QUANT(_Float16, 64);
         else MPGEO_QUANT(_Float16, 32);
@@ -319,14 +330,14 @@ void launch_quantize(const TileMap &map, int k, int first, int count, const floa
 }
 
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
-                        int zband, const void *q, const float *scale, int lowp, hipStream_t stream,
+                        int zband, const void *q, const float *rscale, int lowp, hipStream_t stream,
                         const int32_t *kstart) {
     if (count <= 0 || (!kstart && kend <= kbeg)) return;
     LowpArgs g{};
     g.map = map;
     g.list = list;
     g.q = q;
-    g.scale = scale;
+    g.rscale = rscale;
     g.kbeg = kbeg;
     g.kend = kend;
     g.zband = zband;
