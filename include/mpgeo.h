@@ -16,11 +16,14 @@
  * log-determinant) are always FP64.  The forward solve accumulates in FP64.
  * Optional third tier (more precision layers, the paper's future work in Section IX):
  * with band32 = c >= 0 and lowp = 1 (FP16) or 2 (BF16), tiles with i - j > band64 + c stay
- * FP32-stored but their trailing updates take 16-bit operands: each finished panel tile
- * L_ik is scaled by s_ik = 2^ceil(log2 max|L_ik|) and rounded to nearest-even once into a
- * 16-bit copy of the factor, and A_ij -= s_ik s_jk (Q_ik Q_jk^T) runs on the matrix cores with
- * FP32 accumulation, panel by panel in ascending k (a far tile takes all its earlier panels
- * in one pass two steps before it is solved).
+ * FP32-stored but their trailing updates take 16-bit operands.  Tile row i has one power of
+ * two s_i = 2^max(e_i - 14, -60), e_i = ceil(log2 sqrt(max Sigma_rr)) over its rows (every
+ * |L_rk| <= sqrt(Sigma_rr)); each finished panel tile is rounded to nearest-even once into a
+ * 16-bit copy Q_ik = L_ik / s_i of the factor, and a far tile is updated as
+ * A_ij <- s_i s_j (A_ij / (s_i s_j) - sum_k Q_ik Q_jk^T) on the matrix cores, accumulating in
+ * FP32 from the scaled A_ij, panels in ascending k (a far tile takes its earlier panels in
+ * one pass about two steps before it is solved; the result does not depend on how the
+ * panels are grouped into passes).
  *
  * Conventions for every entry point:
  *  - Return value: an mpgeo_status code; MPGEO_OK (0) on success.

@@ -720,16 +720,19 @@ int run_covgen(mpgeo_dataset *ds, const mpgeo_theta &th) {
 
 // Factor the resident tiles, fused with the forward solve of z, then reduce.
 //
-// Two streams: the context stream runs the bulk of each step's trailing update (tile
-// columns j >= k+2); the side stream runs the critical path one step ahead: the update of
-// column k+1, then POTRF, panel solve and forward-solve step of k+1 (lookahead of depth 1).
-// Staging panels alternate between two buffers so step k+1's panel can be written while
-// step k's bulk update still reads step k's.  Dependencies:
+// Three streams: the bulk stream runs most of each step's trailing update (tile columns
+// j >= k+3, and the 16-bit pass); a second stream runs column k+2's FP64 and FP32 updates,
+// which the next lookahead step needs first; the side stream runs the critical path one step
+// ahead: the update of column k+1, then POTRF, panel TRSMs, quantiser and forward-solve step
+// of k+1 (lookahead of depth 1).  Staging panels alternate between two buffers so step k+1's
+// panel can be written while step k's updates still read step k's.  Dependencies:
 //   F(k)        = POTRF + TRSM + panel solve of step k            (side stream)
-//   U_col(k)    = update of column k+1 with panel k               (side; after U_bulk(k-1))
-//   U_bulk(k)   = update of columns >= k+2 with panel k           (main; after F(k))
-// except in the 16-bit tier, whose tiles wait: U_bulk(k) gives column k+2's 16-bit tiles
-// panels 0 .. k at once from the 16-bit factor copy, and U_col(k+1) adds panel k+1.
+//   U_col(k)    = update of column k+1 with panel k               (side; after U_next(k-1))
+//   U_next(k)   = update of column k+2 with panel k               (second; after F(k), U_bulk(k-1))
+//   U_bulk(k)   = update of columns >= k+3 with panel k           (bulk; after F(k))
+// and F(k+1)'s panel TRSMs wait for U_bulk(k-1), the last reader of their staging buffer.
+// The 16-bit tier's tiles wait instead: U_bulk(k) gives column k+2's 16-bit tiles panels
+// 0 .. k at once from the 16-bit factor copy, and U_col(k+1) adds panel k+1.
 int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     mpgeo_ctx *ctx = ds->ctx;
     hipStream_t s0 = ctx->stream;
@@ -745,12 +748,11 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     double *logdet_part = ds->parts.as<double>();
     double *quad_part = logdet_part + p;
     unsigned long long *info = ds->info.as<unsigned long long>();
-    if (!ctx->ensure_sync_events(4 * (size_t)p + 1)) return MPGEO_E_DEVICE;
+    if (!ctx->ensure_sync_events(3 * (size_t)p + 1)) return MPGEO_E_DEVICE;
     hipEvent_t ev_start = ctx->sync_events[0];
     hipEvent_t *ev_f = ctx->sync_events.data() + 1;       // F(k) done
     hipEvent_t *ev_bulk = ev_f + p;                        // U_bulk(k) done
     hipEvent_t *ev_next = ev_bulk + p;                     // U_next(k) done
-    hipEvent_t *ev_low = ev_next + p;                      // step k's 16-bit bulk pass done
     MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s0));
     launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
     if (L.lowp) launch_row_scale(map, ds->qscale.as<float>(), s0);   // from Sigma's diagonal
@@ -793,7 +795,9 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         ctx->timed_on(s1, kStatPotrf, rk * rk * rk / 3.0, rk * rk * 8.0 * 3.0,
                       [&] { launch_potrf(pa, s1); });
     };
-    auto panel_step = [&](int k) {
+    // part 0: the FP64 panel TRSM (needs only the column's FP64 tiles and POTRF); part 1: the
+    // FP32 panel TRSM, the quantiser and the panel solve
+    auto panel_step = [&](int k, int part) {
         if (k + 1 >= p) return;
         const PotrfArgs pa = potrf_args(k);
         const int npanel = L.panel_count(k);            // panel tiles that are not dropped
@@ -806,28 +810,29 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
         if (L.distance_map()) {   // panel tiles of each precision as lists
             const int64_t b64 = L.trsm64_b[k], c64 = L.trsm64_b[k + 1] - b64;
             const int64_t b32 = L.trsm32_b[k], c32 = L.trsm32_b[k + 1] - b32;
-            if (c64 > 0)
+            if (part == 0 && c64 > 0)
                 ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)c64 * nbd * nbd * 8.0 * 2.0, [&] {
                     launch_trsm(map, k, 0, (int)c64, true, pa.linv, pa.linv32, p64, p32, s1,
                                 /*narrow=*/c64 <= 4, ds->trsm64l.as<TileIJ>() + b64);
                 });
-            if (c32 > 0)
+            if (part == 1 && c32 > 0)
                 ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)c32 * nbd * nbd * 4.0 * 2.0, [&] {
                     launch_trsm(map, k, 0, (int)c32, false, pa.linv, pa.linv32, p64, p32, s1,
                                 false, ds->trsm32l.as<TileIJ>() + b32);
                 });
         } else {
-            if (n64 > 0)
+            if (part == 0 && n64 > 0)
                 ctx->timed_on(s1, kStatTrsm64, L.trsm64_flops[k], (double)n64 * nbd * nbd * 8.0 * 2.0, [&] {
                     launch_trsm(map, k, k + 1, n64, true, pa.linv, pa.linv32, p64, p32, s1,
                                 /*narrow=*/true);
                 });
-            if (n32 > 0)
+            if (part == 1 && n32 > 0)
                 ctx->timed_on(s1, kStatTrsm32, L.trsm32_flops[k], (double)n32 * nbd * nbd * 4.0 * 2.0, [&] {
                     launch_trsm(map, k, first32, n32, false, pa.linv, pa.linv32, p64, p32, s1);
                 });
         }
-        if (quant)   // 16-bit panel copy with per-tile power-of-two scales
+        if (part == 0) return;
+        if (quant)   // 16-bit panel copy
             ctx->timed_on(s1, kStatQuant, 0.0, (double)npanel * nbd * nbd * 6.0, [&] {
                 launch_quantize(map, k, k + 1, npanel, p32, qscale, q16, L.lowp, s1);
             });
@@ -870,7 +875,8 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     };
 
     potrf_step(0);
-    panel_step(0);
+    panel_step(0, 0);
+    panel_step(0, 1);
     MPGEO_HIP(hipEventRecord(ev_f[0], s1));
     for (int k = 0; k < p; ++k) {
         // U_next(k): column k+2's FP64 and FP32 tiles, after F(k) and U_bulk(k-1)
@@ -880,32 +886,33 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
             update_range(k, L.next_b[0][k], L.bulk[0][k].e, L.next_b[1][k], L.bulk[1][k].e, 0, 0,
                          L.next_f[0][k], L.next_f[1][k], 0.0, false, 0.0, sa);
         MPGEO_HIP(hipEventRecord(ev_next[k], sa));
-        // U_bulk(k): the 16-bit pass (column k+2), then FP64 and FP32 columns >= k+3
+        // U_bulk(k): FP64 and FP32 columns >= k+3, then the 16-bit pass (column k+2), whose
+        // long-running workgroups would otherwise hold the compute units the lookahead's
+        // small launches wait for
         MPGEO_HIP(hipStreamWaitEvent(sb, ev_f[k], 0));
-        if (k + 1 < p)
-            update_range(k, 0, 0, 0, 0, L.bulk[2][k].b, L.bulk[2][k].e, 0.0, 0.0,
-                         L.bulk[2][k].flops, false, L.bulk[2][k].panels, sb);
-        MPGEO_HIP(hipEventRecord(ev_low[k], sb));
         if (k + 1 < p)
             update_range(k, L.bulk[0][k].b, L.next_b[0][k], L.bulk[1][k].b, L.next_b[1][k], 0, 0,
                          L.bulk[0][k].flops - L.next_f[0][k], L.bulk[1][k].flops - L.next_f[1][k],
                          0.0, false, 0.0, sb);
+        if (k + 1 < p)
+            update_range(k, 0, 0, 0, 0, L.bulk[2][k].b, L.bulk[2][k].e, 0.0, 0.0,
+                         L.bulk[2][k].flops, false, L.bulk[2][k].panels, sb);
         MPGEO_HIP(hipEventRecord(ev_bulk[k], sb));
         if (k + 1 < p) {
             // Critical path: column k+1 takes panel k (its FP64 tiles, the diagonal tile among
-            // them, once U_next(k-1) is done), then POTRF(k+1); then the column's FP32 tiles and
-            // its 16-bit tiles (once step k-1's 16-bit pass is done), which only the panel TRSM
-            // needs; then the rest of F(k+1), which writes staging buffer (k+1) & 1 and so waits
-            // for U_bulk(k-1), its last reader.
+            // them, once U_next(k-1) is done), then POTRF(k+1) and the FP64 panel TRSM, which
+            // writes staging buffer (k+1) & 1 and so waits for U_bulk(k-1), its last reader (and
+            // so also for step k-1's 16-bit pass); then the column's FP32 and 16-bit tiles take
+            // panel k and the rest of F(k+1) follows.
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_next[k - 1], 0));
             update_range(k, L.col[0][k].b, L.col[0][k].e, 0, 0, 0, 0, L.col[0][k].flops, 0.0, 0.0,
                          true, 0.0, s1);
             potrf_step(k + 1);
-            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_low[k - 1], 0));
+            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
+            panel_step(k + 1, 0);
             update_range(k, 0, 0, L.col[1][k].b, L.col[1][k].e, L.col[2][k].b, L.col[2][k].e, 0.0,
                          L.col[1][k].flops, L.col[2][k].flops, true, 0.0, s1);
-            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
-            panel_step(k + 1);
+            panel_step(k + 1, 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
         MPGEO_HIP(hipGetLastError());
