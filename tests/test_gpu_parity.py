@@ -343,6 +343,40 @@ def test_three_tier_block_banded_is_exact(lib, ctx, lowp):
     assert got["logdet"] == ref["logdet"]
 
 
+def test_three_tier_bits_do_not_depend_on_pass_grouping(lib, ctx):
+    # n = 40,000, tile 256: up to about 140 far tiles per column, more than one wave of the
+    # 16-bit pass on part of the GPU.  A context that leaves compute units to the critical path
+    # (MPGEO_RESERVED_CUS) sizes the waves differently, so the layout groups the far tiles'
+    # panels into different passes (and runs all bulk updates on one stream); each element
+    # still takes the same FP32 accumulation sequence, so l must agree bit for bit.
+    m = 200
+    locs = jittered_grid(m, 41)
+    z = normals(m * m, 42)
+    theta = (1.0, 0.1, 0.5)
+    plan = dict(band32=8, lowp="fp16")
+    ds = lib.Dataset(ctx, locs, z)
+    try:
+        ref = ds.loglik(theta, 256, 2, **plan)
+    finally:
+        ds.close()
+    os.environ["MPGEO_RESERVED_CUS"] = "100"
+    try:
+        ctx2 = lib.Context(0)
+    finally:
+        del os.environ["MPGEO_RESERVED_CUS"]
+    try:
+        ds2 = lib.Dataset(ctx2, locs, z)
+        try:
+            got = ds2.loglik(theta, 256, 2, **plan)
+        finally:
+            ds2.close()
+    finally:
+        ctx2.close()
+    print(f"three-tier n={m * m}: l = {ref['loglik']!r} (reserved compute units: {got['loglik']!r})")
+    assert got["loglik"] == ref["loglik"]
+    assert got["logdet"] == ref["logdet"]
+
+
 def test_three_tier_plan_validation(lib, small_ds):
     for band32, lowp in [(2, None), (-1, "fp16")]:
         with pytest.raises(lib.MpgeoError) as e:
