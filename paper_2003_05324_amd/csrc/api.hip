@@ -879,21 +879,29 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     panel_step(0, 1);
     MPGEO_HIP(hipEventRecord(ev_f[0], s1));
     for (int k = 0; k < p; ++k) {
-        // U_next(k): column k+2's FP64 and FP32 tiles, after F(k) and U_bulk(k-1)
-        MPGEO_HIP(hipStreamWaitEvent(sa, ev_f[k], 0));
-        if (sa != sb && k >= 1) MPGEO_HIP(hipStreamWaitEvent(sa, ev_bulk[k - 1], 0));
-        if (k + 1 < p)
-            update_range(k, L.next_b[0][k], L.bulk[0][k].e, L.next_b[1][k], L.bulk[1][k].e, 0, 0,
-                         L.next_f[0][k], L.next_f[1][k], 0.0, false, 0.0, sa);
-        MPGEO_HIP(hipEventRecord(ev_next[k], sa));
+        // U_next(k): column k+2's FP64 and FP32 tiles, after F(k) and U_bulk(k-1) (with no
+        // stream of its own, it is part of the bulk launches below)
+        const bool own_next = sa != sb;
+        if (own_next) {
+            MPGEO_HIP(hipStreamWaitEvent(sa, ev_f[k], 0));
+            if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(sa, ev_bulk[k - 1], 0));
+            if (k + 1 < p)
+                update_range(k, L.next_b[0][k], L.bulk[0][k].e, L.next_b[1][k], L.bulk[1][k].e, 0, 0,
+                             L.next_f[0][k], L.next_f[1][k], 0.0, false, 0.0, sa);
+            MPGEO_HIP(hipEventRecord(ev_next[k], sa));
+        }
         // U_bulk(k): FP64 and FP32 columns >= k+3, then the 16-bit pass (column k+2), whose
         // long-running workgroups would otherwise hold the compute units the lookahead's
         // small launches wait for
         MPGEO_HIP(hipStreamWaitEvent(sb, ev_f[k], 0));
-        if (k + 1 < p)
-            update_range(k, L.bulk[0][k].b, L.next_b[0][k], L.bulk[1][k].b, L.next_b[1][k], 0, 0,
-                         L.bulk[0][k].flops - L.next_f[0][k], L.bulk[1][k].flops - L.next_f[1][k],
-                         0.0, false, 0.0, sb);
+        if (k + 1 < p) {
+            const int64_t e64 = own_next ? L.next_b[0][k] : L.bulk[0][k].e;
+            const int64_t e32 = own_next ? L.next_b[1][k] : L.bulk[1][k].e;
+            update_range(k, L.bulk[0][k].b, e64, L.bulk[1][k].b, e32, 0, 0,
+                         L.bulk[0][k].flops - (own_next ? L.next_f[0][k] : 0.0),
+                         L.bulk[1][k].flops - (own_next ? L.next_f[1][k] : 0.0), 0.0, false, 0.0, sb);
+        }
+        if (!own_next) MPGEO_HIP(hipEventRecord(ev_next[k], sb));
         if (k + 1 < p)
             update_range(k, 0, 0, 0, 0, L.bulk[2][k].b, L.bulk[2][k].e, 0.0, 0.0,
                          L.bulk[2][k].flops, false, L.bulk[2][k].panels, sb);
@@ -1615,7 +1623,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
 }
 
 // ---- batched evaluation of independent instances ------------------------------------------
-// Lanes are private contexts (own stream pair, events and workspace); instances are dealt to
+// Lanes are private contexts (own two streams, events and workspace); instances are dealt to
 // them largest first so that each lane's buffers reach their final size early, and every
 // evaluation is enqueued without a host synchronisation.  The tile size of an instance is the
 // plan's, or, with plan.tile = 0, the autotuner's choice for its half-octave of n.
@@ -1624,6 +1632,13 @@ static int batch_lanes(mpgeo_ctx *ctx, int want) {
     while ((int)ctx->lanes.size() < want) {
         mpgeo_ctx *c = nullptr;
         MPGEO_TRY(mpgeo_ctx_create(&c, ctx->device, nullptr));
+        // Lanes overlap whole evaluations with each other; a third stream per lane only adds
+        // small launches and queues (the hardware has few), so a lane's column k+2 updates
+        // stay on its bulk stream.
+        if (c->next) {
+            (void)hipStreamDestroy(c->next);
+            c->next = nullptr;
+        }
         ctx->lanes.push_back(c);
         mpgeo_dataset *d = new mpgeo_dataset();
         d->ctx = c;
