@@ -343,6 +343,31 @@ def test_three_tier_block_banded_is_exact(lib, ctx, lowp):
     assert got["logdet"] == ref["logdet"]
 
 
+@pytest.mark.parametrize("band64,band32,lowp", [(-1, -1, None), (2, -1, None), (2, 4, "fp16"),
+                                                 (2, 4, "bf16")])
+def test_row_scaling_by_powers_of_two_is_exact(lib, ctx, band64, band32, lowp):
+    # Scaling the rows and columns of Sigma by powers of two, D Sigma D with D = diag(2^e_r), and
+    # the data by D scales every entry of the factor exactly (binary floating point, no
+    # overflow or underflow here), and each tile row's 16-bit scale follows from its own
+    # diagonal, so l(D Sigma D, D y) + sum_r log d_r must equal l(Sigma, y) up to the rounding
+    # of the logarithms.  A scale shared by all rows would flush the rows scaled by 2^-20 to
+    # zero in FP16.
+    n, tile = 1024, 64
+    locs = jittered_grid(32, 51)
+    sigma = oracle.matern_matrix(locs[oracle.morton_order(locs)], (1.0, 0.1, 0.5))
+    y = normals(n, 52)
+    e = ((np.arange(n) // tile) % 5 - 2) * 10.0          # 2^-20 .. 2^20 by tile row
+    d = np.exp2(e)
+    ref = ctx.factor_dense(sigma, y, tile, band64, band32=band32, lowp=lowp)
+    got = ctx.factor_dense(sigma * d[:, None] * d[None, :], y * d, tile, band64, band32=band32, lowp=lowp)
+    shift = float(np.sum(e) * np.log(2.0))
+    err = abs(got["loglik"] + shift - ref["loglik"]) / max(abs(ref["loglik"]), n)
+    print(f"band64={band64} band32={band32} lowp={lowp}: l = {ref['loglik']:.10f}, scaled + shift "
+          f"= {got['loglik'] + shift:.10f}, rel {err:.2e}")
+    assert err <= 1e-12
+    assert got["quad"] == ref["quad"]
+
+
 def test_three_tier_bits_do_not_depend_on_pass_grouping(lib, ctx):
     # n = 40,000, tile 256: up to about 140 far tiles per column, more than one wave of the
     # 16-bit pass on part of the GPU.  A context that leaves compute units to the critical path

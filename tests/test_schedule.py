@@ -1,0 +1,35 @@
+"""Host logic: the factorization schedule of the tile layout (no GPU work).
+
+The C++ check in schedule_check.hip includes the library's layout code, builds the schedules of
+several plans and verifies them (panel order and completeness of the 16-bit tier's left-looking
+passes, wave filling, the split of each step's FP64/FP32 update lists); it is compiled with
+hipcc and linked against the in-tree library.
+"""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.join(os.path.dirname(HERE), "paper_2003_05324_amd")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def test_schedule_is_consistent():
+    lib = os.path.join(PKG, "libmpgeo.so")
+    if not os.path.exists(lib):
+        pytest.skip("libmpgeo.so is not built")
+    if not shutil.which(HIPCC) and not os.path.exists(HIPCC):
+        pytest.skip("hipcc is not available")
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = os.path.join(tmp, "schedule_check")
+        cmd = [HIPCC, "-O1", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",
+               "-Xclang", "-packed-fp32-ops", os.path.join(HERE, "schedule_check.hip"), "-o", exe,
+               "-L", PKG, "-lmpgeo", f"-Wl,-rpath,{PKG}"]
+        build = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        assert build.returncode == 0, build.stderr[-2000:]
+        run = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        print(run.stdout)
+        assert run.returncode == 0, run.stdout[-2000:]
