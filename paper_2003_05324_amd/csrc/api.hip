@@ -722,9 +722,9 @@ int run_covgen(mpgeo_dataset *ds, const mpgeo_theta &th) {
 //
 // Three streams: the bulk stream runs most of each step's trailing update (tile columns
 // j >= k+3, and the 16-bit pass); a second stream runs column k+2's FP64 and FP32 updates,
-// which the next lookahead step needs first; the side stream runs the critical path one step
-// ahead: the update of column k+1, then POTRF, panel TRSMs, quantiser and forward-solve step
-// of k+1 (lookahead of depth 1).  Staging panels alternate between two buffers so step k+1's
+// which the next lookahead step needs first, and column k+1's FP32 and 16-bit updates; the
+// side stream runs the critical path one step ahead: the update of column k+1's FP64 tiles,
+// then POTRF, panel TRSMs, quantiser and forward-solve step of k+1 (lookahead of depth 1).  Staging panels alternate between two buffers so step k+1's
 // panel can be written while step k's updates still read step k's.  Dependencies:
 //   F(k)        = POTRF + TRSM + panel solve of step k            (side stream)
 //   U_col(k)    = update of column k+1 with panel k               (side; after U_next(k-1))
@@ -748,11 +748,12 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     double *logdet_part = ds->parts.as<double>();
     double *quad_part = logdet_part + p;
     unsigned long long *info = ds->info.as<unsigned long long>();
-    if (!ctx->ensure_sync_events(3 * (size_t)p + 1)) return MPGEO_E_DEVICE;
+    if (!ctx->ensure_sync_events(4 * (size_t)p + 1)) return MPGEO_E_DEVICE;
     hipEvent_t ev_start = ctx->sync_events[0];
     hipEvent_t *ev_f = ctx->sync_events.data() + 1;       // F(k) done
     hipEvent_t *ev_bulk = ev_f + p;                        // U_bulk(k) done
     hipEvent_t *ev_next = ev_bulk + p;                     // U_next(k) done
+    hipEvent_t *ev_col = ev_next + p;                      // column k+1's FP32 / 16-bit tiles done
     MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s0));
     launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
     if (L.lowp) launch_row_scale(map, ds->qscale.as<float>(), s0);   // from Sigma's diagonal
@@ -889,6 +890,13 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
                 update_range(k, L.next_b[0][k], L.bulk[0][k].e, L.next_b[1][k], L.bulk[1][k].e, 0, 0,
                              L.next_f[0][k], L.next_f[1][k], 0.0, false, 0.0, sa);
             MPGEO_HIP(hipEventRecord(ev_next[k], sa));
+            // column k+1's FP32 and 16-bit tiles take panel k here, beside POTRF(k+1) on the
+            // side stream (they were brought up to panel k-1 by U_next(k-1) and step k-1's
+            // 16-bit pass, both done once U_bulk(k-1) is)
+            if (k + 1 < p)
+                update_range(k, 0, 0, L.col[1][k].b, L.col[1][k].e, L.col[2][k].b, L.col[2][k].e, 0.0,
+                             L.col[1][k].flops, L.col[2][k].flops, true, 0.0, sa);
+            MPGEO_HIP(hipEventRecord(ev_col[k], sa));
         }
         // U_bulk(k): FP64 and FP32 columns >= k+3, then the 16-bit pass (column k+2), whose
         // long-running workgroups would otherwise hold the compute units the lookahead's
@@ -910,16 +918,19 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
             // Critical path: column k+1 takes panel k (its FP64 tiles, the diagonal tile among
             // them, once U_next(k-1) is done), then POTRF(k+1) and the FP64 panel TRSM, which
             // writes staging buffer (k+1) & 1 and so waits for U_bulk(k-1), its last reader (and
-            // so also for step k-1's 16-bit pass); then the column's FP32 and 16-bit tiles take
-            // panel k and the rest of F(k+1) follows.
+            // so also for step k-1's 16-bit pass); then, once the column's FP32 and 16-bit tiles
+            // have taken panel k (on the second stream, or here without one), the rest of F(k+1).
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_next[k - 1], 0));
             update_range(k, L.col[0][k].b, L.col[0][k].e, 0, 0, 0, 0, L.col[0][k].flops, 0.0, 0.0,
                          true, 0.0, s1);
             potrf_step(k + 1);
             if (k >= 1) MPGEO_HIP(hipStreamWaitEvent(s1, ev_bulk[k - 1], 0));
             panel_step(k + 1, 0);
-            update_range(k, 0, 0, L.col[1][k].b, L.col[1][k].e, L.col[2][k].b, L.col[2][k].e, 0.0,
-                         L.col[1][k].flops, L.col[2][k].flops, true, 0.0, s1);
+            if (own_next)
+                MPGEO_HIP(hipStreamWaitEvent(s1, ev_col[k], 0));
+            else
+                update_range(k, 0, 0, L.col[1][k].b, L.col[1][k].e, L.col[2][k].b, L.col[2][k].e, 0.0,
+                             L.col[1][k].flops, L.col[2][k].flops, true, 0.0, s1);
             panel_step(k + 1, 1);
             MPGEO_HIP(hipEventRecord(ev_f[k + 1], s1));
         }
@@ -927,7 +938,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     }
     MPGEO_HIP(hipStreamWaitEvent(s0, ev_f[p - 1], 0));
     if (sb != s0) MPGEO_HIP(hipStreamWaitEvent(s0, ev_bulk[p - 1], 0));
-    if (sa != s0) MPGEO_HIP(hipStreamWaitEvent(s0, ev_next[p - 1], 0));
+    if (sa != s0) MPGEO_HIP(hipStreamWaitEvent(s0, sa != sb ? ev_col[p - 1] : ev_next[p - 1], 0));
     if (ev_factored) MPGEO_HIP(hipEventRecord(ev_factored, s0));
     ctx->timed(kStatFinal, 2.0 * p, 16.0 * p, [&] {
         launch_finalize(logdet_part, quad_part, p, L.n, ds->profile, ds->result.as<double>(), s0);
