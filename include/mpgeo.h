@@ -35,7 +35,9 @@
  *  - Layout: locations are n x 2 row-major float64 (x, y), or (longitude, latitude) in
  *    degrees with MPGEO_DIST_GCD; vectors are float64.
  *  - Ordering: all calls are ordered on the context's HIP stream and are synchronous at
- *    return (results filled in).  A context is used by one host thread at a time.
+ *    return (results filled in); inside a factorization the library fans work out to
+ *    streams of its own, which start after and join back into the context's stream.  A
+ *    context is used by one host thread at a time.
  *  - Errors: on a non-OK return the outputs are undefined except mpgeo_result.info.
  *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 < -1, band0 < -1, lowp outside 0..2,
  *    band32 >= 0 without a lowp format or lowp without band32 >= 0, a non-finite or

@@ -399,7 +399,7 @@ struct mpgeo_ctx {
     hipStream_t next = nullptr;
     int reserved_cus = 0;
     int cus = 0;                           // compute units of the device
-    std::vector<hipEvent_t> sync_events;   // dependency events between the two streams
+    std::vector<hipEvent_t> sync_events;   // dependency events between the streams
 
     // at least `count` timing-free events for stream dependencies
     bool ensure_sync_events(size_t count) {
