@@ -14,12 +14,12 @@
 // tri_index(i, k), row-major, K contiguous).
 //
 // Update.  A far tile takes its panels in one left-looking pass:
-//   A_ij <- s_i s_j (A_ij / (s_i s_j) - sum_k Q_ik Q_jk^T),
-// with the FP32 accumulator of each element starting at A_ij / (s_i s_j) (exact: a power of
-// two) and v_mfma_f32_16x16x32_{f16,bf16} adding -Q_ik Q_jk^T to it 32 products at a time,
-// panels in ascending k; the final product by s_i s_j is exact again.  Each element therefore
+//   A_ij <- -s_i s_j (-A_ij / (s_i s_j) + sum_k Q_ik Q_jk^T),
+// with the FP32 accumulator of each element starting at -A_ij / (s_i s_j) (exact: a power of
+// two) and v_mfma_f32_16x16x32_{f16,bf16} adding Q_ik Q_jk^T to it 32 products at a time,
+// panels in ascending k; the final product by -s_i s_j is exact again.  Each element therefore
 // sees one fixed sequence of FP32 roundings, set by the panels it takes and not by how they
-// are split between launches.
+// are split between launches or which of the two kernels below runs them.
 #include "common.h"
 
 namespace mpgeo {
@@ -115,14 +115,13 @@ struct LShape {
 };
 
 // One BM x BN block of target tile (i, j):
-//   C <- s_i s_j (C / (s_i s_j) - sum over panels k of sum_t Q_ik[row][t] Q_jk[col][t]).
+//   C <- -s_i s_j (-C / (s_i s_j) + sum over panels k of sum_t Q_ik[row][t] Q_jk[col][t]).
 // The block's accumulators are held in registers for the whole K loop (their load latency
-// hides behind the first chunks); the row operand is negated as it is staged into LDS.
+// hides behind the first chunks); operands are staged global -> registers -> LDS.
 template <typename T, typename S>
 __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     using L = Lowp<T>;
     using vec8 = typename L::vec8;
-    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     constexpr int BM = S::BM, BN = S::BN, KC = S::KC, NT = S::kThreads;
     constexpr int NBR = BM / S::WM / 16;
     constexpr int NBC = BN / S::WN / 16;
@@ -155,7 +154,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
     const T *R0 = qbase + tri_index(tij.i, kfirst) * te + (int64_t)row0 * nbp;
     const T *Q0 = qbase + tri_index(tij.j, kfirst) * te + (int64_t)col0 * nbp;
     const float f = g.rscale[tij.i] * g.rscale[tij.j];   // a power of two (at least 2^-120)
-    const float inv_f = 1.0f / f;
+    const float ninv_f = -1.0f / f;
     float *C = g.map.pool32 + g.map.off[tri_index(tij.i, tij.j)];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
         for (int b = 0; b < NBR; ++b)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp] * inv_f;
+                acc[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp] * ninv_f;
 
     // Operand chunks stream global -> registers -> LDS.  Chunk x waits in register set
     // x % DEPTH; DEPTH chunks are in flight while the chunk in LDS feeds the matrix cores
@@ -210,9 +209,7 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             const int idx = v * NT + tid;
             if (NVR % NT == 0 || idx < NVR) {
                 const int row = idx / VPR_ROW, col = idx % VPR_ROW;
-                // -Q_ik: flip the sign bit of each 16-bit value (exact)
-                const u32x4 neg = __builtin_bit_cast(u32x4, sr[v]) ^ 0x80008000u;
-                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + col * 8]) = __builtin_bit_cast(vec8, neg);
+                *reinterpret_cast<vec8 *>(&ldsr[buf][row * LD + col * 8]) = sr[v];
             }
         }
     };
@@ -262,8 +259,145 @@ __global__ __launch_bounds__(S::kThreads) void lowp_update_kernel(LowpArgs g) {
             for (int q = 0; q < 4; ++q) {
                 const int row = row0 + wrow + b * 16 + lr;
                 const int col = col0 + wcol + a * 16 + 4 * lg + q;
-                C[row + (int64_t)col * nbp] = acc[a][b][q] * f;
+                C[row + (int64_t)col * nbp] = -(acc[a][b][q] * f);
             }
+}
+
+// The same block update with the operand chunks copied global -> LDS directly
+// (global_load_lds_dwordx4: each lane's 16 bytes land at a wave-uniform LDS offset + 16 * lane),
+// two chunks of K = 64 in LDS, no registers staging the operands.  One wave instruction fills
+// 8 rows of 64 elements; row r keeps its 16-byte vector v at slot v ^ (r & 7), which keeps the
+// fragment reads free of bank conflicts without padding.  Chunk c + 1 is in flight while chunk c
+// feeds the matrix cores.
+extern __shared__ __attribute__((aligned(16))) char lowp_dyn_lds[];
+
+// 16 bytes from global src to LDS byte offset lds_off + 16 * lane (lds_off wave-uniform).  The
+// builtin exists only for the device; the host pass sees an empty body.
+__device__ inline void lds_copy16(const void *src, int lds_off) {
+#if __HIP_DEVICE_COMPILE__
+    __builtin_amdgcn_global_load_lds(src, lowp_dyn_lds + lds_off, 16, 0, 0);
+#endif
+}
+
+template <int BM_, int BN_, int WM_, int WN_>
+struct DShape {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KC = 64;
+    static constexpr int kThreads = 64 * WM * WN;
+    static constexpr size_t kLds = (size_t)2 * (BM + BN) * KC * 2;   // two chunks, bytes
+};
+
+template <typename T, typename S>
+__global__ __launch_bounds__(S::kThreads) void lowp_direct_kernel(LowpArgs g) {
+    using L = Lowp<T>;
+    using vec8 = typename L::vec8;
+    constexpr int BM = S::BM, BN = S::BN, KC = S::KC, NW = S::WM * S::WN;
+    constexpr int NBR = BM / S::WM / 16;
+    constexpr int NBC = BN / S::WN / 16;
+    constexpr int ROWB = KC * 2;                       // bytes per LDS row
+    constexpr int RB = BM * ROWB, QB = BN * ROWB;      // bytes per chunk and operand
+    constexpr int GROUPS = (BM + BN) / 8;              // wave instructions per chunk
+    static_assert(GROUPS % NW == 0, "row groups must split evenly over the waves");
+    constexpr int GPW = GROUPS / NW;
+
+    const int nbp = g.map.nbp;
+    const int rows_per = nbp / BM, cols_per = nbp / BN;
+    const int per_tile = rows_per * cols_per;
+    const int xcd = blockIdx.x % kXcds;
+    const int local = blockIdx.x / kXcds;
+    const int macro = local % per_tile;
+    const int tile = (local / per_tile) * kXcds + xcd;
+    if (tile >= g.ntiles) return;
+    const int row0 = (macro % rows_per) * BM;
+    const int col0 = (macro / rows_per) * BN;
+    const TileIJ tij = g.list[tile];
+    const int kfirst = max(g.kstart ? g.kstart[tile] : g.kbeg, tij.i - g.zband);
+    if (kfirst >= g.kend) return;
+    const int cpp = nbp / KC;
+    const int nchunks = (g.kend - kfirst) * cpp;
+    const int64_t te = (int64_t)nbp * nbp;
+    const T *qbase = static_cast<const T *>(g.q);
+    const T *R0 = qbase + tri_index(tij.i, kfirst) * te + (int64_t)row0 * nbp;
+    const T *Q0 = qbase + tri_index(tij.j, kfirst) * te + (int64_t)col0 * nbp;
+    const float f = g.rscale[tij.i] * g.rscale[tij.j];
+    const float ninv_f = -1.0f / f;
+    float *C = g.map.pool32 + g.map.off[tri_index(tij.i, tij.j)];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wrow = (wave % S::WM) * (BM / S::WM);
+    const int wcol = (wave / S::WM) * (BN / S::WN);
+    const int lr = lane & 15, lg = lane >> 4;
+
+    f32x4 acc[NBC][NBR];
+#pragma unroll
+    for (int a = 0; a < NBC; ++a)
+#pragma unroll
+        for (int b = 0; b < NBR; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc[a][b][q] = C[(row0 + wrow + b * 16 + lr) + (int64_t)(col0 + wcol + a * 16 + 4 * lg + q) * nbp] * ninv_f;
+
+    // this lane's source within a group of 8 rows: row lane / 8, vector (lane & 7) ^ (lane / 8)
+    const int lrow = lane >> 3, lvec = (lane & 7) ^ (lane >> 3);
+    auto issue = [&](int c, int buf) {
+        const int64_t off = (int64_t)(c / cpp) * te + (c % cpp) * KC + lvec * 8;
+#pragma unroll
+        for (int m = 0; m < GPW; ++m) {
+            const int grp = wave + NW * m;   // wave-uniform
+            const bool isr = grp < BM / 8;
+            const int r = (isr ? grp : grp - BM / 8) * 8 + lrow;
+            const T *src = (isr ? R0 : Q0) + off + (int64_t)r * nbp;
+            const int dst = buf * (RB + QB) + (isr ? 0 : RB) + (isr ? grp : grp - BM / 8) * 8 * ROWB;
+            lds_copy16(src, dst);
+        }
+    };
+    auto compute = [&](int buf) {
+        const char *chunk = lowp_dyn_lds + buf * (RB + QB);
+#pragma unroll
+        for (int s = 0; s < KC / 32; ++s) {
+            const int v = 4 * s + lg;               // this lane's 16-byte vector of the row
+            const int sw = (v ^ (lr & 7)) * 16;     // its slot (rows of a fragment share r & 7 = lr & 7)
+            vec8 qa[NBC], rb[NBR];
+#pragma unroll
+            for (int a = 0; a < NBC; ++a)
+                qa[a] = *reinterpret_cast<const vec8 *>(chunk + RB + (wcol + a * 16 + lr) * ROWB + sw);
+#pragma unroll
+            for (int b = 0; b < NBR; ++b)
+                rb[b] = *reinterpret_cast<const vec8 *>(chunk + (wrow + b * 16 + lr) * ROWB + sw);
+#pragma unroll
+            for (int a = 0; a < NBC; ++a)
+#pragma unroll
+                for (int b = 0; b < NBR; ++b) acc[a][b] = L::mac(qa[a], rb[b], acc[a][b]);
+        }
+    };
+
+    issue(0, 0);
+    for (int c = 0; c < nchunks; ++c) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies of chunk c landed
+        __syncthreads();                       // everyone's, and everyone is done with chunk c-1
+        if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+        compute(c & 1);
+    }
+#pragma unroll
+    for (int a = 0; a < NBC; ++a)
+#pragma unroll
+        for (int b = 0; b < NBR; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = row0 + wrow + b * 16 + lr;
+                const int col = col0 + wcol + a * 16 + 4 * lg + q;
+                C[row + (int64_t)col * nbp] = -(acc[a][b][q] * f);
+            }
+}
+
+template <typename T, typename S>
+void launch_direct_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
+    LowpArgs ga = g;
+    ga.ntiles = ntiles;
+    const int nbp = g.map.nbp;
+    const int64_t slots = (ntiles + kXcds - 1) / kXcds * kXcds;
+    const int64_t blocks = slots * (nbp / S::BM) * (nbp / S::BN);
+    hipLaunchKernelGGL((lowp_direct_kernel<T, S>), dim3((unsigned)blocks), dim3(S::kThreads), S::kLds,
+                       stream, ga);
 }
 
 template <typename T, typename S>
@@ -279,7 +413,7 @@ void launch_lowp_shape(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
 
 // many panels (the left-looking pass): 256 x 256 blocks when the tile allows, else 128 x 128
 template <typename T, int BM> struct ManyPanel;
-template <typename T> struct ManyPanel<T, 256> { using S = LShape<256, 256, 4, 4, 64, 1, 16>; };
+template <typename T> struct ManyPanel<T, 256> { using S = DShape<256, 256, 4, 4>; };
 template <typename T> struct ManyPanel<T, 128> { using S = LShape<128, 128, 2, 2, 32, 1, 16>; };
 
 template <typename T>
@@ -288,9 +422,9 @@ void launch_lowp(const LowpArgs &g, int64_t ntiles, hipStream_t stream) {
     const bool many = g.kstart != nullptr || g.kend - g.kbeg > 1;
     if (many && nbp % 256 == 0) {
         // many panels (the left-looking pass, long K): 256 x 256 blocks of 16 waves with 64 x 64
-        // each, K chunks of 64, all of the LDS (measured alone on n ~ 1e5 columns: 850-910
-        // TFLOP/s; 256 x 128 blocks of 8 waves: 705-770)
-        launch_lowp_shape<T, typename ManyPanel<T, 256>::S>(g, ntiles, stream);
+        // each, K chunks of 64 copied straight into LDS (measured alone on n ~ 1e5 columns:
+        // 820-980 TFLOP/s; staged through registers: 770-905; 256 x 128 blocks: 705-770)
+        launch_direct_shape<T, typename ManyPanel<T, 256>::S>(g, ntiles, stream);
     } else if (many && nbp % 128 == 0) {
         launch_lowp_shape<T, typename ManyPanel<T, 128>::S>(g, ntiles, stream);
     } else if (nbp % 128 == 0) {
@@ -350,8 +484,12 @@ namespace {
 template <typename T, int BM> int wave_tiles_of(int nbp, int cus) {
     using S = typename ManyPanel<T, BM>::S;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lowp_update_kernel<T, S>, S::kThreads, 0) !=
-            hipSuccess) {
+    hipError_t e;
+    if constexpr (BM == 256)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lowp_direct_kernel<T, S>, S::kThreads, S::kLds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lowp_update_kernel<T, S>, S::kThreads, 0);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
