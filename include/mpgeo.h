@@ -20,8 +20,8 @@
  * two s_i = 2^max(e_i - 14, -60), e_i = ceil(log2 sqrt(max Sigma_rr)) over its rows (every
  * |L_rk| <= sqrt(Sigma_rr)); each finished panel tile is rounded to nearest-even once into a
  * 16-bit copy Q_ik = L_ik / s_i of the factor, and a far tile is updated as
- * A_ij <- s_i s_j (A_ij / (s_i s_j) - sum_k Q_ik Q_jk^T) on the matrix cores, accumulating in
- * FP32 from the scaled A_ij, panels in ascending k (a far tile takes its earlier panels in
+ * A_ij <- -s_i s_j (-A_ij / (s_i s_j) + sum_k Q_ik Q_jk^T) on the matrix cores, accumulating in
+ * FP32 from -A_ij / (s_i s_j), panels in ascending k (a far tile takes its earlier panels in
  * one pass about two steps before it is solved; the result does not depend on how the
  * panels are grouped into passes).
  *

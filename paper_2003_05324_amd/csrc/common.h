@@ -126,7 +126,7 @@ void launch_row_scale(const TileMap &map, float *rscale, hipStream_t stream);
 // into the 16-bit factor copy q at slot tri_index(i, k).
 void launch_quantize(const TileMap &map, int k, int first, int count, const float *p32,
                      const float *rscale, void *q, int lowp, hipStream_t stream);
-// Third tier: A_ij <- s_i s_j (A_ij / (s_i s_j) - sum_k Q_ik Q_jk^T) over list[0, count)
+// Third tier: A_ij <- -s_i s_j (-A_ij / (s_i s_j) + sum_k Q_ik Q_jk^T) over list[0, count)
 // (FP32-stored tiles), for panels k in [max(k0, i - zband), kend), ascending, from the 16-bit
 // factor copy; k0 is kstart[t] for entry t when kstart is given, else kbeg.
 void launch_update_lowp(const TileMap &map, const TileIJ *list, int64_t count, int kbeg, int kend,
