@@ -124,7 +124,7 @@ def parse():
     ap.add_argument("--serve", type=int, default=0,
                     help="instead of the headline: this many requests (Poisson arrivals) for 16 "
                          "resident datasets (n log-uniform in [2000, 60000]) through the serving "
-                         "loop, mixed plan and FP64 plan; one JSON line")
+                         "loop, three-tier, two-tier and FP64 plans; one JSON line")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="arrivals per second")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline: the n = 40,000 band sweep (6 fields x bands "
@@ -334,7 +334,8 @@ def serve_bench(args):
     """Serving loop: Poisson arrivals of likelihood requests (theta drawn around (1, 0.1, 0.5) as
     an optimiser's trajectory would visit it) for 16 datasets, every fourth a kriging request
     (predictions and variances at 500 new sites), HBM budget 96 GB, 4 lanes; the same trace with
-    the two-tier plan (FP64 band 2, tile 512) and with the all-FP64 plan."""
+    the three-tier plan (FP64 band 2, FP32 next 8 tiles, FP16 operands beyond; tile 512), the
+    two-tier plan (FP64 band 2, FP32 beyond) and the all-FP64 plan."""
     import numpy as np
 
     import paper_2003_05324_amd as mp
@@ -355,9 +356,10 @@ def serve_bench(args):
     ctx = mp.Context(0)
     out = {"serve": f"matern-serve{args.serve}-16sets-n2000-60000", "requests": args.serve,
            "rate_per_s": args.serve_rate, "dataset_sizes": sizes, "sum_n3_over_3": flops}
-    for name, band in (("two_tier_b2", 2), ("fp64", -1)):
+    for name, band, band32, lowp in (("three_tier_b2_c8", 2, 8, "fp16"), ("two_tier_b2", 2, -1, None),
+                                     ("fp64", -1, -1, None)):
         srv = mp.Server(ctx, 96 * 2 ** 30, 4)
-        ids = [srv.add_dataset(locs, z, 512, band) for locs, z in data]
+        ids = [srv.add_dataset(locs, z, 512, band, band32, lowp) for locs, z in data]
         for q in range(args.serve):
             if kriging[q]:
                 srv.submit_krige(ids[picks[q]], thetas[q], new_sites[picks[q]], float(arrivals[q]),
@@ -381,6 +383,7 @@ def serve_bench(args):
         print(f"[serve] {name}: {out[name]}", file=sys.stderr, flush=True)
     ctx.close()
     out["p50_speedup_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["two_tier_b2"]["p50_latency_s"]
+    out["p50_speedup_three_tier_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["three_tier_b2_c8"]["p50_latency_s"]
     print(json.dumps(out), flush=True)
 
 
