@@ -87,3 +87,33 @@ def test_kriging_requests_in_the_mix(lib):
         ds.close()
     srv.close()
     ctx.close()
+
+
+def test_three_tier_served_results_equal_isolated_evaluations(lib):
+    # the serving lanes run the three-tier plan (FP64 band 1, FP32 for 2 more tiles, FP16
+    # operands beyond) with two streams each; every result equals the dataset's own evaluation
+    # bit for bit and the oracle within the third tier's bar
+    ctx = lib.Context(0)
+    sizes = [1500, 3100]
+    data = [(jittered_grid(int(np.ceil(np.sqrt(n))), 90 + q)[:n].copy(), normals(n, 95 + q))
+            for q, n in enumerate(sizes)]
+    srv = lib.Server(ctx, hbm_budget_bytes=1 << 34, lanes=2)
+    ids = [srv.add_dataset(locs, z, 128, 1, 2, "fp16") for locs, z in data]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for q in range(6):
+        d = q % len(sizes)
+        theta = (float(np.exp(rng.normal(0, 0.2))), float(0.1 * np.exp(rng.normal(0, 0.2))), 0.5)
+        reqs.append((srv.submit(ids[d], theta, 0.01 * q), d, theta))
+    st, out = srv.run()
+    assert st == 0
+    for t, d, theta in reqs:
+        r = out[t]
+        ds = lib.Dataset(ctx, *data[d])
+        alone = ds.loglik(theta, 128, 1, band32=2, lowp="fp16")
+        ds.close()
+        assert r["loglik"] == alone["loglik"] and r["logdet"] == alone["logdet"], (t, d)
+        want = oracle.loglik(data[d][0], data[d][1], theta)["loglik"]
+        assert abs(r["loglik"] - want) / max(abs(want), sizes[d]) <= 20 * 2.0 ** -11
+    srv.close()
+    ctx.close()
