@@ -64,6 +64,18 @@ def test_autotuned_tiles_and_band_plan(ctx, problems):
         assert abs(r["loglik"] - want) / max(abs(want), len(z)) <= 1e-5
 
 
+def test_three_tier_plan_through_the_lanes(ctx, problems):
+    # the third tier through the batched lanes (tile 64, FP64 band 1, FP32 for 1 more tile,
+    # FP16 operands beyond): identical to single calls, within the third tier's bar of the oracle
+    st, res, tiles = ctx.batch_loglik(problems, tile=64, band64=1, band32=1, lowp="fp16")
+    assert st == 0 and tiles == [64] * len(problems)
+    for (locs, z, theta), r in zip(problems, res):
+        one = ctx.loglik(locs, z, theta, 64, 1, band32=1, lowp="fp16")
+        assert r["loglik"] == one["loglik"] and r["logdet"] == one["logdet"]
+        want = oracle.loglik(locs, z, theta)["loglik"]
+        assert abs(r["loglik"] - want) / max(abs(want), len(z)) <= 20 * 2.0 ** -11
+
+
 def test_failure_is_reported_per_instance(lib, ctx):
     # with tiles beyond band0 = 3 dropped, the n = 1,600 workload is not positive definite
     # (the oracle's truncated matrix fails too); one-tile instances are untouched by band0
