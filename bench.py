@@ -389,6 +389,10 @@ def serve_bench(args):
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              f"sharding of the path is a design note, not a build", file=sys.stderr)
+        sys.exit(2)
     if args.serve:
         serve_bench(args)
         return
@@ -398,10 +402,6 @@ def main():
     if args.batch:
         batch_bench(args)
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              f"sharding of the path is a design note, not a build", file=sys.stderr)
-        sys.exit(2)
     import torch
 
     import numpy as np
