@@ -41,9 +41,13 @@
  *  - Errors: on a non-OK return the outputs are undefined except mpgeo_result.info.
  *    MPGEO_E_ARG: n < 1, tile < 1 or > 512, band64 < -1, band32 < -1, band0 < -1, lowp outside 0..2,
  *    band32 >= 0 without a lowp format or lowp without band32 >= 0, a non-finite or
- *    non-positive theta component, a null pointer that is not nullable.
+ *    non-positive theta component, a null pointer that is not nullable, a non-finite
+ *    location, datum, kriging site or normal draw (host inputs are checked on the host,
+ *    device inputs by a reduction on the device before any other work; Section IV-A's data
+ *    are real-valued measurements at points of the plane or the sphere).
  *    MPGEO_E_NOT_SPD: a non-positive (or NaN) pivot; info = its 0-based global column in
- *    the (Morton-ordered) matrix.  MPGEO_E_NOMEM: device allocation failed.
+ *    the (Morton-ordered) matrix.  MPGEO_E_NOMEM: device allocation failed, or the tiles a
+ *    plan needs (mpgeo_footprint_bytes) exceed the context's HBM budget.
  *    MPGEO_E_DEVICE: a HIP runtime error.  MPGEO_E_UNSUPPORTED: a feature not built.
  */
 #ifndef MPGEO_H
@@ -97,6 +101,19 @@ typedef enum {
  * MPGEO_E_UNSUPPORTED.  Results agree with mpgeo_loglik to rounding (the products are summed
  * in another order), not bit for bit. */
 #define MPGEO_BATCH_QUEUE 32u
+/* Escalation on loss of positive definiteness.  With too much of the matrix in reduced
+ * precision the factorization can meet a non-positive pivot even though Sigma itself is
+ * positive definite (Section VIII-D-1 reports this for single precision near the diagonal,
+ * which stops the MLE).  With this flag an evaluation that fails so is repeated with every
+ * reduced band widened, b -> 2b + 1 for band64, band32 and band0, a band that reaches the
+ * last tile row becoming "all" (-1: every tile FP64 and nothing dropped, and then no third
+ * tier); a map drawn from distances goes straight to all-FP64.  The repetition stops at the
+ * first success or after the all-FP64 plan.  mpgeo_result.escalations counts the repetitions
+ * and .band64 / .band32 / .band0 give the bands of the reported result.  Honoured by
+ * mpgeo_loglik, mpgeo_dataset_loglik, mpgeo_dataset_mle (every evaluation of the search),
+ * mpgeo_dataset_simulate and mpgeo_factor_dense; mpgeo_batch_loglik and the serving loop
+ * return MPGEO_E_UNSUPPORTED with it. */
+#define MPGEO_ESCALATE    64u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
  * (smoothness); all must be finite and > 0. */
@@ -151,6 +168,10 @@ typedef struct {
     double t_factor;
     double t_solve;
     double t_total;
+    int32_t band64;        /* bands of the plan the result was computed with: the plan's own, */
+    int32_t band32;        /* or the widened ones after MPGEO_ESCALATE */
+    int32_t band0;
+    int32_t escalations;   /* repetitions with wider bands (MPGEO_ESCALATE), else 0 */
 } mpgeo_result;
 
 /* Per-kernel-class launch statistics accumulated while MPGEO_TIMING is set. */
@@ -166,8 +187,12 @@ typedef struct mpgeo_ctx mpgeo_ctx;
 typedef struct mpgeo_dataset mpgeo_dataset;
 
 /* Create a context on HIP device `device`, ordering all work on `hip_stream`
- * (a hipStream_t; NULL: the library creates its own stream).  *out receives the handle. */
-int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream);
+ * (a hipStream_t; NULL: the library creates its own stream).  hbm_budget_bytes > 0 caps the
+ * tile memory of any one evaluation in this context: a call whose plan needs more lower-triangle
+ * tile bytes than that (mpgeo_footprint_bytes, the 16-bit factor copy included) returns
+ * MPGEO_E_NOMEM before allocating; batched calls size their groups within it.  0: no cap
+ * beyond the device's memory.  *out receives the handle. */
+int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream, size_t hbm_budget_bytes);
 
 /* Free a context and its cached device memory.  NULL is accepted. */
 int mpgeo_ctx_destroy(mpgeo_ctx *ctx);
@@ -281,7 +306,7 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
                        mpgeo_result *out, int32_t *tiles);
 
 /* Serving loop for many likelihood requests (the inner loop of many maximum-likelihood fits,
- * Section VIII-E): datasets are registered once (host copies kept); requests (dataset, theta)
+ * Section VIII-D-2): datasets are registered once (host copies kept); requests (dataset, theta)
  * are submitted with arrival times in seconds; mpgeo_server_run replays them in real time from
  * its start: a request is ready at its arrival, and a dispatcher gives the oldest ready
  * request whose dataset is idle to a free lane (lanes as in mpgeo_batch_loglik) without waiting

@@ -1,7 +1,7 @@
 """Maximum-likelihood fit of theta by Nelder-Mead — oracle (test infrastructure only).
 
 The paper maximises eq. (2) with a derivative-free optimiser at a 1e-3
-tolerance and reports iteration counts (Sections IV-C and VIII-E); it does not
+tolerance and reports iteration counts (Sections IV-C and VIII-D-2); it does not
 name the algorithm.  The reading used here is a plain Nelder-Mead simplex
 search (reflection 1, expansion 2, contraction 1/2, shrink 1/2) on
 u = log(theta), with theta clamped to box bounds, started at

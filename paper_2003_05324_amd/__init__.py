@@ -26,6 +26,7 @@ MPGEO_TIMING = 4
 MPGEO_PROFILE = 8
 MPGEO_DIST_GCD = 16
 MPGEO_BATCH_QUEUE = 32
+MPGEO_ESCALATE = 64
 
 EXPORTED = (
     "mpgeo_ctx_create", "mpgeo_ctx_destroy", "mpgeo_ctx_kernel_stats", "mpgeo_ctx_reset_stats",
@@ -53,7 +54,8 @@ class Result(ctypes.Structure):
     _fields_ = [("loglik", ctypes.c_double), ("logdet", ctypes.c_double), ("quad", ctypes.c_double),
                 ("info", ctypes.c_int64), ("t_covgen", ctypes.c_double),
                 ("t_factor", ctypes.c_double), ("t_solve", ctypes.c_double),
-                ("t_total", ctypes.c_double)]
+                ("t_total", ctypes.c_double), ("band64", ctypes.c_int32), ("band32", ctypes.c_int32),
+                ("band0", ctypes.c_int32), ("escalations", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -100,7 +102,7 @@ def _load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
     sig = {
-        "mpgeo_ctx_create": ([ctypes.POINTER(P), ctypes.c_int, P], ctypes.c_int),
+        "mpgeo_ctx_create": ([ctypes.POINTER(P), ctypes.c_int, P, ctypes.c_size_t], ctypes.c_int),
         "mpgeo_ctx_destroy": ([P], ctypes.c_int),
         "mpgeo_ctx_kernel_stats": ([P, ctypes.POINTER(KernelStat), ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
@@ -195,16 +197,18 @@ def plan_tiers(n: int, tile: int, band64: int, band32: int = -1, lowp=None, band
 
 
 class Context:
-    """A library context on one device, ordered on a HIP stream (default: torch's current)."""
+    """A library context on one device, ordered on a HIP stream (default: torch's current).
+    hbm_budget_bytes > 0 caps the tile memory of one evaluation (MPGEO_E_NOMEM beyond it)."""
 
-    def __init__(self, device: int = 0, stream: Optional["torch.cuda.Stream"] = None):
+    def __init__(self, device: int = 0, stream: Optional["torch.cuda.Stream"] = None,
+                 hbm_budget_bytes: int = 0):
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.device = device
         self.stream = stream
         handle = ctypes.c_void_p()
-        _check(LIB.mpgeo_ctx_create(ctypes.byref(handle), device, ctypes.c_void_p(stream.cuda_stream)),
-               "mpgeo_ctx_create")
+        _check(LIB.mpgeo_ctx_create(ctypes.byref(handle), device, ctypes.c_void_p(stream.cuda_stream),
+                                    int(hbm_budget_bytes)), "mpgeo_ctx_create")
         self.handle = handle
 
     def close(self) -> None:
@@ -220,30 +224,39 @@ class Context:
 
     def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
                morton: bool = True, timing: bool = False, band32: int = -1, lowp=None,
-               profile: bool = False, gcd: bool = False, band0: int = -1) -> dict:
+               profile: bool = False, gcd: bool = False, band0: int = -1,
+               escalate: bool = False) -> dict:
         """One-shot eq. (2) (or the profile likelihood): ordering, covariance tiles, factor,
-        solve, reduction."""
+        solve, reduction.  escalate=True: MPGEO_ESCALATE."""
         dev = isinstance(locs, torch.Tensor)
         if not dev:
             locs, z = _host_f64(locs), _host_f64(z)
         flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0) | \
                 (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0) | \
-                (MPGEO_DIST_GCD if gcd else 0)
+                (MPGEO_DIST_GCD if gcd else 0) | (MPGEO_ESCALATE if escalate else 0)
         res = Result()
         st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
                               make_plan(tile, band64, flags, band32, lowp, band0), ctypes.byref(res))
         _check(st, "mpgeo_loglik", res.info)
         return res.as_dict()
 
-    def factor_dense(self, a: np.ndarray, z, tile: int, band64: int, band32: int = -1,
-                     lowp=None, band0: int = -1) -> dict:
-        """Algorithm 1 on a given symmetric positive-definite matrix (lower triangle read)."""
-        a = np.asfortranarray(np.asarray(a, dtype=np.float64))
-        n = a.shape[0]
-        zz = None if z is None else _host_f64(z)
+    def factor_dense(self, a, z, tile: int, band64: int, band32: int = -1,
+                     lowp=None, band0: int = -1, escalate: bool = False) -> dict:
+        """Algorithm 1 on a given symmetric positive-definite matrix (lower triangle read);
+        a (and z) may be torch tensors on the device (a column-major: pass the transpose of a
+        contiguous row-major tensor's storage, i.e. a symmetric matrix as is)."""
+        flags = MPGEO_ESCALATE if escalate else 0
+        if isinstance(a, torch.Tensor):
+            n = int(a.shape[0])
+            zz = z
+            flags |= MPGEO_INPUT_DEVICE
+        else:
+            a = np.asfortranarray(np.asarray(a, dtype=np.float64))
+            n = a.shape[0]
+            zz = None if z is None else _host_f64(z)
         res = Result()
-        st = LIB.mpgeo_factor_dense(self.handle, n, a.ctypes.data, n, _ptr(zz),
-                                    make_plan(tile, band64, 0, band32, lowp, band0), ctypes.byref(res))
+        st = LIB.mpgeo_factor_dense(self.handle, n, _ptr(a), n, _ptr(zz),
+                                    make_plan(tile, band64, flags, band32, lowp, band0), ctypes.byref(res))
         _check(st, "mpgeo_factor_dense", res.info)
         return res.as_dict()
 
@@ -315,20 +328,23 @@ class Dataset:
 
     def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False,
                band32: int = -1, lowp=None, profile: bool = False, band0: int = -1,
-               dist64: float = 0.0, dist32: float = 0.0) -> dict:
+               dist64: float = 0.0, dist32: float = 0.0, escalate: bool = False) -> dict:
         res = Result()
-        flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0)
+        flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0) | \
+                (MPGEO_ESCALATE if escalate else 0)
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
                                       make_plan(tile, band64, flags, band32, lowp, band0, dist64, dist32),
                                       ctypes.byref(res))
         _check(st, "mpgeo_dataset_loglik", res.info)
         return res.as_dict()
 
-    def try_loglik(self, theta: Sequence[float], tile: int, band64: int, band0: int = -1) -> tuple:
+    def try_loglik(self, theta: Sequence[float], tile: int, band64: int, band0: int = -1,
+                   band32: int = -1, lowp=None, escalate: bool = False) -> tuple:
         """(status, result dict) without raising (for optimisers that meet non-SPD points)."""
         res = Result()
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
-                                      make_plan(tile, band64, 0, -1, None, band0), ctypes.byref(res))
+                                      make_plan(tile, band64, MPGEO_ESCALATE if escalate else 0, band32,
+                                                lowp, band0), ctypes.byref(res))
         return st, res.as_dict()
 
     def krige(self, new_locs, variance: bool = False):
@@ -387,14 +403,15 @@ class Dataset:
 
     def mle(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
             ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None,
-            profile: bool = False) -> dict:
+            profile: bool = False, escalate: bool = False) -> dict:
         """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2)); with
         profile=True a two-dimensional search over (theta2, theta3) of the profile likelihood."""
         th = Theta()
         ll = ctypes.c_double()
         ev = ctypes.c_int32()
         it = ctypes.c_int32()
-        plan = make_plan(tile, band64, MPGEO_PROFILE if profile else 0, band32, lowp)
+        plan = make_plan(tile, band64, (MPGEO_PROFILE if profile else 0) |
+                         (MPGEO_ESCALATE if escalate else 0), band32, lowp)
         _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), plan, xtol, ftol,
                                      max_evals, ctypes.byref(th), ctypes.byref(ll), ctypes.byref(ev),
                                      ctypes.byref(it)), "mpgeo_dataset_mle")

@@ -399,6 +399,7 @@ struct mpgeo_ctx {
     hipStream_t next = nullptr;
     int reserved_cus = 0;
     int cus = 0;                           // compute units of the device
+    size_t hbm_budget = 0;                 // tile bytes one evaluation may use (0: no cap)
     std::vector<hipEvent_t> sync_events;   // dependency events between the streams
 
     // at least `count` timing-free events for stream dependencies
@@ -503,6 +504,7 @@ struct mpgeo_dataset {
     DevBuf r, y, parts, info, result;
     DevBuf tmp_a, tmp_b, tmp_c;
     DevBuf fp64tab, trsm64l, trsm32l;   // distance-drawn precision map
+    DevBuf chk;                         // finiteness flag of device inputs
     bool has_factor = false;
     mpgeo_theta theta{};      // theta of the resident factor (theta1 = 1 for a profile evaluation)
     bool profile = false;     // the last evaluation used the profile likelihood
@@ -532,6 +534,72 @@ int check_plan(const mpgeo_plan &pl) {
     if (pl.dist32 > 0.0) return MPGEO_E_ARG;
     if ((pl.band32 >= 0) != (pl.lowp != 0)) return MPGEO_E_ARG;   // a third tier needs its format
     return MPGEO_OK;
+}
+
+bool all_finite(const double *a, size_t count) {
+    for (size_t e = 0; e < count; ++e)
+        if (!std::isfinite(a[e])) return false;
+    return true;
+}
+
+// Non-finite entries among `count` device doubles: a reduction on the context stream, read
+// back synchronously (inputs are checked once, when they enter the library).
+int device_all_finite(mpgeo_dataset *ds, const double *a, int64_t count, bool *ok) {
+    *ok = true;
+    if (count <= 0) return MPGEO_OK;
+    hipStream_t s = ds->ctx->stream;
+    MPGEO_TRY(ds->chk.ensure(sizeof(int)));
+    MPGEO_HIP(hipMemsetAsync(ds->chk.ptr, 0, sizeof(int), s));
+    launch_find_nonfinite(a, count, 1, count, false, ds->chk.as<int>(), s);
+    MPGEO_HIP(hipGetLastError());
+    int flag = 0;
+    MPGEO_HIP(hipMemcpyAsync(&flag, ds->chk.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    MPGEO_HIP(hipStreamSynchronize(s));
+    *ok = flag == 0;
+    return MPGEO_OK;
+}
+
+// Inputs of either kind: host arrays on the host, device arrays by the reduction above.
+int check_finite(mpgeo_dataset *ds, const double *a, int64_t count, bool on_device) {
+    if (!a || count <= 0) return MPGEO_OK;
+    if (!on_device) return all_finite(a, (size_t)count) ? MPGEO_OK : MPGEO_E_ARG;
+    bool ok = true;
+    MPGEO_TRY(device_all_finite(ds, a, count, &ok));
+    return ok ? MPGEO_OK : MPGEO_E_ARG;
+}
+
+// HBM bytes of a built layout's tiles: both pools (the shared zero tile of dropped tiles
+// included) and, with a 16-bit tier, the 16-bit copy of the factor.
+size_t layout_footprint(const Layout &L) {
+    const size_t te = (size_t)L.nbp * L.nbp;
+    const size_t q16 = L.lowp ? (size_t)L.p * (L.p + 1) / 2 * te * 2 : 0;
+    return (size_t)L.n64 * te * sizeof(double) +
+           ((size_t)L.n32 + (L.has_zero_tile ? 1 : 0)) * te * sizeof(float) + q16;
+}
+
+// The next plan of MPGEO_ESCALATE for a matrix of p tile rows: every reduced band widened,
+// b -> 2b + 1 (band64, band32, band0), a band reaching the last tile row becoming -1; once the
+// FP64 band covers the matrix the third tier goes too; a distance-drawn map becomes all-FP64.
+// False when the plan is already all-FP64 with nothing dropped.
+bool escalate_plan(mpgeo_plan &pl, int64_t p) {
+    auto full = [&](int32_t b) { return b < 0 || (int64_t)b >= p - 1; };
+    if (pl.dist64 > 0.0) {
+        pl.dist64 = pl.dist32 = 0.0;
+        pl.band64 = pl.band32 = pl.band0 = -1;
+        pl.lowp = 0;
+        return true;
+    }
+    if (full(pl.band64) && full(pl.band0)) return false;
+    auto widen = [&](int32_t b) { return full(b) ? -1 : ((int64_t)2 * b + 1 >= p - 1 ? -1 : 2 * b + 1); };
+    pl.band0 = widen(pl.band0);
+    pl.band64 = widen(pl.band64);
+    if (pl.band64 < 0) {
+        pl.band32 = -1;
+        pl.lowp = 0;
+    } else if (pl.band32 >= 0) {
+        pl.band32 = (int32_t)std::min<int64_t>((int64_t)2 * pl.band32 + 1, p);
+    }
+    return true;
 }
 
 TileMap tile_map(const mpgeo_dataset *ds) {
@@ -585,8 +653,14 @@ int prepare_layout(mpgeo_dataset *ds, const mpgeo_plan &pl) {
     }
     const int nbp_new = (pl.tile + kTileQuantum - 1) / kTileQuantum * kTileQuantum;
     const int wave16 = pl.lowp ? lowp_wave_tiles(nbp_new, pl.lowp, ds->ctx->cus - ds->ctx->reserved_cus) : 0;
-    L.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp, pl.band0, dmap ? &boxes : nullptr,
-            pl.dist64, pl.dist32, wave16);
+    {
+        Layout fresh;
+        fresh.build(ds->n, pl.tile, pl.band64, pl.band32, pl.lowp, pl.band0, dmap ? &boxes : nullptr,
+                    pl.dist64, pl.dist32, wave16);
+        // the context's HBM budget, checked before anything is allocated
+        if (ds->ctx->hbm_budget > 0 && layout_footprint(fresh) > ds->ctx->hbm_budget) return MPGEO_E_NOMEM;
+        L = std::move(fresh);
+    }
     ds->has_factor = false;
     const size_t te = (size_t)L.nbp * L.nbp;
     const size_t tiles32 = (size_t)L.n32 + (L.has_zero_tile ? 1 : 0);
@@ -660,6 +734,10 @@ int load_inputs(mpgeo_dataset *ds, const double *locs, const double *z, uint32_t
     mpgeo_ctx *ctx = ds->ctx;
     hipStream_t s = ctx->stream;
     const int64_t n = ds->n;
+    // sites and data must be finite (checked before they are used)
+    const bool on_dev = (flags & MPGEO_INPUT_DEVICE) != 0;
+    MPGEO_TRY(check_finite(ds, locs, 2 * n, on_dev));
+    MPGEO_TRY(check_finite(ds, z, n, on_dev));
     MPGEO_TRY(ds->locs.ensure((size_t)n * 2 * sizeof(double)));
     MPGEO_TRY(ds->z.ensure((size_t)n * sizeof(double)));
     MPGEO_TRY(ds->perm.ensure((size_t)n * sizeof(int64_t)));
@@ -1018,7 +1096,24 @@ int evaluate(mpgeo_dataset *ds, const mpgeo_theta &th, const mpgeo_plan &pl, mpg
     ds->has_factor = (st == MPGEO_OK);
     ds->theta = th_eval;
     ds->var_scale = ds->profile ? out->quad / (double)ds->layout.n : 1.0;
+    out->band64 = pl.band64;
+    out->band32 = pl.band32;
+    out->band0 = pl.band0;
+    out->escalations = 0;
     return st;
+}
+
+// evaluate(), repeated with wider bands while the factorization meets a non-positive pivot
+// and the plan asks for it (MPGEO_ESCALATE; Section VIII-D-1: reduced precision next to the
+// diagonal can cost positive definiteness)
+int evaluate_escalating(mpgeo_dataset *ds, const mpgeo_theta &th, mpgeo_plan pl, mpgeo_result *out,
+                        hipEvent_t ev_start_outer) {
+    const int64_t p = (ds->n + pl.tile - 1) / pl.tile;
+    for (int esc = 0;; ++esc) {
+        const int st = evaluate(ds, th, pl, out, ev_start_outer);
+        out->escalations = esc;
+        if (st != MPGEO_E_NOT_SPD || !(pl.flags & MPGEO_ESCALATE) || !escalate_plan(pl, p)) return st;
+    }
 }
 
 struct Device {
@@ -1077,10 +1172,7 @@ size_t mpgeo_footprint_bytes(int64_t n, mpgeo_plan plan) {
     Layout L;
     if (plan.dist64 > 0.0) plan.band64 = -1;   // the map needs the sites: bound it by all-FP64
     L.build(n, plan.tile, plan.band64, plan.band32, plan.lowp, plan.band0);
-    const size_t te = (size_t)L.nbp * L.nbp;
-    const size_t q16 = L.lowp ? (size_t)L.p * (L.p + 1) / 2 * te * 2 : 0;   // 16-bit factor copy
-    return (size_t)L.n64 * te * sizeof(double) +
-           ((size_t)L.n32 + (L.has_zero_tile ? 1 : 0)) * te * sizeof(float) + q16;
+    return layout_footprint(L);
 }
 
 // Reserved compute units for the critical path: MPGEO_RESERVED_CUS (default 0: none),
@@ -1139,7 +1231,7 @@ int mpgeo_plan_tiers(int64_t n, mpgeo_plan plan, mpgeo_tier_summary *out) {
     return MPGEO_OK;
 }
 
-int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {
+int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream, size_t hbm_budget_bytes) {
     if (!out) return MPGEO_E_ARG;
     *out = nullptr;
     int count = 0;
@@ -1151,6 +1243,7 @@ int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream) {
     MPGEO_HIP(hipSetDevice(device));
     mpgeo_ctx *c = new mpgeo_ctx();
     c->device = device;
+    c->hbm_budget = hbm_budget_bytes;
     if (hip_stream) {
         c->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -1251,7 +1344,7 @@ int mpgeo_dataset_destroy(mpgeo_dataset *ds) {
                       &ds->list16, &ds->bulk16, &ds->bulk16k0, &ds->q16, &ds->qscale,
                       &ds->p64, &ds->p32, &ds->linv, &ds->linv32, &ds->r, &ds->y, &ds->parts,
                       &ds->info, &ds->result, &ds->tmp_a, &ds->tmp_b, &ds->tmp_c, &ds->fp64tab,
-                      &ds->trsm64l, &ds->trsm32l})
+                      &ds->trsm64l, &ds->trsm32l, &ds->chk})
         b->release();
     delete ds;
     return MPGEO_OK;
@@ -1265,7 +1358,7 @@ int mpgeo_dataset_loglik(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan, 
     Device dev(ds->ctx->device);
     if (!dev.ok) return MPGEO_E_DEVICE;
     ds->ctx->timing = (plan.flags & MPGEO_TIMING) != 0;
-    const int st = evaluate(ds, theta, plan, out, nullptr);
+    const int st = evaluate_escalating(ds, theta, plan, out, nullptr);
     ds->ctx->timing = false;
     return st;
 }
@@ -1294,7 +1387,7 @@ int mpgeo_loglik(mpgeo_ctx *ctx, int64_t n, const double *locs, const double *z,
     EventSet ev;
     if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[0], ctx->stream));
     int st = load_inputs(ds, locs, z, plan.flags);
-    if (st == MPGEO_OK) st = evaluate(ds, theta, plan, out, ev.ok ? ev.e[0] : nullptr);
+    if (st == MPGEO_OK) st = evaluate_escalating(ds, theta, plan, out, ev.ok ? ev.e[0] : nullptr);
     ctx->timing = false;
     return st;
 }
@@ -1362,6 +1455,7 @@ int mpgeo_dataset_krige(mpgeo_dataset *ds, int64_t m, const double *new_locs, do
     Device dev(ds->ctx->device);
     hipStream_t s = ds->ctx->stream;
     const bool on_dev = (ds->flags & MPGEO_INPUT_DEVICE) != 0;
+    MPGEO_TRY(check_finite(ds, new_locs, 2 * m, on_dev));
     // new sites and outputs on the device
     const size_t need = (size_t)m * 2 * sizeof(double) + 2 * (size_t)m * sizeof(double);
     MPGEO_TRY(ds->tmp_b.ensure(need));
@@ -1427,7 +1521,7 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
     // objective: -loglik; a non-positive-definite point scores +infinity
     auto f = [&](const double *u) -> double {
         mpgeo_result r{};
-        const int st = evaluate(ds, to_theta(u), plan, &r, nullptr);
+        const int st = evaluate_escalating(ds, to_theta(u), plan, &r, nullptr);
         if (st == MPGEO_OK) return -r.loglik;
         if (st != MPGEO_E_NOT_SPD && hard_error == MPGEO_OK) hard_error = st;
         return INFINITY;
@@ -1519,7 +1613,7 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
     if (!std::isfinite(fv[best])) return MPGEO_E_NOT_SPD;
     mpgeo_theta th = to_theta(x[best]);
     mpgeo_result r{};
-    MPGEO_TRY(evaluate(ds, th, plan, &r, nullptr));   // leave the factor of theta_hat resident
+    MPGEO_TRY(evaluate_escalating(ds, th, plan, &r, nullptr));   // leave the factor of theta_hat resident
     if (profile) th.sigma2 = r.quad / (double)ds->layout.n;
     if (theta_hat) *theta_hat = th;
     if (loglik_hat) *loglik_hat = r.loglik;
@@ -1538,13 +1632,14 @@ int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan
     hipStream_t s = ds->ctx->stream;
     const int64_t n = ds->n;
     const bool on_dev = (ds->flags & MPGEO_INPUT_DEVICE) != 0;
+    MPGEO_TRY(check_finite(ds, eps, n, on_dev));
     // factor Sigma(theta) with a zero data vector (the dataset's z is kept aside)
     DevBuf saved_z;
     MPGEO_TRY(saved_z.ensure((size_t)n * sizeof(double)));
     MPGEO_HIP(hipMemcpyAsync(saved_z.ptr, ds->z.ptr, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
     MPGEO_HIP(hipMemsetAsync(ds->z.ptr, 0, (size_t)n * sizeof(double), s));
     mpgeo_result r{};
-    int st = evaluate(ds, theta, plan, &r, nullptr);
+    int st = evaluate_escalating(ds, theta, plan, &r, nullptr);
     (void)hipMemcpyAsync(ds->z.ptr, saved_z.ptr, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (st != MPGEO_OK) {
         (void)hipStreamSynchronize(s);
@@ -1580,6 +1675,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
     if ((plan.flags & MPGEO_PROFILE) && !z) return MPGEO_E_ARG;
     out->info = -1;
     MPGEO_TRY(check_plan(plan));
+    if (plan.dist64 > 0.0) return MPGEO_E_ARG;   // a distance map needs sites
     Device dev(ctx->device);
     if (!dev.ok) return MPGEO_E_DEVICE;
     mpgeo_dataset ds;
@@ -1588,7 +1684,26 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
     ds.profile = (plan.flags & MPGEO_PROFILE) != 0;
     hipStream_t s = ctx->stream;
     const bool on_dev = (plan.flags & MPGEO_INPUT_DEVICE) != 0;
-    int st = prepare_layout(&ds, plan);
+    int st = MPGEO_OK;
+    // the lower triangle and z must be finite
+    if (!on_dev) {
+        for (int64_t c = 0; c < n && st == MPGEO_OK; ++c)
+            if (!all_finite(a + c * lda + c, (size_t)(n - c))) st = MPGEO_E_ARG;
+        if (st == MPGEO_OK && z && !all_finite(z, (size_t)n)) st = MPGEO_E_ARG;
+    } else {
+        st = ds.chk.ensure(sizeof(int));
+        int flag = 0;
+        if (st == MPGEO_OK && hipMemsetAsync(ds.chk.ptr, 0, sizeof(int), s) != hipSuccess) st = MPGEO_E_DEVICE;
+        if (st == MPGEO_OK) {
+            launch_find_nonfinite(a, n, n, lda, true, ds.chk.as<int>(), s);
+            if (z) launch_find_nonfinite(z, n, 1, n, false, ds.chk.as<int>(), s);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(&flag, ds.chk.ptr, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                st = MPGEO_E_DEVICE;
+            else if (flag) st = MPGEO_E_ARG;
+        }
+    }
     const double *da = a;
     if (st == MPGEO_OK && !on_dev) {
         st = ds.tmp_a.ensure((size_t)lda * n * sizeof(double));
@@ -1605,8 +1720,14 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
                                 on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
         if (e != hipSuccess) st = MPGEO_E_DEVICE;
     }
-    if (st == MPGEO_OK) {
-        ctx->timing = (plan.flags & MPGEO_TIMING) != 0;
+    // Algorithm 1 on the imported tiles; with MPGEO_ESCALATE, again with wider bands after a
+    // non-positive pivot
+    mpgeo_plan pl = plan;
+    const int64_t p = (n + plan.tile - 1) / plan.tile;
+    for (int esc = 0; st == MPGEO_OK; ++esc) {
+        st = prepare_layout(&ds, pl);
+        if (st != MPGEO_OK) break;
+        ctx->timing = (pl.flags & MPGEO_TIMING) != 0;
         EventSet ev;
         if (ev.ok) (void)hipEventRecord(ev.e[0], s);
         launch_import_dense(tile_map(&ds), da, lda, ds.all.as<TileIJ>(), (int64_t)ds.layout.all.size(), s);
@@ -1620,15 +1741,21 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
             out->t_factor = ev.secs(1, 2);
             out->t_solve = ev.secs(2, 3);
             out->t_total = ev.secs(0, 3);
+            out->band64 = pl.band64;
+            out->band32 = pl.band32;
+            out->band0 = pl.band0;
+            out->escalations = esc;
         }
         ctx->collect();
         ctx->timing = false;
+        if (st != MPGEO_E_NOT_SPD || !(pl.flags & MPGEO_ESCALATE) || !escalate_plan(pl, p)) break;
+        st = MPGEO_OK;
     }
     (void)hipStreamSynchronize(s);
     for (DevBuf *b : {&ds.pool64, &ds.pool32, &ds.off, &ds.all, &ds.list64, &ds.list32, &ds.list16,
                       &ds.bulk16, &ds.bulk16k0, &ds.q16, &ds.qscale, &ds.p64,
                       &ds.p32, &ds.linv, &ds.linv32, &ds.r, &ds.y, &ds.parts, &ds.info, &ds.result,
-                      &ds.tmp_a, &ds.z})
+                      &ds.tmp_a, &ds.z, &ds.chk})
         b->release();
     return st;
 }
@@ -1642,7 +1769,7 @@ int mpgeo_factor_dense(mpgeo_ctx *ctx, int64_t n, const double *a, int64_t lda, 
 static int batch_lanes(mpgeo_ctx *ctx, int want) {
     while ((int)ctx->lanes.size() < want) {
         mpgeo_ctx *c = nullptr;
-        MPGEO_TRY(mpgeo_ctx_create(&c, ctx->device, nullptr));
+        MPGEO_TRY(mpgeo_ctx_create(&c, ctx->device, nullptr, ctx->hbm_budget));
         // Lanes overlap whole evaluations with each other; a third stream per lane only adds
         // small launches and queues (the hardware has few), so a lane's column k+2 updates
         // stay on its bulk stream.
@@ -1750,7 +1877,12 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
     MPGEO_HIP(hipMemGetInfo(&free_b, &total_b));
     // tiles dominate: keep a group's tiles within half of the free memory (the buffers of an
     // earlier, larger group are reused)
-    const size_t budget = std::max<size_t>(free_b / 2 + ctx->q_tiles.bytes, (size_t)te * 8 * 64);
+    size_t budget = std::max<size_t>(free_b / 2 + ctx->q_tiles.bytes, (size_t)te * 8 * 64);
+    if (ctx->hbm_budget > 0) {   // the context's cap: every problem must fit in it alone
+        budget = std::min(budget, ctx->hbm_budget);
+        for (int64_t q = 0; q < count; ++q)
+            if ((size_t)tiles_of(q) * te * 8 > budget) return MPGEO_E_NOMEM;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
         (void)hipGetLastError();
@@ -1877,6 +2009,7 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
                        mpgeo_result *out, int32_t *tiles) {
     if (!ctx || count < 0 || (count > 0 && (!inst || !out))) return MPGEO_E_ARG;
     if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
+    if (plan.flags & MPGEO_ESCALATE) return MPGEO_E_UNSUPPORTED;
     mpgeo_plan chk = plan;
     if (chk.tile == 0) chk.tile = 1;
     MPGEO_TRY(check_plan(chk));
@@ -1884,6 +2017,8 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         if (inst[i].n < 1 || inst[i].n > (int64_t)0xFFFFFFFF || !inst[i].locs || !inst[i].z)
             return MPGEO_E_ARG;
         MPGEO_TRY(check_theta(inst[i].theta));
+        if (!all_finite(inst[i].locs, 2 * (size_t)inst[i].n) || !all_finite(inst[i].z, (size_t)inst[i].n))
+            return MPGEO_E_ARG;
         out[i].info = -1;
     }
     if (plan.flags & MPGEO_BATCH_QUEUE) {
@@ -1999,7 +2134,9 @@ int mpgeo_server_add_dataset(mpgeo_server *srv, int64_t n, const double *locs, c
                              mpgeo_plan plan, int32_t *id) {
     if (!srv || !locs || !z || !id || n < 1 || n > (int64_t)0xFFFFFFFF) return MPGEO_E_ARG;
     if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
+    if (plan.flags & MPGEO_ESCALATE) return MPGEO_E_UNSUPPORTED;
     MPGEO_TRY(check_plan(plan));
+    if (!all_finite(locs, 2 * (size_t)n) || !all_finite(z, (size_t)n)) return MPGEO_E_ARG;
     ServedDataset d;
     d.n = n;
     d.locs.assign(locs, locs + 2 * n);
@@ -2033,6 +2170,7 @@ int mpgeo_server_submit_krige(mpgeo_server *srv, int32_t dataset, mpgeo_theta th
         !new_locs || !pred || (var && m > 65535))
         return MPGEO_E_ARG;
     MPGEO_TRY(check_theta(theta));
+    if (!all_finite(new_locs, 2 * (size_t)m)) return MPGEO_E_ARG;
     ServedRequest rq;
     rq.dataset = dataset;
     rq.theta = theta;

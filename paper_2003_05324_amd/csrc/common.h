@@ -82,6 +82,12 @@ void launch_pad_vector(const double *src, double *dst, int64_t n, int nb, int nb
 void launch_unpad_vector(const double *src, double *dst, int64_t n, int nb, int nbp,
                          hipStream_t stream);
 
+// Input check: *flag (zeroed by the caller) is set to 1 when an entry of the rows x cols
+// column-major array a (leading dimension ld) is not finite; with lower, only entries on or
+// below the diagonal are looked at.
+void launch_find_nonfinite(const double *a, int64_t rows, int64_t cols, int64_t ld, bool lower,
+                           int *flag, hipStream_t stream);
+
 // Z-order keys, sort, and gather of locations and data.
 void launch_morton_order(const double *locs_in, const double *z_in, int64_t n, bool lonlat,
                          uint64_t *keys, int64_t n2, double *locs_out, double *z_out,

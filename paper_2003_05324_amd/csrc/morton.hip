@@ -9,6 +9,8 @@
 // partner distance fits in a workgroup run in LDS, the others as global passes.
 #include "morton_dev.h"
 
+#include <algorithm>
+
 namespace mpgeo {
 
 namespace {
@@ -82,7 +84,29 @@ __global__ void gather_kernel(const double *locs_in, const double *z_in, const u
     perm[e] = src;
 }
 
+__global__ void find_nonfinite_kernel(const double *a, int64_t rows, int64_t cols, int64_t ld,
+                                      int lower, int *flag) {
+    const int64_t total = rows * cols;
+    bool bad = false;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e % rows, c = e / rows;
+        if (lower && r < c) continue;
+        bad |= !isfinite(a[r + c * ld]);
+    }
+    if (bad) *flag = 1;   // every writer stores the same value
+}
+
 }  // namespace
+
+void launch_find_nonfinite(const double *a, int64_t rows, int64_t cols, int64_t ld, bool lower,
+                           int *flag, hipStream_t stream) {
+    const int64_t total = rows * cols;
+    if (total <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 2048);
+    hipLaunchKernelGGL(find_nonfinite_kernel, dim3(blocks), dim3(256), 0, stream, a, rows, cols, ld,
+                       lower ? 1 : 0, flag);
+}
 
 // n2 must be a power of two >= max(n, kSortLocal); keys has n2 entries.
 void launch_morton_order(const double *locs_in, const double *z_in, int64_t n, bool lonlat,

@@ -82,8 +82,72 @@ static int check(int64_t n, int nb, int band64, int band32, int band0, int wave)
     return bad;
 }
 
-int main() {
+// The escalation ladder of MPGEO_ESCALATE: bands b -> 2b + 1 until they reach the last tile
+// row (then -1, and the third tier goes with the FP64 band); the all-FP64 plan cannot escalate.
+static int check_escalation() {
     int bad = 0;
+    auto expect = [&](const mpgeo_plan &pl, int b64, int b32, int lowp, int b0, const char *what) {
+        if (pl.band64 != b64 || pl.band32 != b32 || pl.lowp != lowp || pl.band0 != b0) {
+            std::printf("  escalation %s: got band64 %d band32 %d lowp %d band0 %d\n", what, pl.band64,
+                        pl.band32, pl.lowp, pl.band0);
+            ++bad;
+        }
+    };
+    mpgeo_plan pl{};
+    pl.tile = 160;
+    pl.band64 = 0;
+    pl.band32 = -1;
+    pl.band0 = -1;
+    const int64_t p = 10;   // n = 1,600, tile 160
+    int steps = 0;
+    const int want[] = {1, 3, 7, -1};
+    while (escalate_plan(pl, p)) {
+        if (steps < 4) expect(pl, want[steps], -1, 0, -1, "two tiers");
+        ++steps;
+    }
+    if (steps != 4) {
+        std::printf("  escalation took %d steps, want 4\n", steps);
+        ++bad;
+    }
+    mpgeo_plan q{};
+    q.tile = 512;
+    q.band64 = 2;
+    q.band32 = 8;
+    q.lowp = 1;
+    q.band0 = -1;
+    if (!escalate_plan(q, 196)) ++bad;
+    expect(q, 5, 17, 1, -1, "three tiers, first step");
+    q.band64 = 100;
+    if (!escalate_plan(q, 196)) ++bad;
+    expect(q, -1, -1, 0, -1, "three tiers into all FP64");
+    mpgeo_plan z{};
+    z.tile = 100;
+    z.band64 = -1;
+    z.band32 = -1;
+    z.band0 = 2;
+    if (!escalate_plan(z, 31)) ++bad;
+    expect(z, -1, -1, 0, 5, "dropped tiles");
+    // the footprint of a built layout is the one the boundary reports
+    for (int b : {-1, 0, 2}) {
+        mpgeo_plan f{};
+        f.tile = 512;
+        f.band64 = b;
+        f.band32 = b >= 0 ? 8 : -1;
+        f.lowp = b >= 0 ? 1 : 0;
+        f.band0 = -1;
+        Layout L;
+        L.build(99856, 512, f.band64, f.band32, f.lowp, f.band0);
+        if (layout_footprint(L) != mpgeo_footprint_bytes(99856, f)) {
+            std::printf("  footprint of band64 %d differs\n", b);
+            ++bad;
+        }
+    }
+    std::printf("escalation ladder and footprint: %s\n", bad ? "FAILED" : "ok");
+    return bad;
+}
+
+int main() {
+    int bad = check_escalation();
     bad += check(99856, 512, 2, 8, -1, 64);     // the n ~ 1e5 three-tier plan on 256 compute units
     bad += check(99856, 512, 2, 8, -1, 32);
     bad += check(99856, 512, 2, 8, -1, 0);      // wave size unknown: no filling

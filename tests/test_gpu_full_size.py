@@ -8,7 +8,10 @@ oracle computes one at a time, and properties that hold at any size:
   * sampled rows of L y = z (forward solve);
   * logdet = 2 sum log L_ii over the whole diagonal;
   * the band path's log-likelihood against the all-FP64 path (itself oracle-exact at the
-    sizes the oracle reaches): |dl| / max(|l|, n) <= 1e-5.
+    sizes the oracle reaches): |dl| / |l| <= 1e-5 (l = 29,534 here);
+  * the three-tier plans likewise: FP16 operands at FP32 width 8 within 1e-5; BF16 operands at
+    width 8 miss it (a reported row, held to the derived worst case 20 * 2^-8), at width 24
+    they are asserted within 1e-5.
 """
 import math
 
@@ -121,23 +124,25 @@ def test_band_path_against_fp64_path(lib, full):
     a = ds.loglik(THETA, TILE, 2)
     b = ds.loglik(THETA, TILE, -1)
     ds.close()
-    assert abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), n) <= 1e-5
+    assert abs(a["loglik"] - b["loglik"]) / abs(b["loglik"]) <= 1e-5
     assert abs(a["logdet"] - b["logdet"]) / abs(b["logdet"]) <= 1e-6
 
 
-@pytest.mark.parametrize("lowp", ["fp16", "bf16"])
-def test_three_tier_against_fp64_path(lib, full, lowp):
-    # FP64 band 2, FP32 for the next 8 tiles, 16-bit operands beyond (the n ~ 1e5 workload)
+@pytest.mark.parametrize("lowp,band32,asserted", [("fp16", 8, True), ("bf16", 8, False),
+                                                  ("bf16", 24, True)])
+def test_three_tier_against_fp64_path(lib, full, lowp, band32, asserted):
+    # FP64 band 2, FP32 for the next band32 tiles, 16-bit operands beyond (the n ~ 1e5 workload)
     ctx, locs = full["ctx"], full["locs"]
     gen = lib.Dataset(ctx, locs, None)
     z = gen.simulate(THETA, LARGE.eps(), TILE, -1)
     gen.close()
     ds = lib.Dataset(ctx, locs, z)
     n = LARGE.n
-    a = ds.loglik(THETA, TILE, 2, band32=8, lowp=lowp)
+    a = ds.loglik(THETA, TILE, 2, band32=band32, lowp=lowp)
     b = ds.loglik(THETA, TILE, -1)
     ds.close()
-    err = abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), n)
-    print(f"n={n} three-tier {lowp}: |dl|/max(|l|,n) vs FP64 path = {err:.3e}, "
-          f"dlogdet/|logdet| = {abs(a['logdet'] - b['logdet']) / abs(b['logdet']):.3e}")
-    assert err <= {"fp16": 1e-2, "bf16": 8e-2}[lowp]
+    err = abs(a["loglik"] - b["loglik"]) / abs(b["loglik"])
+    print(f"n={n} three-tier {lowp} band32={band32}: |dl|/|l| vs FP64 path = {err:.3e}, "
+          f"dlogdet/|logdet| = {abs(a['logdet'] - b['logdet']) / abs(b['logdet']):.3e}"
+          f"{'' if asserted else ' (reported row)'}")
+    assert err <= (1e-5 if asserted else 20 * 2.0 ** -8)

@@ -2,7 +2,10 @@
 
 Tolerances:
   * all-FP64 path:       |dl| / |l| <= 1e-10 (also logdet and quad);
-  * FP64/FP32 band path: |dl| / max(|l|, n) <= 1e-5;
+  * FP64/FP32 band path: |dl| / |l| <= 1e-5 where l is well away from zero (the n = 1,600
+    workload: |l| ~ 1,200 at every theta), |dl| / max(|l|, n) <= 1e-5 for the small random
+    problems whose l can pass through zero;
+  * third tier (FP16 operands): |dl| / |l| <= 1e-5; BF16 where its FP32 width makes it;
   * Morton permutation:  bit-exact;
   * covariance entries:  FP64 tiles within 1e-13 relative of the oracle for nu = 1/2 (both
     sides elementary) and 5e-13 for general nu (the oracle's Bessel routine itself is good
@@ -97,12 +100,11 @@ def test_fp64_path_matches_oracle(small_ds, theta):
 
 
 @pytest.mark.parametrize("band", [2, 1, 0])
-@pytest.mark.parametrize("theta", [SMALL.theta] + perturbed_thetas(SMALL.theta)[::3])
+@pytest.mark.parametrize("theta", [SMALL.theta] + perturbed_thetas(SMALL.theta))
 def test_band_path_matches_oracle(small_ds, theta, band):
     want = small_oracle(tuple(theta))
     got = small_ds.loglik(theta, SMALL.tile, band)
-    n = SMALL.n
-    assert abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), n) <= 1e-5
+    assert rel(got["loglik"], want["loglik"]) <= 1e-5
 
 
 def test_one_shot_equals_resident_dataset(lib, ctx, small_ds):
@@ -306,28 +308,29 @@ def test_mle_matches_oracle(lib, small_ds, band):
 
 
 # ---- third precision tier (16-bit operands for the farthest tiles) -------------------------
-# Tolerance (derived): a 16-bit operand carries a relative rounding error u (2^-11 for FP16,
-# 2^-8 for BF16); each far-tile update A_ij -= L_ik L_jk^T then errs by at most 2u of the
-# magnitude sum |L_ik||L_jk| <= sigma2, and those perturbations enter l through
-# tr(Sigma^-1 dSigma) and the quadratic form.  For the n = 1,600 workload this is bounded here
-# by |dl| / max(|l|, n) <= 20u: 1e-2 (FP16) and 8e-2 (BF16) — generous on purpose; the test
-# prints the measured error, which is what the benchmark reports.
-LOWP_TOL = {"fp16": 20 * 2.0 ** -11, "bf16": 20 * 2.0 ** -8}
+# Bar: the mixed paths' 1e-5 on |dl| / |l|.  FP16 (u = 2^-11 per operand) meets it at every FP32
+# width here; BF16 (u = 2^-8) needs FP32 tiles beyond the band (width >= 2): with width 0 its
+# error reaches 2e-5 at some of the nine theta, a reported row, held only to the derived worst
+# case 20u of a BF16 operand tier (each far-tile update errs by at most 2u of
+# sum |L_ik||L_jk| <= theta1, entering l through tr(Sigma^-1 dSigma) and the quadratic form).
+LOWP_BAR = 1e-5
+LOWP_WORST = {"fp16": 20 * 2.0 ** -11, "bf16": 20 * 2.0 ** -8}
 
 
 @pytest.mark.parametrize("lowp", ["fp16", "bf16"])
 @pytest.mark.parametrize("band32", [0, 2, 5])
-def test_three_tier_matches_oracle(small_ds, lowp, band32):
-    theta = SMALL.theta
+@pytest.mark.parametrize("theta", [SMALL.theta] + perturbed_thetas(SMALL.theta))
+def test_three_tier_matches_oracle(small_ds, theta, lowp, band32):
     want = small_oracle(tuple(theta))
     got = small_ds.loglik(theta, SMALL.tile, 2, band32=band32, lowp=lowp)
-    err = abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n)
-    print(f"three-tier {lowp} band64=2 band32={band32}: |dl|/max(|l|,n) = {err:.3e}")
-    assert err <= LOWP_TOL[lowp]
+    err = rel(got["loglik"], want["loglik"])
+    asserted = lowp == "fp16" or band32 >= 2
+    print(f"three-tier {lowp} band64=2 band32={band32} theta={theta}: |dl|/|l| = {err:.3e}"
+          f"{'' if asserted else ' (reported row)'}")
+    assert err <= (LOWP_BAR if asserted else LOWP_WORST[lowp])
     # the two-tier path is the c -> infinity limit: more FP32 tiles never hurts much
     two = small_ds.loglik(theta, SMALL.tile, 2)
-    err2 = abs(two["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n)
-    assert err2 <= max(err, 1e-6)
+    assert rel(two["loglik"], want["loglik"]) <= max(err, 1e-6)
 
 
 @pytest.mark.parametrize("lowp", ["fp16", "bf16"])
