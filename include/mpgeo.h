@@ -91,15 +91,16 @@ typedef enum {
  * a one-shot plan flag); kriging sites use the same convention. */
 #define MPGEO_DIST_GCD    16u
 /* Batched evaluation (mpgeo_batch_loglik) as one persistent kernel over a device task queue
- * instead of per-problem launch sequences: every problem is cut into 128 x 128 FP64 tiles and
- * factored left-looking, one task per lower tile (covariance block, the products with its
- * earlier panels, then the diagonal Cholesky fused with the forward solve or the panel solve
- * through the diagonal inverse), workgroups taking tasks in dependency order from an atomic
- * counter and waiting on per-tile done flags.  For small problems, whose launch sequences
- * leave the device idle.  Needs an all-FP64 plan (band64 = -1, band32 = -1, lowp = 0,
- * band0 = -1, dist64 = 0), tile 128 or 0 (then 128), and n <= 16384 per problem; otherwise
- * MPGEO_E_UNSUPPORTED.  Results agree with mpgeo_loglik to rounding (the products are summed
- * in another order), not bit for bit. */
+ * instead of per-problem launch sequences: every problem is cut into 128 x 128 tiles, FP64
+ * within band64 tiles of the diagonal and FP32 beyond (Algorithm 1's map, each problem its own
+ * band with MPGEO_TUNE_BAND), and factored left-looking, one task per lower tile (covariance
+ * block in the tile's precision, the products with its earlier panels in that precision, then
+ * the diagonal Cholesky fused with the forward solve, or the panel solve through the diagonal
+ * inverse), workgroups taking tasks in dependency order from an atomic counter and waiting on
+ * per-tile done flags.  For small problems, whose launch sequences leave the device idle.
+ * Needs a two-tier plan (band64 >= -1, band32 = -1, lowp = 0, band0 = -1, dist64 = 0), tile
+ * 128 or 0 (then 128), and n <= 16384 per problem; otherwise MPGEO_E_UNSUPPORTED.  Results agree
+ * with mpgeo_loglik to rounding (the products are summed in another order), not bit for bit. */
 #define MPGEO_BATCH_QUEUE 32u
 /* Escalation on loss of positive definiteness.  With too much of the matrix in reduced
  * precision the factorization can meet a non-positive pivot even though Sigma itself is
@@ -114,6 +115,16 @@ typedef enum {
  * mpgeo_dataset_simulate and mpgeo_factor_dense; mpgeo_batch_loglik and the serving loop
  * return MPGEO_E_UNSUPPORTED with it. */
 #define MPGEO_ESCALATE    64u
+/* Band tuning for batched evaluation (mpgeo_batch_loglik; the choice of the precision map that
+ * Section VIII-C-1 makes by hand for each size).  plan.band64 is then ignored: for each class
+ * of problems (half-octave of n, tile, path) the first problem is evaluated all-FP64 and with
+ * FP64 bands 0, 1, 2, 4, 8 tiles (FP32 beyond), and the narrowest band whose log-likelihood
+ * is within 1e-6 (relative) of the all-FP64 one is used for the whole class (all-FP64 when
+ * none is).  The choice depends only on that problem's deterministic results and is kept in
+ * the context for later batches; mpgeo_result.band64 reports it per problem.  With plan.tile
+ * = 0 the tile is tuned first, on the all-FP64 plan.  Works with and without
+ * MPGEO_BATCH_QUEUE; other entry points ignore the flag. */
+#define MPGEO_TUNE_BAND  128u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
  * (smoothness); all must be finite and > 0. */
@@ -130,7 +141,8 @@ typedef struct {
  *          -1: FP32 from band64 + 1 to the edge of the matrix (two tiers).
  *  lowp:   0 with band32 = -1; 1 (FP16) or 2 (BF16) with band32 >= 0.
  *  flags:  MPGEO_ORDER_MORTON | MPGEO_INPUT_DEVICE | MPGEO_TIMING | MPGEO_PROFILE |
- *          MPGEO_DIST_GCD | MPGEO_BATCH_QUEUE (mpgeo_batch_loglik only).
+ *          MPGEO_DIST_GCD | MPGEO_BATCH_QUEUE, MPGEO_TUNE_BAND (mpgeo_batch_loglik only) |
+ *          MPGEO_ESCALATE.
  *  band0:  z >= 0: tiles with i - j > z are dropped (taken as zero, never stored, generated or
  *          updated: the diagonal-super-tile approximation the paper compares against, which
  *          factors the block-banded matrix exactly because the Cholesky factor of a matrix of

@@ -430,6 +430,7 @@ struct mpgeo_ctx {
     std::vector<mpgeo_ctx *> lanes;
     std::vector<mpgeo_dataset *> lane_ds;
     std::map<std::string, int> tuned_tile;
+    std::map<std::string, int> tuned_band;    // MPGEO_TUNE_BAND: FP64 band per class of n and tile
     DevBuf batch_res;                         // per-instance {loglik, logdet, quad, info}
     // the persistent task-queue batch: inputs, tiles, vectors and control words
     DevBuf q_in_locs, q_in_z, q_locs, q_vec, q_tiles, q_linv, q_parts, q_flags, q_ctrl,
@@ -1864,47 +1865,152 @@ static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, d
     return MPGEO_OK;
 }
 
+// Candidate FP64 bands of the band tuner (in tiles), narrowest first, and its bar: the relative
+// log-likelihood difference to the all-FP64 evaluation of the class's first problem (a tenth of
+// the mixed paths' 1e-5, a margin for the other problems of the class).
+static const int kTuneBands[] = {0, 1, 2, 4, 8};
+constexpr double kTuneBandBar = 1e-6;
+
+static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
+                       mpgeo_result *out, int32_t *tiles, char *arena, size_t arena_bytes,
+                       const int32_t *bands);
+
+// FP64 band (MPGEO_TUNE_BAND) for an instance evaluated with tile `tile`: the narrowest
+// candidate whose log-likelihood on the first instance of its class (half-octave of n, tile,
+// plan flags) is within kTuneBandBar of the all-FP64 one, else all-FP64 (-1).  The choice
+// depends only on that instance's results, which the kernels make deterministic; it is kept in
+// the context for later batches.  Probes run through the queue (queue) or a lane.
+static int batch_band(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, int tile, bool queue,
+                      double *scratch, int *band_out) {
+    const int bucket = (int)std::floor(2.0 * std::log2((double)in.n));
+    const std::string key = std::to_string(bucket) + "/" + std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
+                            std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
+    auto it = ctx->tuned_band.find(key);
+    if (it != ctx->tuned_band.end()) {
+        *band_out = it->second;
+        return MPGEO_OK;
+    }
+    const int64_t p = (in.n + tile - 1) / tile;
+    std::vector<int> cand{-1};
+    for (int b : kTuneBands)
+        if (b < p - 1) cand.push_back(b);
+    std::vector<double> ll(cand.size(), 0.0);
+    std::vector<int> ok(cand.size(), 0);
+    for (size_t c = 0; c < cand.size(); ++c) {
+        mpgeo_plan q = pl;
+        q.tile = tile;
+        q.band64 = cand[c];
+        q.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
+        mpgeo_result r{};
+        int st;
+        if (queue) {
+            const int32_t b = cand[c];
+            st = batch_queue(ctx, 1, &in, q, &r, nullptr, nullptr, 0, &b);
+        } else {
+            st = batch_enqueue(ctx->lane_ds[0], in, q, scratch);
+            batch_sync(ctx);
+            if (st == MPGEO_OK) {
+                double host[4];
+                MPGEO_HIP(hipMemcpy(host, scratch, sizeof(host), hipMemcpyDeviceToHost));
+                unsigned long long info;
+                std::memcpy(&info, host + 3, sizeof(info));
+                r.loglik = host[0];
+                st = info == ~0ull ? MPGEO_OK : MPGEO_E_NOT_SPD;
+            }
+        }
+        if (st != MPGEO_OK && st != MPGEO_E_NOT_SPD) return st;
+        ok[c] = st == MPGEO_OK;
+        ll[c] = r.loglik;
+    }
+    int best = -1;
+    if (ok[0])
+        for (size_t c = 1; c < cand.size(); ++c)
+            if (ok[c] && std::fabs(ll[c] - ll[0]) <= kTuneBandBar * std::fabs(ll[0])) {
+                best = cand[c];
+                break;
+            }
+    ctx->tuned_band[key] = best;
+    *band_out = best;
+    return MPGEO_OK;
+}
+
 // The persistent task-queue batch (MPGEO_BATCH_QUEUE): problems are packed into shared buffers
 // in groups that fit in device memory, each group one ordering launch and one queue launch.
+// The work buffers of a group come either from the context's growing buffers or from a fixed
+// device array of `arena_bytes` at `arena` (nothing is
+// allocated; every group must fit in the array, and what must start at zero is cleared by a
+// fill kernel).
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
-                       mpgeo_result *out, int32_t *tiles) {
+                       mpgeo_result *out, int32_t *tiles, char *arena, size_t arena_bytes,
+                       const int32_t *bands) {
     const int64_t te = (int64_t)kQueueTile * kQueueTile;
+    auto p_of = [&](int64_t q) { return (inst[q].n + kQueueTile - 1) / kQueueTile; };
     auto tiles_of = [&](int64_t q) {
-        const int64_t p = (inst[q].n + kQueueTile - 1) / kQueueTile;
+        const int64_t p = p_of(q);
         return p * (p + 1) / 2;
     };
-    size_t free_b = 0, total_b = 0;
-    MPGEO_HIP(hipMemGetInfo(&free_b, &total_b));
-    // tiles dominate: keep a group's tiles within half of the free memory (the buffers of an
-    // earlier, larger group are reused)
-    size_t budget = std::max<size_t>(free_b / 2 + ctx->q_tiles.bytes, (size_t)te * 8 * 64);
-    if (ctx->hbm_budget > 0) {   // the context's cap: every problem must fit in it alone
-        budget = std::min(budget, ctx->hbm_budget);
+    // FP64 band of problem q in tiles: the plan's (or the tuned one), capped at p (every tile)
+    auto band_of = [&](int64_t q) {
+        const int64_t p = p_of(q);
+        const int32_t b = bands ? bands[q] : plan.band64;
+        return (int32_t)((b < 0 || b > p) ? p : b);
+    };
+    // bytes of the tiles of problem q: FP64 tiles 8 bytes per entry, FP32 tiles 4
+    auto tile_bytes = [&](int64_t q) { return (size_t)queue_tile_units(p_of(q), 0, band_of(q)) * sizeof(float); };
+    // bytes of every work buffer problem q adds to a group (the fixed array's packing rule)
+    auto prob_bytes = [&](int64_t q) {
+        const int64_t n = inst[q].n, p = p_of(q), tl = tiles_of(q);
+        return (size_t)n * 5 * sizeof(double) +                    // packed inputs, ordered sites
+               (size_t)3 * p * kQueueTile * sizeof(double) +        // z, r, y (padded)
+               tile_bytes(q) + (size_t)p * te * sizeof(double) +     // tiles, diagonal inverses
+               (size_t)2 * p * sizeof(double) +                     // logdet / quad parts
+               (size_t)tl * (sizeof(int) + sizeof(BatchTask)) +     // done flags, tasks
+               sizeof(BatchInst) + 3 * sizeof(double) + sizeof(unsigned long long);
+    };
+    constexpr size_t kSlack = 13 * 256 + 2 * sizeof(int);            // alignment of 13 buffers, control
+    const bool fixed = arena != nullptr;
+    size_t budget = 0;
+    if (fixed) {
         for (int64_t q = 0; q < count; ++q)
-            if ((size_t)tiles_of(q) * te * 8 > budget) return MPGEO_E_NOMEM;
+            if (prob_bytes(q) + kSlack > arena_bytes) return MPGEO_E_ARG;   // beyond the array
+    } else {
+        size_t free_b = 0, total_b = 0;
+        MPGEO_HIP(hipMemGetInfo(&free_b, &total_b));
+        // tiles dominate: keep a group's tiles within half of the free memory (the buffers of an
+        // earlier, larger group are reused)
+        budget = std::max<size_t>(free_b / 2 + ctx->q_tiles.bytes, (size_t)te * 8 * 64);
+        if (ctx->hbm_budget > 0) {   // the context's cap: every problem must fit in it alone
+            budget = std::min(budget, ctx->hbm_budget);
+            for (int64_t q = 0; q < count; ++q)
+                if (tile_bytes(q) > budget) return MPGEO_E_NOMEM;
+        }
     }
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
-        (void)hipGetLastError();
-        cus = 256;
-    }
+    const int cus = ctx->cus > 0 ? ctx->cus : 256;
     hipStream_t s = ctx->stream;
     int status = MPGEO_OK;
     for (int64_t g0 = 0; g0 < count;) {
         // ---- group [g0, g1) and its layout -------------------------------------------------------
-        int64_t g1 = g0, ntiles = 0;
-        while (g1 < count && (g1 == g0 || (size_t)(ntiles + tiles_of(g1)) * te * 8 <= budget)) ntiles += tiles_of(g1++);
+        int64_t g1 = g0;
+        size_t gbytes = kSlack, tbytes = 0;
+        if (fixed) {
+            while (g1 < count && gbytes + prob_bytes(g1) <= arena_bytes) gbytes += prob_bytes(g1++);
+        } else {
+            while (g1 < count && (g1 == g0 || tbytes + tile_bytes(g1) <= budget)) tbytes += tile_bytes(g1++);
+        }
         const int64_t gc = g1 - g0;
         std::vector<BatchInst> bi((size_t)gc);
-        int64_t pts = 0, tl = 0, lv = 0, vec = 0, prt = 0;
+        int64_t pts = 0, tl = 0, lv = 0, vec = 0, prt = 0, units = 0;
         int max_n = 1, max_p = 1;
         for (int64_t q = 0; q < gc; ++q) {
             const mpgeo_instance &x = inst[g0 + q];
             BatchInst &b = bi[(size_t)q];
             b.n = x.n;
             b.p = (int32_t)((x.n + kQueueTile - 1) / kQueueTile);
+            b.band = band_of(g0 + q);
             b.in0 = pts;
-            b.tile0 = tl;
+            b.tile0 = units;
             b.flag0 = tl;
             b.linv0 = lv;
             b.vec0 = vec;
@@ -1913,6 +2019,7 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
             b.mp.gcd = (plan.flags & MPGEO_DIST_GCD) ? 1 : 0;
             pts += x.n;
             tl += (int64_t)b.p * (b.p + 1) / 2;
+            units += queue_tile_units(b.p, 0, b.band);
             lv += b.p;
             vec += (int64_t)b.p * kQueueTile;
             prt += 2 * (int64_t)b.p;
@@ -1934,48 +2041,70 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
             std::memcpy(hl.data() + 2 * bi[(size_t)q].in0, x.locs, (size_t)x.n * 2 * sizeof(double));
             std::memcpy(hz.data() + bi[(size_t)q].in0, x.z, (size_t)x.n * sizeof(double));
         }
-        // ---- buffers (grow only; growing waits for the device) ------------------------------
-        MPGEO_TRY(ctx->q_in_locs.ensure(hl.size() * sizeof(double)));
-        MPGEO_TRY(ctx->q_in_z.ensure(hz.size() * sizeof(double)));
-        MPGEO_TRY(ctx->q_locs.ensure(hl.size() * sizeof(double)));
-        MPGEO_TRY(ctx->q_vec.ensure(3 * (size_t)vec * sizeof(double)));
-        MPGEO_TRY(ctx->q_tiles.ensure((size_t)tl * te * sizeof(double)));
-        MPGEO_TRY(ctx->q_linv.ensure((size_t)lv * te * sizeof(double)));
-        MPGEO_TRY(ctx->q_parts.ensure((size_t)prt * sizeof(double)));
-        MPGEO_TRY(ctx->q_flags.ensure((size_t)tl * sizeof(int)));
-        MPGEO_TRY(ctx->q_ctrl.ensure(2 * sizeof(int)));
-        MPGEO_TRY(ctx->q_insts.ensure((size_t)gc * sizeof(BatchInst)));
-        MPGEO_TRY(ctx->q_tasks.ensure(tasks.size() * sizeof(BatchTask)));
-        MPGEO_TRY(ctx->q_res.ensure((size_t)gc * 3 * sizeof(double)));
-        MPGEO_TRY(ctx->q_info.ensure((size_t)gc * sizeof(unsigned long long)));
-        MPGEO_HIP(hipMemcpyAsync(ctx->q_in_locs.ptr, hl.data(), hl.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemcpyAsync(ctx->q_in_z.ptr, hz.data(), hz.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemcpyAsync(ctx->q_insts.ptr, bi.data(), bi.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemcpyAsync(ctx->q_tasks.ptr, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemsetAsync(ctx->q_flags.ptr, 0, (size_t)tl * sizeof(int), s));
-        MPGEO_HIP(hipMemsetAsync(ctx->q_ctrl.ptr, 0, 2 * sizeof(int), s));
-        MPGEO_HIP(hipMemsetAsync(ctx->q_info.ptr, 0xFF, (size_t)gc * sizeof(unsigned long long), s));
-        double *vz = ctx->q_vec.as<double>();
-        launch_batch_order(ctx->q_insts.as<BatchInst>(), gc, max_n, ctx->q_in_locs.as<double>(),
-                           ctx->q_in_z.as<double>(), ctx->q_locs.as<double>(), vz,
+        // ---- buffers -------------------------------------------------------------------------------
+        const size_t sz[13] = {hl.size() * sizeof(double), hz.size() * sizeof(double), hl.size() * sizeof(double),
+                               3 * (size_t)vec * sizeof(double), (size_t)units * sizeof(float),
+                               (size_t)lv * te * sizeof(double), (size_t)prt * sizeof(double),
+                               (size_t)tl * sizeof(int), 2 * sizeof(int), (size_t)gc * sizeof(BatchInst),
+                               tasks.size() * sizeof(BatchTask), (size_t)gc * 3 * sizeof(double),
+                               (size_t)gc * sizeof(unsigned long long)};
+        void *ptr[13];
+        if (fixed) {   // carved from the fixed array, 256-byte aligned
+            size_t off = 0;
+            for (int q = 0; q < 13; ++q) {
+                ptr[q] = arena + off;
+                off += align256(sz[q]);
+            }
+            if (off > arena_bytes) return MPGEO_E_ARG;   // (the packing rule keeps it inside)
+        } else {   // grow only; growing waits for the device
+            DevBuf *bufs[13] = {&ctx->q_in_locs, &ctx->q_in_z, &ctx->q_locs, &ctx->q_vec, &ctx->q_tiles,
+                                &ctx->q_linv, &ctx->q_parts, &ctx->q_flags, &ctx->q_ctrl, &ctx->q_insts,
+                                &ctx->q_tasks, &ctx->q_res, &ctx->q_info};
+            for (int q = 0; q < 13; ++q) {
+                MPGEO_TRY(bufs[q]->ensure(sz[q]));
+                ptr[q] = bufs[q]->ptr;
+            }
+        }
+        double *in_locs = static_cast<double *>(ptr[0]), *in_z = static_cast<double *>(ptr[1]);
+        double *q_locs = static_cast<double *>(ptr[2]), *q_vec = static_cast<double *>(ptr[3]);
+        int *q_flags = static_cast<int *>(ptr[7]), *q_ctrl = static_cast<int *>(ptr[8]);
+        BatchInst *q_insts = static_cast<BatchInst *>(ptr[9]);
+        BatchTask *q_tasks = static_cast<BatchTask *>(ptr[10]);
+        double *q_res = static_cast<double *>(ptr[11]);
+        unsigned long long *q_info = static_cast<unsigned long long *>(ptr[12]);
+        MPGEO_HIP(hipMemcpyAsync(in_locs, hl.data(), sz[0], hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(in_z, hz.data(), sz[1], hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(q_insts, bi.data(), sz[9], hipMemcpyHostToDevice, s));
+        MPGEO_HIP(hipMemcpyAsync(q_tasks, tasks.data(), sz[10], hipMemcpyHostToDevice, s));
+        if (fixed) {   // the array keeps the previous call's contents: clear flags, counter, info
+            launch_fill_u32(reinterpret_cast<uint32_t *>(q_flags), 0u, (size_t)tl, s);
+            launch_fill_u32(reinterpret_cast<uint32_t *>(q_ctrl), 0u, 2, s);
+            launch_fill_u32(reinterpret_cast<uint32_t *>(q_info), ~0u, 2 * (size_t)gc, s);
+            MPGEO_HIP(hipGetLastError());
+        } else {
+            MPGEO_HIP(hipMemsetAsync(q_flags, 0, sz[7], s));
+            MPGEO_HIP(hipMemsetAsync(q_ctrl, 0, sz[8], s));
+            MPGEO_HIP(hipMemsetAsync(q_info, 0xFF, sz[12], s));
+        }
+        launch_batch_order(q_insts, gc, max_n, in_locs, in_z, q_locs, q_vec,
                            true, (plan.flags & MPGEO_DIST_GCD) != 0, s);   // always ordered, as a lane would
         MPGEO_HIP(hipGetLastError());
         QueueArgs qa{};
-        qa.tasks = ctx->q_tasks.as<BatchTask>();
+        qa.tasks = q_tasks;
         qa.ntasks = (int64_t)tasks.size();
-        qa.insts = ctx->q_insts.as<BatchInst>();
-        qa.locs = ctx->q_locs.as<double>();
-        qa.z = vz;
-        qa.r = vz + vec;
-        qa.y = vz + 2 * vec;
-        qa.tiles = ctx->q_tiles.as<double>();
-        qa.linv = ctx->q_linv.as<double>();
-        qa.parts = ctx->q_parts.as<double>();
-        qa.flags = ctx->q_flags.as<int>();
-        qa.head = ctx->q_ctrl.as<unsigned>();
-        qa.abort_flag = ctx->q_ctrl.as<int>() + 1;
-        qa.info = ctx->q_info.as<unsigned long long>();
-        qa.result = ctx->q_res.as<double>();
+        qa.insts = q_insts;
+        qa.locs = q_locs;
+        qa.z = q_vec;
+        qa.r = q_vec + vec;
+        qa.y = q_vec + 2 * vec;
+        qa.tiles = static_cast<float *>(ptr[4]);
+        qa.linv = static_cast<double *>(ptr[5]);
+        qa.parts = static_cast<double *>(ptr[6]);
+        qa.flags = q_flags;
+        qa.head = reinterpret_cast<unsigned *>(q_ctrl);
+        qa.abort_flag = q_ctrl + 1;
+        qa.info = q_info;
+        qa.result = q_res;
         qa.profile = (plan.flags & MPGEO_PROFILE) ? 1 : 0;
         qa.spin_limit = 8 << 20;   // about 2 s of sleeps per wait
         const int wgs = (int)std::min<int64_t>((int64_t)tasks.size(), (int64_t)cus);
@@ -1984,10 +2113,10 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         std::vector<double> res((size_t)gc * 3);
         std::vector<unsigned long long> info((size_t)gc);
         int ctrl[2] = {0, 0};
-        MPGEO_HIP(hipMemcpyAsync(res.data(), ctx->q_res.ptr, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        MPGEO_HIP(hipMemcpyAsync(info.data(), ctx->q_info.ptr, info.size() * sizeof(unsigned long long),
+        MPGEO_HIP(hipMemcpyAsync(res.data(), q_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipMemcpyAsync(info.data(), q_info, info.size() * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, s));
-        MPGEO_HIP(hipMemcpyAsync(ctrl, ctx->q_ctrl.ptr, sizeof(ctrl), hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipMemcpyAsync(ctrl, q_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, s));
         MPGEO_HIP(hipStreamSynchronize(s));
         if (ctrl[1] != 0) return MPGEO_E_DEVICE;   // a wait timed out
         for (int64_t q = 0; q < gc; ++q) {
@@ -1997,6 +2126,8 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
             o.logdet = res[(size_t)q * 3 + 1];
             o.quad = res[(size_t)q * 3 + 2];
             o.info = (info[(size_t)q] == ~0ull) ? -1 : (int64_t)info[(size_t)q];
+            o.band64 = bi[(size_t)q].band >= bi[(size_t)q].p - 1 ? -1 : bi[(size_t)q].band;
+            o.band32 = o.band0 = -1;
             if (o.info >= 0) status = MPGEO_E_NOT_SPD;
             if (tiles) tiles[g0 + q] = kQueueTile;
         }
@@ -2005,8 +2136,22 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
     return status;
 }
 
-int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
-                       mpgeo_result *out, int32_t *tiles) {
+// Arguments of the queued batch: a two-tier plan (FP64 band, FP32 beyond; or all FP64) at
+// tile 128, each problem at most kQueueMaxN sites.
+static int queue_plan_ok(const mpgeo_plan &plan) {
+    const bool two_tier = plan.band32 == -1 && plan.lowp == 0 && plan.band0 == -1 && plan.dist64 == 0.0 &&
+                          (plan.tile == 0 || plan.tile == kQueueTile);
+    return two_tier ? MPGEO_OK : MPGEO_E_UNSUPPORTED;
+}
+static int queue_sizes_ok(int64_t count, const mpgeo_instance *inst) {
+    for (int64_t i = 0; i < count; ++i)
+        if (inst[i].n > kQueueMaxN) return MPGEO_E_UNSUPPORTED;
+    return MPGEO_OK;
+}
+
+// The batch arguments every path checks: instances, theta, finite host inputs, the plan.
+static int check_batch_args(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
+                            mpgeo_result *out) {
     if (!ctx || count < 0 || (count > 0 && (!inst || !out))) return MPGEO_E_ARG;
     if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
     if (plan.flags & MPGEO_ESCALATE) return MPGEO_E_UNSUPPORTED;
@@ -2021,16 +2166,29 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
             return MPGEO_E_ARG;
         out[i].info = -1;
     }
+    return MPGEO_OK;
+}
+
+int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
+                       mpgeo_result *out, int32_t *tiles) {
+    MPGEO_TRY(check_batch_args(ctx, count, inst, plan, out));
+    const bool tune_band = (plan.flags & MPGEO_TUNE_BAND) != 0;
     if (plan.flags & MPGEO_BATCH_QUEUE) {
-        const bool fp64 = plan.band64 == -1 && plan.band32 == -1 && plan.lowp == 0 && plan.band0 == -1 &&
-                          plan.dist64 == 0.0 && (plan.tile == 0 || plan.tile == kQueueTile);
-        if (!fp64) return MPGEO_E_UNSUPPORTED;
-        for (int64_t i = 0; i < count; ++i)
-            if (inst[i].n > kQueueMaxN) return MPGEO_E_UNSUPPORTED;
+        MPGEO_TRY(queue_plan_ok(plan));
+        MPGEO_TRY(queue_sizes_ok(count, inst));
         if (count == 0) return MPGEO_OK;
         Device dev(ctx->device);
         if (!dev.ok) return MPGEO_E_DEVICE;
-        return batch_queue(ctx, count, inst, plan, out, tiles);
+        std::vector<int32_t> bands;
+        if (tune_band) {
+            bands.resize((size_t)count);
+            for (int64_t i = 0; i < count; ++i) {
+                int b = -1;
+                MPGEO_TRY(batch_band(ctx, inst[i], plan, kQueueTile, true, nullptr, &b));
+                bands[(size_t)i] = b;
+            }
+        }
+        return batch_queue(ctx, count, inst, plan, out, tiles, nullptr, 0, tune_band ? bands.data() : nullptr);
     }
     if (count == 0) return MPGEO_OK;
     Device dev(ctx->device);
@@ -2041,9 +2199,16 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
     MPGEO_TRY(batch_lanes(ctx, nlanes));
     MPGEO_TRY(ctx->batch_res.ensure((size_t)(count + 1) * 4 * sizeof(double)));
     double *res = ctx->batch_res.as<double>();
-    std::vector<int> tile((size_t)count);
+    std::vector<int> tile((size_t)count), band((size_t)count, plan.band64);
     for (int64_t i = 0; i < count; ++i) {
-        const int st = batch_tile(ctx, inst[i], plan, res + 4 * count, &tile[(size_t)i]);
+        mpgeo_plan tp = plan;
+        if (tune_band) {   // the tile is timed on the all-FP64 plan, the band then chosen for it
+            tp.band64 = -1;
+            tp.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
+        }
+        int st = batch_tile(ctx, inst[i], tp, res + 4 * count, &tile[(size_t)i]);
+        if (st == MPGEO_OK && tune_band)
+            st = batch_band(ctx, inst[i], plan, tile[(size_t)i], false, res + 4 * count, &band[(size_t)i]);
         if (st != MPGEO_OK) {
             batch_sync(ctx);
             return st;
@@ -2057,6 +2222,8 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         const int64_t i = order[(size_t)q];
         mpgeo_plan pl = plan;
         pl.tile = tile[(size_t)i];
+        pl.band64 = band[(size_t)i];
+        pl.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
         status = batch_enqueue(ctx->lane_ds[(size_t)(q % nlanes)], inst[i], pl, res + 4 * i);
     }
     batch_sync(ctx);
@@ -2072,6 +2239,9 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         out[i].logdet = r[1];
         out[i].quad = r[2];
         out[i].info = (info == ~0ull) ? -1 : (int64_t)info;
+        out[i].band64 = band[(size_t)i];
+        out[i].band32 = plan.band32;
+        out[i].band0 = plan.band0;
         if (out[i].info >= 0) status = MPGEO_E_NOT_SPD;
         if (tiles) tiles[i] = tile[(size_t)i];
     }

@@ -182,17 +182,32 @@ void launch_column_var(const double *c, int64_t ldc, int64_t rows, int64_t m, do
 constexpr int kQueueTile = 128;        // tile size of the queue path
 constexpr int kQueueMaxN = 16384;      // largest problem (its sort runs in one workgroup's LDS)
 
+// Tiles of a queued problem are packed in row-major lower order, a tile (i, j) with
+// i - j <= band in FP64 (2 kQueueTile^2 four-byte units), the others in FP32 (kQueueTile^2
+// units).  Offset of tile (i, j) in four-byte units: FP64 tiles before it (rows r < i hold
+// min(r, band) + 1 each; row i those with j' >= i - band) count twice.
+__host__ __device__ inline int64_t queue_fp64_before(int64_t i, int64_t j, int64_t band) {
+    const int64_t rows = (i <= band + 1) ? i * (i + 1) / 2
+                                         : (band + 1) * (band + 2) / 2 + (i - band - 1) * (band + 1);
+    const int64_t first = i - band > 0 ? i - band : 0;
+    return rows + (j > first ? j - first : 0);
+}
+__host__ __device__ inline int64_t queue_tile_units(int64_t i, int64_t j, int64_t band) {
+    const int64_t te = (int64_t)kQueueTile * kQueueTile;
+    return (tri_index(i, j) + queue_fp64_before(i, j, band)) * te;
+}
+
 // One problem of a queued batch; all offsets are in elements of the shared buffers.
 struct BatchInst {
     int64_t n;
     int64_t in0;     // first site / datum in the packed inputs and ordered sites (sites 2 in0)
-    int64_t tile0;   // tile (i, j) at tile0 + tri_index(i, j), kQueueTile^2 doubles each
+    int64_t tile0;   // tile (i, j) at tile0 + queue_tile_units(i, j, band) four-byte units
     int64_t linv0;   // L_jj^-1 at linv0 + j
     int64_t vec0;    // padded vectors z, r, y: element e at vec0 + e (p * kQueueTile long)
     int64_t flag0;   // done flag of tile (i, j) at flag0 + tri_index(i, j)
     int64_t part0;   // logdet parts at part0 + j, quadratic-form parts at part0 + p + j
     int32_t p;
-    int32_t pad_;
+    int32_t band;    // tile (i, j) is FP64 iff i - j <= band (band >= p - 1: every tile)
     MaternParams mp;
 };
 struct BatchTask {
@@ -204,7 +219,8 @@ struct QueueArgs {
     const BatchInst *insts;
     const double *locs;        // ordered sites
     const double *z;           // ordered, padded data
-    double *tiles, *linv, *r, *y, *parts;
+    float *tiles;              // four-byte units (see queue_tile_units)
+    double *linv, *r, *y, *parts;
     int *flags;                // zero on entry
     unsigned *head;            // zero on entry
     int *abort_flag;           // zero on entry; non-zero on exit: a wait timed out
@@ -218,5 +234,7 @@ void launch_batch_order(const BatchInst *insts, int64_t count, int max_n, const 
                         const double *z_in, double *locs, double *zpad, bool order, bool lonlat,
                         hipStream_t stream);
 void launch_batch_queue(const QueueArgs &args, int workgroups, hipStream_t stream);
+// p[0 .. count) = value (clearing flags and counters without a memset node)
+void launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream);
 
 }  // namespace mpgeo

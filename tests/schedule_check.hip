@@ -146,8 +146,32 @@ static int check_escalation() {
     return bad;
 }
 
+// Tile offsets of the queued batch's mixed-precision layout: every tile (i, j) of a problem of
+// p tile rows starts where the one before it (row-major lower order) ends, FP64 tiles taking
+// 2 kQueueTile^2 four-byte units and FP32 tiles kQueueTile^2, the last ending at the total.
+static int check_queue_offsets() {
+    int bad = 0;
+    const int64_t te = (int64_t)kQueueTile * kQueueTile;
+    for (int p = 1; p <= 40; ++p)
+        for (int band = 0; band <= p + 1; ++band) {
+            int64_t expect = 0;
+            for (int i = 0; i < p; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    if (queue_tile_units(i, j, band) != expect) {
+                        if (bad++ < 5) std::printf("  queue offset p %d band %d tile %d,%d\n", p, band, i, j);
+                    }
+                    expect += (i - j <= band ? 2 : 1) * te;
+                }
+            if (queue_tile_units(p, 0, band) != expect) {
+                if (bad++ < 5) std::printf("  queue total p %d band %d\n", p, band);
+            }
+        }
+    std::printf("queue tile offsets: %s\n", bad ? "FAILED" : "ok");
+    return bad;
+}
+
 int main() {
-    int bad = check_escalation();
+    int bad = check_escalation() + check_queue_offsets();
     bad += check(99856, 512, 2, 8, -1, 64);     // the n ~ 1e5 three-tier plan on 256 compute units
     bad += check(99856, 512, 2, 8, -1, 32);
     bad += check(99856, 512, 2, 8, -1, 0);      // wave size unknown: no filling

@@ -14,7 +14,7 @@ def run_bench(*args):
                           capture_output=True, text=True, timeout=120)
 
 
-@pytest.mark.parametrize("mode", [[], ["--batch", "4"], ["--serve", "2"], ["--sweep"]])
+@pytest.mark.parametrize("mode", [[], ["--batch", "4"], ["--serve", "2"], ["--sweep"], ["--small"]])
 def test_more_than_one_gpu_is_refused_in_every_mode(mode):
     res = run_bench("--gpus", "2", *mode)
     assert res.returncode == 2
@@ -25,5 +25,5 @@ def test_more_than_one_gpu_is_refused_in_every_mode(mode):
 def test_help_lists_the_modes():
     res = run_bench("--help")
     assert res.returncode == 0
-    for flag in ("--steps", "--warmup", "--gpus", "--batch", "--serve", "--sweep", "--lowp"):
+    for flag in ("--steps", "--warmup", "--gpus", "--batch", "--serve", "--sweep", "--lowp", "--small", "--legs"):
         assert flag in res.stdout

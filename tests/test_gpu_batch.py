@@ -145,9 +145,64 @@ def test_queue_profile_and_great_circle(lib, ctx):
     assert st == 0 and _rel(res[0]["loglik"], oracle.loglik(ll, zz, th, metric="gcd")["loglik"]) <= 1e-10
 
 
+@pytest.mark.parametrize("band", [0, 1, 3])
+def test_queue_two_tier_plans(lib, ctx, problems, band):
+    # FP64 within `band` tiles of 128, FP32 beyond, in the persistent queue: within the band
+    # path's bar of the oracle, close to the same plan through the lanes (the FP32 products are
+    # summed in another order), deterministic, and reported with its band
+    st, res, _ = ctx.batch_loglik(problems, tile=128, band64=band, queue=True)
+    assert st == 0
+    _, lanes, _ = ctx.batch_loglik(problems, tile=128, band64=band)
+    worst = 0.0
+    for (locs, z, theta), r, l in zip(problems, res, lanes):
+        want = oracle.loglik(locs, z, theta)["loglik"]
+        err = abs(r["loglik"] - want) / abs(want)
+        worst = max(worst, err)
+        assert err <= 1e-5, (len(z), theta, err)
+        assert abs(r["loglik"] - l["loglik"]) / abs(l["loglik"]) <= 1e-6
+        p = -(-len(z) // 128)
+        assert r["band64"] == (band if band < p - 1 else -1)
+    print(f"queue band {band}: max |dl|/|l| vs oracle = {worst:.2e}")
+    st2, res2, _ = ctx.batch_loglik(problems, tile=128, band64=band, queue=True)
+    assert [r["loglik"] for r in res2] == [r["loglik"] for r in res]
+
+
+def test_band_tuner(lib, problems):
+    # MPGEO_TUNE_BAND: one band per class of n (narrowest within 1e-6 of all-FP64 on the class's
+    # first problem), the same for the queue and the lanes at tile 128, deterministic across
+    # contexts, every result within the band path's bar of the oracle
+    c1, c2 = lib.Context(0), lib.Context(0)
+    try:
+        st, res, _ = c1.batch_loglik(problems, tile=128, queue=True, tune_band=True)
+        assert st == 0
+        st2, res2, _ = c2.batch_loglik(problems, tile=128, queue=True, tune_band=True)
+        assert [r["band64"] for r in res2] == [r["band64"] for r in res]
+        assert [r["loglik"] for r in res2] == [r["loglik"] for r in res]
+        classes = {}
+        for (locs, z, theta), r in zip(problems, res):
+            classes.setdefault(int(np.floor(2 * np.log2(len(z)))), set()).add(r["band64"])
+            want = oracle.loglik(locs, z, theta)["loglik"]
+            assert abs(r["loglik"] - want) / abs(want) <= 1e-5
+        assert all(len(b) == 1 for b in classes.values())
+        print("tuned bands per class:", {k: sorted(v) for k, v in classes.items()})
+        # the lanes probe their classes themselves (their products are summed in another order,
+        # so a band at the edge of the bar may come out differently)
+        st, lanes, tiles = c1.batch_loglik(problems, tile=128, tune_band=True)
+        assert st == 0 and tiles == [128] * len(problems)
+        lane_classes = {}
+        for (locs, z, theta), r in zip(problems, lanes):
+            lane_classes.setdefault(int(np.floor(2 * np.log2(len(z)))), set()).add(r["band64"])
+            want = oracle.loglik(locs, z, theta)["loglik"]
+            assert abs(r["loglik"] - want) / abs(want) <= 1e-5
+        assert all(len(b) == 1 for b in lane_classes.values())
+    finally:
+        c1.close()
+        c2.close()
+
+
 def test_queue_rejects_what_it_does_not_cover(lib, ctx, problems):
     assert ctx.batch_loglik([], tile=0, queue=True)[0] == 0
-    for kw in (dict(band64=1), dict(tile=256), dict(band0=2)):
+    for kw in (dict(band64=1, band32=1, lowp="fp16"), dict(tile=256), dict(band0=2)):
         args = dict(tile=0, band64=-1)
         args.update(kw)
         with pytest.raises(lib.MpgeoError):
