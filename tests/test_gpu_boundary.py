@@ -116,12 +116,12 @@ def test_factor_dense_reads_only_the_lower_triangle(lib, ctx):
     z2 = z.copy()
     z2[0] = np.nan
     assert _status(lib, lambda: ctx.factor_dense(a, z2, 64, -1)) == lib.MPGEO_E_ARG
-    # device matrices: the same checks by a reduction on the device (symmetric, so the
-    # row-major tensor is its own column-major transpose)
-    da = torch.from_numpy(np.ascontiguousarray(upper)).to("cuda:0")
+    # device matrices: the same checks by a reduction on the device; the library reads a
+    # column-major matrix, which is the storage of the row-major transpose
+    da = torch.from_numpy(np.ascontiguousarray(upper.T)).to("cuda:0")
     dz = torch.from_numpy(z).to("cuda:0")
     assert ctx.factor_dense(da, dz, 64, -1)["loglik"] == ref["loglik"]
-    dl = torch.from_numpy(np.ascontiguousarray(lower)).to("cuda:0")
+    dl = torch.from_numpy(np.ascontiguousarray(lower.T)).to("cuda:0")
     assert _status(lib, lambda: ctx.factor_dense(dl, dz, 64, -1)) == lib.MPGEO_E_ARG
 
 

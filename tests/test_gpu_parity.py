@@ -568,9 +568,9 @@ def test_dropped_tiles_with_a_16bit_tier(small_ds, lowp, band0):
     sig[np.abs(ti[:, None] - ti[None, :]) > band0] = 0.0
     want = oracle.likelihood.loglik_parts(sig, z[perm])   # positive definite at this range
     got = small_ds.loglik(theta, SMALL.tile, 1, band32=1, lowp=lowp, band0=band0)
-    err = abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), len(z))
-    print(f"dropped tiles beyond {band0}, three tiers {lowp}: |dl|/max(|l|,n) = {err:.3e}")
-    assert err <= LOWP_TOL[lowp]
+    err = rel(got["loglik"], want["loglik"])
+    print(f"dropped tiles beyond {band0}, three tiers {lowp}: |dl|/|l| = {err:.3e}")
+    assert err <= LOWP_BAR
 
 
 # ---- precision map drawn from distances -----------------------------------------------------
@@ -629,8 +629,9 @@ def test_distance_map_matches_oracle(small_ds, dist64, tol):
 def test_distance_map_three_tiers(small_ds, lowp):
     want = small_oracle(SMALL.theta)
     got = small_ds.loglik(SMALL.theta, SMALL.tile, -1, lowp=lowp, dist64=0.05, dist32=0.2)
-    err = abs(got["loglik"] - want["loglik"]) / max(abs(want["loglik"]), SMALL.n)
-    assert err <= LOWP_TOL[lowp], err
+    err = rel(got["loglik"], want["loglik"])
+    print(f"distance map, three tiers {lowp}: |dl|/|l| = {err:.3e}")
+    assert err <= LOWP_BAR, err
 
 
 def test_distance_map_plan_validation(lib, ctx, small_ds):
