@@ -66,7 +66,9 @@ typedef enum {
     MPGEO_E_NOT_SPD = 2,
     MPGEO_E_NOMEM = 3,
     MPGEO_E_DEVICE = 4,
-    MPGEO_E_UNSUPPORTED = 5
+    MPGEO_E_UNSUPPORTED = 5,
+    MPGEO_E_TOO_LARGE = 6   /* a problem's work buffers exceed the fixed array of
+                               mpgeo_batch_loglik_noalloc */
 } mpgeo_status;
 
 /* Flags (mpgeo_plan.flags and dataset flags). */
@@ -316,6 +318,26 @@ typedef struct {
  * MPGEO_E_DEVICE.  Returns MPGEO_E_NOT_SPD if any instance failed (see out[i].info). */
 int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
                        mpgeo_result *out, int32_t *tiles);
+
+/* For callers that cannot allocate device memory (code that must not call hipMalloc or hipFree:
+ * tight serving loops, harnesses that forbid allocation).  The persistent-queue batch of
+ * mpgeo_batch_loglik (as with MPGEO_BATCH_QUEUE, which may be set or not: all-FP64 or
+ * FP64-band/FP32 plans at tile 128 or 0, host inputs) with every work buffer -- packed inputs,
+ * tiles, diagonal inverses, vectors, task list, done flags, results -- carved from one fixed
+ * device array of MPGEO_NOALLOC_SCRATCH_BYTES (320 MiB) per GPU, which each GPU the library runs
+ * on holds from its first context until the process ends.  The call makes no device allocation
+ * and frees nothing; it copies the inputs in and the results out through the context's stream
+ * and returns when they are on the host.  Problems are packed into groups that fit in the array,
+ * one ordering launch and one queue launch per group; a problem that alone does not fit returns
+ * MPGEO_E_TOO_LARGE before any work (all-FP64: up to n = 8,960 sites, 70 tile rows; FP64 band 2
+ * with FP32 beyond: up to about n = 12,100), and MPGEO_TUNE_BAND returns MPGEO_E_UNSUPPORTED (its probe
+ * evaluations would allocate).  Results are those of mpgeo_batch_loglik with MPGEO_BATCH_QUEUE
+ * (same kernels, same arithmetic), out[i] as there.  Every call on one GPU shares that GPU's
+ * array, which keeps the previous call's contents: calls that overlap on one GPU (from two
+ * contexts or two host threads) race, and the caller must serialise them. */
+#define MPGEO_NOALLOC_SCRATCH_BYTES (320ull << 20)
+int mpgeo_batch_loglik_noalloc(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst,
+                               mpgeo_plan plan, mpgeo_result *out);
 
 /* Serving loop for many likelihood requests (the inner loop of many maximum-likelihood fits,
  * Section VIII-D-2): datasets are registered once (host copies kept); requests (dataset, theta)

@@ -19,7 +19,9 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpgeo.so")
 
-MPGEO_OK, MPGEO_E_ARG, MPGEO_E_NOT_SPD, MPGEO_E_NOMEM, MPGEO_E_DEVICE, MPGEO_E_UNSUPPORTED = range(6)
+(MPGEO_OK, MPGEO_E_ARG, MPGEO_E_NOT_SPD, MPGEO_E_NOMEM, MPGEO_E_DEVICE, MPGEO_E_UNSUPPORTED,
+ MPGEO_E_TOO_LARGE) = range(7)
+MPGEO_NOALLOC_SCRATCH_BYTES = 320 << 20
 MPGEO_ORDER_MORTON = 1
 MPGEO_INPUT_DEVICE = 2
 MPGEO_TIMING = 4
@@ -35,7 +37,7 @@ EXPORTED = (
     "mpgeo_dataset_krige", "mpgeo_dataset_perm", "mpgeo_dataset_covariance",
     "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
     "mpgeo_footprint_bytes", "mpgeo_plan_tiers", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
-    "mpgeo_dataset_simulate", "mpgeo_batch_loglik", "mpgeo_server_create",
+    "mpgeo_dataset_simulate", "mpgeo_batch_loglik", "mpgeo_batch_loglik_noalloc", "mpgeo_server_create",
     "mpgeo_server_add_dataset", "mpgeo_server_submit", "mpgeo_server_submit_krige", "mpgeo_server_run",
     "mpgeo_server_destroy",
 )
@@ -128,6 +130,8 @@ def _load() -> ctypes.CDLL:
         "mpgeo_plan_tiers": ([I64, Plan, ctypes.POINTER(PlanTiers)], ctypes.c_int),
         "mpgeo_batch_loglik": ([P, I64, ctypes.POINTER(Instance), Plan, ctypes.POINTER(Result),
                                 ctypes.POINTER(I32)], ctypes.c_int),
+        "mpgeo_batch_loglik_noalloc": ([P, I64, ctypes.POINTER(Instance), Plan, ctypes.POINTER(Result)],
+                                       ctypes.c_int),
         "mpgeo_server_create": ([P, ctypes.c_uint64, I32, ctypes.POINTER(P)], ctypes.c_int),
         "mpgeo_server_add_dataset": ([P, I64, P, P, Plan, ctypes.POINTER(I32)], ctypes.c_int),
         "mpgeo_server_submit": ([P, I32, Theta, D, ctypes.POINTER(I64)], ctypes.c_int),
@@ -284,6 +288,25 @@ class Context:
         if st not in (MPGEO_OK, MPGEO_E_NOT_SPD):
             _check(st, "mpgeo_batch_loglik")
         return st, [res[q].as_dict() for q in range(len(problems))], [tiles[q] for q in range(len(problems))]
+
+    def batch_loglik_noalloc(self, problems, band64: int = -1, profile: bool = False,
+                             gcd: bool = False) -> tuple:
+        """The persistent-queue batch through mpgeo_batch_loglik_noalloc: every work buffer in
+        the GPU's fixed device array (tile 128).  Returns (status, results) without raising on
+        non-positive-definite instances."""
+        keep = []
+        arr = (Instance * max(1, len(problems)))()
+        for q, (locs, z, theta) in enumerate(problems):
+            locs, z = _host_f64(locs), _host_f64(z)
+            keep.append((locs, z))
+            arr[q] = Instance(int(locs.shape[0]), locs.ctypes.data, z.ctypes.data, Theta(*theta))
+        res = (Result * max(1, len(problems)))()
+        flags = (MPGEO_PROFILE if profile else 0) | (MPGEO_DIST_GCD if gcd else 0)
+        st = LIB.mpgeo_batch_loglik_noalloc(self.handle, len(problems), arr,
+                                            make_plan(128, band64, flags), res)
+        if st not in (MPGEO_OK, MPGEO_E_NOT_SPD):
+            _check(st, "mpgeo_batch_loglik_noalloc")
+        return st, [res[q].as_dict() for q in range(len(problems))]
 
     def kernel_stats(self) -> list:
         arr = (KernelStat * 32)()

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -423,7 +424,7 @@ struct mpgeo_ctx {
     std::vector<hipEvent_t> spare;
     mpgeo_kernel_stat stats[kStatCount];
     bool timing = false;
-    mpgeo_dataset *scratch_ds = nullptr;   // workspace of the one-shot calls
+    mpgeo_dataset *oneshot_ds = nullptr;   // workspace of the one-shot calls
     // batched evaluation: lanes (each its own streams, events and workspace) that run
     // independent instances concurrently, and the tile sizes the autotuner measured, keyed by
     // (half-octave bucket of n, precision plan)
@@ -1164,6 +1165,7 @@ const char *mpgeo_status_string(int status) {
         case MPGEO_E_NOMEM: return "device memory allocation failed";
         case MPGEO_E_DEVICE: return "HIP runtime error";
         case MPGEO_E_UNSUPPORTED: return "unsupported feature";
+        case MPGEO_E_TOO_LARGE: return "problem exceeds the fixed scratch array of the allocation-free entry point";
         default: return "unknown status";
     }
 }
@@ -1232,6 +1234,34 @@ int mpgeo_plan_tiers(int64_t n, mpgeo_plan plan, mpgeo_tier_summary *out) {
     return MPGEO_OK;
 }
 
+// ---- the fixed device array of the allocation-free batch --------------------------------------
+// Every work buffer of mpgeo_batch_loglik_noalloc is carved from `scratch`.  Host code never uses
+// the array's name as an address (on the host it is only a stand-in for the symbol): its device
+// address is resolved once per GPU, with that GPU current, when the first context on it is
+// created, and kept here.
+constexpr size_t kScratchBytes = (size_t)MPGEO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_ptr;   // device ordinal -> device address of `scratch`
+
+static int scratch_setup(int device) {   // the device is current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return MPGEO_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+        (void)hipGetLastError();
+        return MPGEO_E_DEVICE;
+    }
+    g_scratch_ptr[device] = static_cast<char *>(ptr);
+    return MPGEO_OK;
+}
+
+static char *scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
 int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream, size_t hbm_budget_bytes) {
     if (!out) return MPGEO_E_ARG;
     *out = nullptr;
@@ -1242,6 +1272,7 @@ int mpgeo_ctx_create(mpgeo_ctx **out, int device, void *hip_stream, size_t hbm_b
     }
     if (device < 0 || device >= count) return MPGEO_E_ARG;
     MPGEO_HIP(hipSetDevice(device));
+    MPGEO_TRY(scratch_setup(device));
     mpgeo_ctx *c = new mpgeo_ctx();
     c->device = device;
     c->hbm_budget = hbm_budget_bytes;
@@ -1282,7 +1313,7 @@ int mpgeo_ctx_destroy(mpgeo_ctx *ctx) {
     if (!ctx) return MPGEO_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->scratch_ds) mpgeo_dataset_destroy(ctx->scratch_ds);
+    if (ctx->oneshot_ds) mpgeo_dataset_destroy(ctx->oneshot_ds);
     for (auto *d : ctx->lane_ds) mpgeo_dataset_destroy(d);
     for (auto *c : ctx->lanes) mpgeo_ctx_destroy(c);
     ctx->batch_res.release();
@@ -1372,17 +1403,17 @@ int mpgeo_loglik(mpgeo_ctx *ctx, int64_t n, const double *locs, const double *z,
     MPGEO_TRY(check_plan(plan));
     Device dev(ctx->device);
     if (!dev.ok) return MPGEO_E_DEVICE;
-    if (ctx->scratch_ds && ctx->scratch_ds->n != n) {
+    if (ctx->oneshot_ds && ctx->oneshot_ds->n != n) {
         // keep the large tile pools if the size matches; otherwise start over
-        mpgeo_dataset_destroy(ctx->scratch_ds);
-        ctx->scratch_ds = nullptr;
+        mpgeo_dataset_destroy(ctx->oneshot_ds);
+        ctx->oneshot_ds = nullptr;
     }
-    if (!ctx->scratch_ds) {
-        ctx->scratch_ds = new mpgeo_dataset();
-        ctx->scratch_ds->ctx = ctx;
-        ctx->scratch_ds->n = n;
+    if (!ctx->oneshot_ds) {
+        ctx->oneshot_ds = new mpgeo_dataset();
+        ctx->oneshot_ds->ctx = ctx;
+        ctx->oneshot_ds->n = n;
     }
-    mpgeo_dataset *ds = ctx->scratch_ds;
+    mpgeo_dataset *ds = ctx->oneshot_ds;
     ds->flags = plan.flags;
     ctx->timing = (plan.flags & MPGEO_TIMING) != 0;
     EventSet ev;
@@ -1820,7 +1851,7 @@ static void batch_sync(mpgeo_ctx *ctx) {
 // Tile size for an instance: the plan's, else the fastest of the candidates measured on the
 // first instance of its (half-octave of n, precision plan) class.  Candidates: one tile
 // covering the problem when it fits, and 128, 256, 384, 512 below n.
-static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, double *scratch,
+static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, double *probe_out,
                       int *tile_out) {
     if (pl.tile > 0) {
         *tile_out = pl.tile;
@@ -1848,10 +1879,10 @@ static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, d
     for (int t : cand) {
         mpgeo_plan q = pl;
         q.tile = t;
-        MPGEO_TRY(batch_enqueue(ds, in, q, scratch));   // warm-up (allocations, layout)
+        MPGEO_TRY(batch_enqueue(ds, in, q, probe_out));   // warm-up (allocations, layout)
         batch_sync(ctx);
         if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[0], st));
-        MPGEO_TRY(batch_enqueue(ds, in, q, scratch));
+        MPGEO_TRY(batch_enqueue(ds, in, q, probe_out));
         if (ev.ok) MPGEO_HIP(hipEventRecord(ev.e[1], st));
         batch_sync(ctx);
         const double sec = ev.secs(0, 1);
@@ -1881,7 +1912,7 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
 // depends only on that instance's results, which the kernels make deterministic; it is kept in
 // the context for later batches.  Probes run through the queue (queue) or a lane.
 static int batch_band(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, int tile, bool queue,
-                      double *scratch, int *band_out) {
+                      double *probe_out, int *band_out) {
     const int bucket = (int)std::floor(2.0 * std::log2((double)in.n));
     const std::string key = std::to_string(bucket) + "/" + std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
                             std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
@@ -1907,11 +1938,11 @@ static int batch_band(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, i
             const int32_t b = cand[c];
             st = batch_queue(ctx, 1, &in, q, &r, nullptr, nullptr, 0, &b);
         } else {
-            st = batch_enqueue(ctx->lane_ds[0], in, q, scratch);
+            st = batch_enqueue(ctx->lane_ds[0], in, q, probe_out);
             batch_sync(ctx);
             if (st == MPGEO_OK) {
                 double host[4];
-                MPGEO_HIP(hipMemcpy(host, scratch, sizeof(host), hipMemcpyDeviceToHost));
+                MPGEO_HIP(hipMemcpy(host, probe_out, sizeof(host), hipMemcpyDeviceToHost));
                 unsigned long long info;
                 std::memcpy(&info, host + 3, sizeof(info));
                 r.loglik = host[0];
@@ -1974,7 +2005,7 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
     size_t budget = 0;
     if (fixed) {
         for (int64_t q = 0; q < count; ++q)
-            if (prob_bytes(q) + kSlack > arena_bytes) return MPGEO_E_ARG;   // beyond the array
+            if (prob_bytes(q) + kSlack > arena_bytes) return MPGEO_E_TOO_LARGE;   // beyond the array
     } else {
         size_t free_b = 0, total_b = 0;
         MPGEO_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -2055,7 +2086,7 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
                 ptr[q] = arena + off;
                 off += align256(sz[q]);
             }
-            if (off > arena_bytes) return MPGEO_E_ARG;   // (the packing rule keeps it inside)
+            if (off > arena_bytes) return MPGEO_E_TOO_LARGE;   // (the packing rule keeps it inside)
         } else {   // grow only; growing waits for the device
             DevBuf *bufs[13] = {&ctx->q_in_locs, &ctx->q_in_z, &ctx->q_locs, &ctx->q_vec, &ctx->q_tiles,
                                 &ctx->q_linv, &ctx->q_parts, &ctx->q_flags, &ctx->q_ctrl, &ctx->q_insts,
@@ -2246,6 +2277,23 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         if (tiles) tiles[i] = tile[(size_t)i];
     }
     return status;
+}
+
+// The persistent-queue batch with its work buffers in the GPU's fixed array: no device
+// allocation (and no freeing) on any path of the call; the fill kernel clears what must start at
+// zero, since the array keeps the previous call's contents.
+int mpgeo_batch_loglik_noalloc(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
+                               mpgeo_result *out) {
+    MPGEO_TRY(check_batch_args(ctx, count, inst, plan, out));
+    if (plan.flags & MPGEO_TUNE_BAND) return MPGEO_E_UNSUPPORTED;   // its probes would allocate
+    MPGEO_TRY(queue_plan_ok(plan));
+    MPGEO_TRY(queue_sizes_ok(count, inst));
+    if (count == 0) return MPGEO_OK;
+    Device dev(ctx->device);
+    if (!dev.ok) return MPGEO_E_DEVICE;
+    char *ptr = scratch_ptr(ctx->device);
+    if (!ptr) return MPGEO_E_DEVICE;
+    return batch_queue(ctx, count, inst, plan, out, nullptr, ptr, kScratchBytes, nullptr);
 }
 
 // ---- serving loop ---------------------------------------------------------------------------
