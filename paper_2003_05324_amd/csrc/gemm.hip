@@ -272,14 +272,19 @@ void launch_shape(const GemmArgs &g, int64_t ntiles, hipStream_t stream) {
                        stream, ga);
 }
 
-// Production shapes: 128 x 128 blocks of 4 waves when the tile allows, else 64 or 32;
-// K chunks of 16 columns.  `narrow` (the few-tile FP64 launches of the critical path, which
-// run beside the wide trailing updates): 64 x 64 blocks with K chunks of 8, 20 KB of LDS
+// Production shapes: 128 x 128 blocks of 8 waves (64 x 32 each) when the tile allows, else 64
+// or 32; K chunks of 16 columns.  `narrow` (the few-tile FP64 launches of the critical path,
+// which run beside the wide trailing updates): 64 x 64 blocks with K chunks of 8, 20 KB of LDS
 // instead of 72 KB, so a workgroup fits where one of the concurrent update workgroups ends.
-// Trailing updates measured alone on the n ~ 1e5 step-0 lists: FP64 band lists (a third of
-// them diagonal tiles) 56.5 TFLOP/s with 64 x 64 blocks of 4 waves (128 x 128: 51.7; the
-// diagonal tiles' skipped upper blocks waste less), while the long all-FP64 lists run faster
-// on 128 x 128 blocks; FP32 128 x 128 blocks of 8 waves (32 x 64 each) 130 TFLOP/s (4 waves: 124).
+// Measured in the n ~ 1e5 evaluations: FP32 updates 123 TFLOP/s with 8 waves of 64 x 32 (8
+// waves of 32 x 64: 119.6; 4 waves of 64 x 64, accumulators in AGPRs at 3 waves per SIMD: 114;
+// 256 x 128 or 256 x 256 blocks, or K chunks of 32 or 8: 93-106); the all-FP64 evaluation 5.32 s
+// against 5.54 s with 4 waves.  The panel TRSMs keep 4 waves of 64 x 64: with 8 waves they ran
+// 3.8x faster on the lookahead stream but took compute units from the 16-bit pass beside them
+// (three-tier evaluation 1.00 against 1.06 evaluations/s).  FP64 band lists (a third
+// of them diagonal tiles) run faster on 64 x 64 blocks of 4 waves (56.5 TFLOP/s measured alone
+// on the step-0 lists against 51.7 with 128 x 128: the diagonal tiles' skipped upper blocks
+// waste less).
 constexpr int64_t kShortFp64List = 1024;
 template <typename T, int EPI>
 void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream, bool narrow = false) {
@@ -288,9 +293,8 @@ void launch_gemm(const GemmArgs &g, int64_t ntiles, hipStream_t stream, bool nar
     if (narrow && nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 8>, EPI>(g, ntiles, stream);
     else if (EPI == kUpdate && sizeof(T) == 8 && nbp % 64 == 0 && ntiles <= kShortFp64List)
         launch_shape<T, Shape<64, 64, 2, 2, 16>, EPI>(g, ntiles, stream);
-    else if (EPI == kUpdate && sizeof(T) == 4 && nbp % 128 == 0)
-        launch_shape<T, Shape<128, 128, 4, 2, 16>, EPI>(g, ntiles, stream);
-    else if (nbp % 128 == 0) launch_shape<T, Shape<128, 128, 2, 2, 16>, EPI>(g, ntiles, stream);
+    else if (nbp % 128 == 0 && EPI == kTrsm) launch_shape<T, Shape<128, 128, 2, 2, 16>, EPI>(g, ntiles, stream);
+    else if (nbp % 128 == 0) launch_shape<T, Shape<128, 128, 2, 4, 16>, EPI>(g, ntiles, stream);
     else if (nbp % 64 == 0) launch_shape<T, Shape<64, 64, 2, 2, 16>, EPI>(g, ntiles, stream);
     else launch_shape<T, Shape<32, 32, 2, 2, 16>, EPI>(g, ntiles, stream);
 }
