@@ -127,10 +127,16 @@ def parse():
                          "(n log-uniform in [500, 8000]) through the batched entry point, against "
                          "one-at-a-time evaluation; one JSON line")
     ap.add_argument("--serve", type=int, default=0,
-                    help="instead of the headline: this many requests (Poisson arrivals) for 16 "
-                         "resident datasets (n log-uniform in [2000, 60000]) through the serving "
-                         "loop, three-tier, two-tier and FP64 plans; one JSON line")
+                    help="instead of the headline: this many requests (Poisson arrivals, theta along "
+                         "Nelder-Mead trajectories) for 16 resident datasets (n log-uniform in "
+                         "[2000, 60000], the small ones through the persistent queue) through the "
+                         "serving loop, three-tier, two-tier and FP64 plans; one JSON line")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="arrivals per second")
+    ap.add_argument("--serve-theta", default="trajectory", choices=["trajectory", "lognormal"],
+                    help="request theta: along Nelder-Mead trajectories, or log-normal around theta_0 "
+                         "with nu = 1/2 fixed")
+    ap.add_argument("--serve-queue-max-n", type=int, default=4096,
+                    help="datasets up to this n are served through the persistent queue (0: none)")
     ap.add_argument("--small", action="store_true",
                     help="instead of the headline: the n = 1,600 plain-method workload (40 x 40 "
                          "jittered grid, tile 160, FP64 band 2): --repeats evaluations at the true "
@@ -141,6 +147,11 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline: the n = 40,000 band sweep (6 fields x bands "
                          "0, 1, 4, 16, all), one JSON line")
+    ap.add_argument("--sweep-fields", default="",
+                    help="comma list of sweep field indices (0-5) to run (default: all)")
+    ap.add_argument("--sweep-mle", action="store_true",
+                    help="with --sweep: also the maximum-likelihood fit of theta at bands 0, 4 and "
+                         "all (Nelder-Mead from theta_0 * (1.5, 0.5, 1.2), xtol 1e-5 in log-theta)")
     return ap.parse_args()
 
 
@@ -344,21 +355,32 @@ def small_bench(args):
 def band_sweep(args):
     """n = 40,000 band sweep: sigma2 = 1, beta in {0.03, 0.1, 0.3} x nu in {0.5, 1.0}, each field
     drawn by the library's FP64 sampler; for every FP64 band b the log-likelihood at the true
-    theta, its error against the all-FP64 path, SPD failures and the factor rate."""
+    theta, its error against the all-FP64 path and against the oracle's eq. (2) at the true
+    theta (stored in tests/golden/sweep_n40000.json by a script that calls only the oracle; the
+    oracle's z = L eps comes from its own factor, equal to the library's draw to rounding), SPD
+    failures and the factor rate; with --sweep-mle the maximum-likelihood fit of theta at bands
+    0, 4 and all."""
     import torch
 
     import paper_2003_05324_amd as mp
     from synthetic import SWEEP
+    gold_path = os.path.join(ROOT, "tests", "golden", "sweep_n40000.json")
+    gold = {}
+    if os.path.exists(gold_path):
+        gold = {f["field"]: f for f in json.load(open(gold_path))["fields"]}
+    fields = [int(x) for x in args.sweep_fields.split(",")] if args.sweep_fields else range(len(SWEEP))
     ctx = mp.Context(0)
     dev = torch.device("cuda:0")
-    rows = []
-    for w in SWEEP:
+    rows, fits = [], []
+    for fi in fields:
+        w = SWEEP[fi]
         locs = torch.from_numpy(w.locations()).to(dev)
         gen = mp.Dataset(ctx, locs, None)
         z = gen.simulate(w.theta, torch.from_numpy(w.eps()).to(dev), w.tile, -1)
         gen.close()
         ds = mp.Dataset(ctx, locs, z)
         ref = None
+        og = gold.get(w.name)
         for band in sorted(w.bands, key=lambda b: (b < 0, b), reverse=True):   # all-FP64 first
             st, _ = ds.try_loglik(w.theta, w.tile, band)                       # warm-up
             times, res = [], None
@@ -372,21 +394,48 @@ def band_sweep(args):
                 t = statistics.median(times)
                 row.update({"loglik": res["loglik"], "logdet": res["logdet"], "quad": res["quad"],
                             "t_factor_s": t, "cholesky_tflops": w.n ** 3 / 3.0 / t / 1e12})
+                if og is not None:
+                    row["dloglik_rel_vs_oracle"] = abs(res["loglik"] - og["loglik"]) / abs(og["loglik"])
+                    row["dlogdet_rel_vs_oracle"] = abs(res["logdet"] - og["logdet"]) / abs(og["logdet"])
                 if band < 0:
                     ref = res
                 elif ref is not None:
-                    row["dloglik_rel"] = abs(res["loglik"] - ref["loglik"]) / max(abs(ref["loglik"]), w.n)
+                    row["dloglik_rel_vs_fp64"] = abs(res["loglik"] - ref["loglik"]) / abs(ref["loglik"])
                     row["dlogdet_rel"] = abs(res["logdet"] - ref["logdet"]) / abs(ref["logdet"])
                     row["dquad_rel"] = abs(res["quad"] - ref["quad"]) / ref["quad"]
             rows.append(row)
             print(f"[sweep] {row}", file=sys.stderr, flush=True)
+        if args.sweep_mle:
+            start = [min(max(t * sc, lo), hi) for t, sc, lo, hi in
+                     zip(w.theta, (1.5, 0.5, 1.2), (0.01, 0.001, 0.1), (10.0, 2.0, 3.0))]
+            fit_ref = None
+            for band in (-1, 4, 0):
+                t0 = time.perf_counter()
+                try:
+                    fit = ds.mle(start, w.tile, band, xtol=1e-5)
+                except mp.MpgeoError as e:
+                    fit = {"error": str(e)}
+                sec = time.perf_counter() - t0
+                f = {"field": w.name, "band64": band, "start": start, "seconds": sec}
+                f.update(fit)
+                if "theta" in fit:
+                    if band < 0:
+                        fit_ref = fit
+                    elif fit_ref is not None:
+                        f["max_rel_dtheta_vs_fp64_fit"] = max(abs(a - b) / abs(b) for a, b in
+                                                              zip(fit["theta"], fit_ref["theta"]))
+                fits.append(f)
+                print(f"[sweep] mle {f}", file=sys.stderr, flush=True)
         ds.close()
     for r in rows:
         base = next(x for x in rows if x["field"] == r["field"] and x["band64"] < 0)
         if "t_factor_s" in r and "t_factor_s" in base:
             r["speedup_vs_fp64"] = base["t_factor_s"] / r["t_factor_s"]
     ctx.close()
-    print(json.dumps({"sweep": "matern-n40000-nb512", "steps": args.steps, "rows": rows}), flush=True)
+    out = {"sweep": "matern-n40000-nb512", "steps": args.steps, "rows": rows}
+    if args.sweep_mle:
+        out["mle"] = fits
+    print(json.dumps(out), flush=True)
 
 
 def batch_bench(args):
@@ -463,35 +512,73 @@ def batch_bench(args):
 
 
 def serve_bench(args):
-    """Serving loop: Poisson arrivals of likelihood requests (theta drawn around (1, 0.1, 0.5) as
-    an optimiser's trajectory would visit it) for 16 datasets, every fourth a kriging request
-    (predictions and variances at 500 new sites), HBM budget 96 GB, 4 lanes; the same trace with
-    the three-tier plan (FP64 band 2, FP32 next 8 tiles, FP16 operands beyond; tile 512), the
-    two-tier plan (FP64 band 2, FP32 beyond) and the all-FP64 plan."""
+    """Serving loop: Poisson arrivals of likelihood requests for 16 datasets (n log-uniform in
+    [2,000, 60,000], z a draw of the Matern field at theta_0 = (1, 0.1, 0.5) by the library's FP64
+    sampler), every fourth a kriging request (predictions and variances at 500 new sites), HBM
+    budget 96 GB, 4 lanes.  The theta of the requests for a dataset follow, in order, a seeded
+    Nelder-Mead trajectory: the library's own maximum-likelihood search (mpgeo_dataset_mle_trace,
+    all-FP64, tile 128) on a 30 x 30 field drawn at theta_0 with the dataset's seed, from
+    theta_0 * (1.5, 0.5, 1.2).  Datasets of n <= 4,096 are served through the persistent queue
+    (tile 128, FP64 within the same distance of the diagonal as the leg's plan, FP32 beyond;
+    ready requests batched into one launch), the others on the lanes with the leg's plan at tile
+    512: the three-tier plan (FP64 band 2, FP32 next 8 tiles, FP16 operands beyond), the two-tier
+    plan (FP64 band 2, FP32 beyond) and the all-FP64 plan, the same trace each time."""
     import numpy as np
 
     import paper_2003_05324_amd as mp
     from synthetic import jittered_grid, normals, uniform_sites
     rng = np.random.default_rng(21)
     sizes = [int(round(np.exp(rng.uniform(np.log(2000), np.log(60000))))) for _ in range(16)]
+    theta0 = (1.0, 0.1, 0.5)
+    ctx = mp.Context(0)
     data = []
     for q, n in enumerate(sizes):
         m = int(np.ceil(np.sqrt(n)))
-        data.append((jittered_grid(m, 700 + q)[:n].copy(), normals(n, 800 + q)))
+        locs = jittered_grid(m, 700 + q)[:n].copy()
+        gen = mp.Dataset(ctx, locs, None)
+        z = gen.simulate(theta0, normals(n, 800 + q), 512, -1)
+        gen.close()
+        data.append((locs, np.asarray(z)))
+    # one optimiser trajectory per dataset
+    start = (1.5 * theta0[0], 0.5 * theta0[1], 1.2 * theta0[2])
+    trajectories = []
+    for q in range(len(sizes)):
+        tl = jittered_grid(30, 1700 + q)
+        gen = mp.Dataset(ctx, tl, None)
+        tz = gen.simulate(theta0, normals(len(tl), 1800 + q), 128, -1)
+        gen.close()
+        tds = mp.Dataset(ctx, tl, tz)
+        fit = tds.mle_trace(start, 128, -1, xtol=1e-4, max_evals=400)
+        tds.close()
+        trajectories.append([th for th, ll in zip(fit["trace"], fit["trace_loglik"]) if np.isfinite(ll)])
     arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, args.serve))
     picks = rng.integers(0, len(sizes), args.serve)
-    thetas = [(float(np.exp(rng.normal(0, 0.15))), float(0.1 * np.exp(rng.normal(0, 0.15))), 0.5)
-              for _ in range(args.serve)]
+    used = [0] * len(sizes)
+    thetas = []
+    for d in picks:
+        tr = trajectories[d]
+        thetas.append(tuple(tr[used[d] % len(tr)]))
+        used[d] += 1
+    if args.serve_theta == "lognormal":
+        trng = np.random.default_rng(22)
+        thetas = [(float(np.exp(trng.normal(0, 0.15))), float(0.1 * np.exp(trng.normal(0, 0.15))), 0.5)
+                  for _ in range(args.serve)]
     flops = float(sum(sizes[d] ** 3 / 3.0 for d in picks))
     kriging = [q % 4 == 3 for q in range(args.serve)]
     new_sites = [uniform_sites(500, 950 + q) for q in range(len(sizes))]
-    ctx = mp.Context(0)
+    small = [n <= args.serve_queue_max_n for n in sizes]
     out = {"serve": f"matern-serve{args.serve}-16sets-n2000-60000", "requests": args.serve,
-           "rate_per_s": args.serve_rate, "dataset_sizes": sizes, "sum_n3_over_3": flops}
+           "rate_per_s": args.serve_rate, "dataset_sizes": sizes, "sum_n3_over_3": flops,
+           "queued_datasets": int(sum(small)),
+           "queued_requests": int(sum(1 for d, k in zip(picks, kriging) if small[d] and not k)),
+           "trajectory_evals": [len(t) for t in trajectories]}
     for name, band, band32, lowp in (("three_tier_b2_c8", 2, 8, "fp16"), ("two_tier_b2", 2, -1, None),
                                      ("fp64", -1, -1, None)):
         srv = mp.Server(ctx, 96 * 2 ** 30, 4)
-        ids = [srv.add_dataset(locs, z, 512, band, band32, lowp) for locs, z in data]
+        qband = -1 if band < 0 else (band + 1) * 512 // 128 - 1   # the same FP64 distance at tile 128
+        ids = [srv.add_dataset(locs, z, 128, qband, queue=True) if sm else
+               srv.add_dataset(locs, z, 512, band, band32, lowp)
+               for (locs, z), sm in zip(data, small)]
         for q in range(args.serve):
             if kriging[q]:
                 srv.submit_krige(ids[picks[q]], thetas[q], new_sites[picks[q]], float(arrivals[q]),
@@ -503,19 +590,25 @@ def serve_bench(args):
         srv.close()
         lat = np.array([r["finish_s"] - r["arrival_s"] for r in res])
         klat = np.array([r["finish_s"] - r["arrival_s"] for r, k in zip(res, kriging) if k])
+        qlat = np.array([r["finish_s"] - r["arrival_s"] for r, d, k in zip(res, picks, kriging)
+                         if small[d] and not k])
         wait = np.array([r["start_s"] - r["arrival_s"] for r in res])
         span = max(r["finish_s"] for r in res)
-        out[name] = {"status": st, "p50_latency_s": float(np.percentile(lat, 50)),
+        failed = int(sum(1 for r in res if r["info"] >= 0))
+        out[name] = {"status": st, "status_string": mp.status_string(st), "failed_requests": failed,
+                     "p50_latency_s": float(np.percentile(lat, 50)),
                      "p99_latency_s": float(np.percentile(lat, 99)),
                      "kriging_requests": int(sum(kriging)),
                      "kriging_p50_latency_s": float(np.percentile(klat, 50)) if len(klat) else None,
+                     "queued_p50_latency_s": float(np.percentile(qlat, 50)) if len(qlat) else None,
                      "mean_wait_s": float(wait.mean()), "makespan_s": span,
                      "evals_per_s": args.serve / span, "tflops": flops / span / 1e12,
                      "loglik_first": res[0]["loglik"]}
         print(f"[serve] {name}: {out[name]}", file=sys.stderr, flush=True)
     ctx.close()
-    out["p50_speedup_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["two_tier_b2"]["p50_latency_s"]
-    out["p50_speedup_three_tier_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["three_tier_b2_c8"]["p50_latency_s"]
+    if all(out[k]["status"] == 0 for k in ("fp64", "two_tier_b2", "three_tier_b2_c8")):
+        out["p50_speedup_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["two_tier_b2"]["p50_latency_s"]
+        out["p50_speedup_three_tier_vs_fp64"] = out["fp64"]["p50_latency_s"] / out["three_tier_b2_c8"]["p50_latency_s"]
     print(json.dumps(out), flush=True)
 
 

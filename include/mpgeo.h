@@ -287,6 +287,16 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
                       double ftol, int32_t max_evals, mpgeo_theta *theta_hat,
                       double *loglik_hat, int32_t *evals, int32_t *iters);
 
+/* mpgeo_dataset_mle that also records the search's trajectory, the sequence of parameter
+ * vectors an optimiser asks a likelihood service for (Section VIII-D-2: each fit is many
+ * evaluations of eq. (2)): trace[e] (max_evals entries, host memory, not NULL) receives the
+ * e-th evaluated theta and trace_loglik[e] (nullable) its log-likelihood, -infinity where the
+ * matrix was not positive definite; *evals of them are written.  Same search, same result. */
+int mpgeo_dataset_mle_trace(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
+                            double ftol, int32_t max_evals, mpgeo_theta *theta_hat,
+                            double *loglik_hat, int32_t *evals, int32_t *iters,
+                            mpgeo_theta *trace, double *trace_loglik);
+
 /* Algorithm 1 on a caller-given symmetric positive-definite matrix: A is n x n,
  * column-major with leading dimension lda >= n, only its lower triangle is read; z
  * (n entries) is optional (NULL: quad = 0 and loglik uses quad = 0).  No reordering.

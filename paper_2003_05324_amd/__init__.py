@@ -37,6 +37,7 @@ EXPORTED = (
     "mpgeo_dataset_krige", "mpgeo_dataset_perm", "mpgeo_dataset_covariance",
     "mpgeo_dataset_matrix", "mpgeo_dataset_solution", "mpgeo_factor_dense",
     "mpgeo_footprint_bytes", "mpgeo_plan_tiers", "mpgeo_status_string", "mpgeo_dataset_entries", "mpgeo_dataset_mle",
+    "mpgeo_dataset_mle_trace",
     "mpgeo_dataset_simulate", "mpgeo_batch_loglik", "mpgeo_batch_loglik_noalloc", "mpgeo_server_create",
     "mpgeo_server_add_dataset", "mpgeo_server_submit", "mpgeo_server_submit_krige", "mpgeo_server_run",
     "mpgeo_server_destroy",
@@ -126,6 +127,9 @@ def _load() -> ctypes.CDLL:
         "mpgeo_dataset_mle": ([P, Theta, Plan, D, D, I32, ctypes.POINTER(Theta),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
                                ctypes.POINTER(I32)], ctypes.c_int),
+        "mpgeo_dataset_mle_trace": ([P, Theta, Plan, D, D, I32, ctypes.POINTER(Theta),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
+                                     ctypes.POINTER(I32), ctypes.POINTER(Theta), P], ctypes.c_int),
         "mpgeo_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "mpgeo_plan_tiers": ([I64, Plan, ctypes.POINTER(PlanTiers)], ctypes.c_int),
         "mpgeo_batch_loglik": ([P, I64, ctypes.POINTER(Instance), Plan, ctypes.POINTER(Result),
@@ -443,6 +447,24 @@ class Dataset:
         return {"theta": (th.sigma2, th.beta, th.nu), "loglik": ll.value, "evals": ev.value,
                 "iters": it.value}
 
+    def mle_trace(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
+                  ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None) -> dict:
+        """mle() that also returns the search's trajectory: every evaluated theta in order and
+        its log-likelihood (-inf where the matrix was not positive definite)."""
+        th = Theta()
+        ll = ctypes.c_double()
+        ev = ctypes.c_int32()
+        it = ctypes.c_int32()
+        trace = (Theta * max_evals)()
+        trace_ll = np.empty(max_evals)
+        _check(LIB.mpgeo_dataset_mle_trace(self.handle, Theta(*start), make_plan(tile, band64, 0, band32, lowp),
+                                           xtol, ftol, max_evals, ctypes.byref(th), ctypes.byref(ll),
+                                           ctypes.byref(ev), ctypes.byref(it), trace, trace_ll.ctypes.data),
+               "mpgeo_dataset_mle_trace")
+        e = ev.value
+        return {"theta": (th.sigma2, th.beta, th.nu), "loglik": ll.value, "evals": e, "iters": it.value,
+                "trace": [(t.sigma2, t.beta, t.nu) for t in trace[:e]], "trace_loglik": trace_ll[:e].copy()}
+
     def solution(self) -> np.ndarray:
         out = np.empty(self.n)
         _check(LIB.mpgeo_dataset_solution(self.handle, out.ctypes.data), "mpgeo_dataset_solution")
@@ -461,11 +483,15 @@ class Server:
         self.count = 0
         self._krige = {}   # ticket -> (sites, pred, var) kept alive until run
 
-    def add_dataset(self, locs, z, tile: int, band64: int, band32: int = -1, lowp=None) -> int:
+    def add_dataset(self, locs, z, tile: int, band64: int, band32: int = -1, lowp=None,
+                    queue: bool = False) -> int:
+        """queue=True: the dataset's likelihood requests run through the persistent task queue,
+        batched with the other ready ones (two-tier plans at tile 128, n <= 16,384)."""
         locs, z = _host_f64(locs), _host_f64(z)
         out = ctypes.c_int32()
+        flags = MPGEO_BATCH_QUEUE if queue else 0
         _check(LIB.mpgeo_server_add_dataset(self.handle, locs.shape[0], locs.ctypes.data, z.ctypes.data,
-                                            make_plan(tile, band64, 0, band32, lowp), ctypes.byref(out)),
+                                            make_plan(tile, band64, flags, band32, lowp), ctypes.byref(out)),
                "mpgeo_server_add_dataset")
         return out.value
 

@@ -1528,9 +1528,11 @@ int mpgeo_dataset_entries(mpgeo_dataset *ds, int64_t count, const int64_t *rows,
     return MPGEO_OK;
 }
 
-int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
-                      double ftol, int32_t max_evals, mpgeo_theta *theta_hat, double *loglik_hat,
-                      int32_t *evals_out, int32_t *iters_out) {
+// The Nelder-Mead search of mpgeo_dataset_mle; with trace != NULL every evaluated theta (and
+// its log-likelihood, -inf where not positive definite) is recorded in evaluation order.
+static int dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol, double ftol,
+                       int32_t max_evals, mpgeo_theta *theta_hat, double *loglik_hat, int32_t *evals_out,
+                       int32_t *iters_out, mpgeo_theta *trace, double *trace_loglik) {
     if (!ds || max_evals < 4 || !(xtol >= 0.0) || !(ftol >= 0.0)) return MPGEO_E_ARG;
     MPGEO_TRY(check_theta(start));
     MPGEO_TRY(check_plan(plan));
@@ -1551,9 +1553,16 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
     };
     int hard_error = MPGEO_OK;
     // objective: -loglik; a non-positive-definite point scores +infinity
+    int traced = 0;
     auto f = [&](const double *u) -> double {
         mpgeo_result r{};
-        const int st = evaluate_escalating(ds, to_theta(u), plan, &r, nullptr);
+        const mpgeo_theta th = to_theta(u);
+        const int st = evaluate_escalating(ds, th, plan, &r, nullptr);
+        if (trace && traced < max_evals) {
+            trace[traced] = th;
+            if (trace_loglik) trace_loglik[traced] = (st == MPGEO_OK) ? r.loglik : -INFINITY;
+            ++traced;
+        }
         if (st == MPGEO_OK) return -r.loglik;
         if (st != MPGEO_E_NOT_SPD && hard_error == MPGEO_OK) hard_error = st;
         return INFINITY;
@@ -1652,6 +1661,22 @@ int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, dou
     if (evals_out) *evals_out = evals;
     if (iters_out) *iters_out = iters;
     return MPGEO_OK;
+}
+
+int mpgeo_dataset_mle(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
+                      double ftol, int32_t max_evals, mpgeo_theta *theta_hat, double *loglik_hat,
+                      int32_t *evals_out, int32_t *iters_out) {
+    return dataset_mle(ds, start, plan, xtol, ftol, max_evals, theta_hat, loglik_hat, evals_out, iters_out,
+                       nullptr, nullptr);
+}
+
+int mpgeo_dataset_mle_trace(mpgeo_dataset *ds, mpgeo_theta start, mpgeo_plan plan, double xtol,
+                            double ftol, int32_t max_evals, mpgeo_theta *theta_hat, double *loglik_hat,
+                            int32_t *evals_out, int32_t *iters_out, mpgeo_theta *trace,
+                            double *trace_loglik) {
+    if (!trace) return MPGEO_E_ARG;
+    return dataset_mle(ds, start, plan, xtol, ftol, max_evals, theta_hat, loglik_hat, evals_out, iters_out,
+                       trace, trace_loglik);
 }
 
 int mpgeo_dataset_simulate(mpgeo_dataset *ds, mpgeo_theta theta, mpgeo_plan plan,
@@ -1973,40 +1998,180 @@ static int batch_band(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, i
 // fill kernel).
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static int64_t queue_p(int64_t n) { return (n + kQueueTile - 1) / kQueueTile; }
+
+// FP64 band of a problem of n sites in tiles: the requested one, capped at p (every tile)
+static int32_t queue_band(int64_t n, int32_t band) {
+    const int64_t p = queue_p(n);
+    return (int32_t)((band < 0 || band > p) ? p : band);
+}
+
+// bytes of the tiles of a problem: FP64 tiles 8 bytes per entry, FP32 tiles 4
+static size_t queue_tile_bytes(int64_t n, int32_t band) {
+    return (size_t)queue_tile_units(queue_p(n), 0, queue_band(n, band)) * sizeof(float);
+}
+
+// bytes of every work buffer a problem adds to a group (the fixed array's packing rule)
+static size_t queue_prob_bytes(int64_t n, int32_t band) {
+    const int64_t te = (int64_t)kQueueTile * kQueueTile;
+    const int64_t p = queue_p(n), tl = p * (p + 1) / 2;
+    return (size_t)n * 5 * sizeof(double) +                    // packed inputs, ordered sites
+           (size_t)3 * p * kQueueTile * sizeof(double) +        // z, r, y (padded)
+           queue_tile_bytes(n, band) + (size_t)p * te * sizeof(double) +   // tiles, diagonal inverses
+           (size_t)2 * p * sizeof(double) +                     // logdet / quad parts
+           (size_t)tl * (sizeof(int) + sizeof(BatchTask)) +     // done flags, tasks
+           sizeof(BatchInst) + 3 * sizeof(double) + sizeof(unsigned long long);
+}
+constexpr size_t kQueueSlack = 13 * 256 + 2 * sizeof(int);     // alignment of 13 buffers, control
+
+// Host side of one queued group (layout, task list, packed inputs: kept until the group's
+// copies and launches have completed) and where its results land on the device.
+struct QueueGroup {
+    std::vector<BatchInst> bi;
+    std::vector<BatchTask> tasks;
+    std::vector<double> hl, hz;
+    double *res = nullptr;               // loglik, logdet, quad per problem
+    unsigned long long *info = nullptr;  // failing column per problem, all ones if none
+    int *ctrl = nullptr;                 // task counter, abort flag
+};
+
+// Lays out problems inst[0 .. gc) (FP64 band of each in bands[]) as one group, uploads their
+// inputs and enqueues the ordering launch and the queue launch on stream s without waiting.
+static int queue_group_enqueue(mpgeo_ctx *ctx, hipStream_t s, const mpgeo_instance *const *inst, int64_t gc,
+                               const int32_t *bands, const mpgeo_plan &plan, char *arena, size_t arena_bytes,
+                               QueueGroup &G, int max_workgroups = 0) {
+    const int64_t te = (int64_t)kQueueTile * kQueueTile;
+    const bool fixed = arena != nullptr;
+    G.bi.assign((size_t)gc, BatchInst{});
+    int64_t pts = 0, tl = 0, lv = 0, vec = 0, prt = 0, units = 0;
+    int max_n = 1, max_p = 1;
+    for (int64_t q = 0; q < gc; ++q) {
+        const mpgeo_instance &x = *inst[q];
+        BatchInst &b = G.bi[(size_t)q];
+        b.n = x.n;
+        b.p = (int32_t)queue_p(x.n);
+        b.band = queue_band(x.n, bands[q]);
+        b.in0 = pts;
+        b.tile0 = units;
+        b.flag0 = tl;
+        b.linv0 = lv;
+        b.vec0 = vec;
+        b.part0 = prt;
+        b.mp = make_matern_params((plan.flags & MPGEO_PROFILE) ? 1.0 : x.theta.sigma2, x.theta.beta, x.theta.nu);
+        b.mp.gcd = (plan.flags & MPGEO_DIST_GCD) ? 1 : 0;
+        pts += x.n;
+        tl += (int64_t)b.p * (b.p + 1) / 2;
+        units += queue_tile_units(b.p, 0, b.band);
+        lv += b.p;
+        vec += (int64_t)b.p * kQueueTile;
+        prt += 2 * (int64_t)b.p;
+        max_n = std::max<int>(max_n, (int)x.n);
+        max_p = std::max<int>(max_p, b.p);
+    }
+    // tasks: column by column; in a column the diagonal tiles of every problem, then the rest
+    G.tasks.clear();
+    G.tasks.reserve((size_t)tl);
+    for (int j = 0; j < max_p; ++j) {
+        for (int64_t q = 0; q < gc; ++q)
+            if (j < G.bi[(size_t)q].p) G.tasks.push_back({(int32_t)q, j, j, 0});
+        for (int64_t q = 0; q < gc; ++q)
+            for (int i = j + 1; i < G.bi[(size_t)q].p; ++i) G.tasks.push_back({(int32_t)q, i, j, 0});
+    }
+    G.hl.assign((size_t)pts * 2, 0.0);
+    G.hz.assign((size_t)pts, 0.0);
+    for (int64_t q = 0; q < gc; ++q) {
+        const mpgeo_instance &x = *inst[q];
+        std::memcpy(G.hl.data() + 2 * G.bi[(size_t)q].in0, x.locs, (size_t)x.n * 2 * sizeof(double));
+        std::memcpy(G.hz.data() + G.bi[(size_t)q].in0, x.z, (size_t)x.n * sizeof(double));
+    }
+    // ---- buffers -----------------------------------------------------------------------------------
+    const size_t sz[13] = {G.hl.size() * sizeof(double), G.hz.size() * sizeof(double), G.hl.size() * sizeof(double),
+                           3 * (size_t)vec * sizeof(double), (size_t)units * sizeof(float),
+                           (size_t)lv * te * sizeof(double), (size_t)prt * sizeof(double),
+                           (size_t)tl * sizeof(int), 2 * sizeof(int), (size_t)gc * sizeof(BatchInst),
+                           G.tasks.size() * sizeof(BatchTask), (size_t)gc * 3 * sizeof(double),
+                           (size_t)gc * sizeof(unsigned long long)};
+    void *ptr[13];
+    if (fixed) {   // carved from the fixed array, 256-byte aligned
+        size_t off = 0;
+        for (int q = 0; q < 13; ++q) {
+            ptr[q] = arena + off;
+            off += align256(sz[q]);
+        }
+        if (off > arena_bytes) return MPGEO_E_TOO_LARGE;   // (the packing rule keeps it inside)
+    } else {   // grow only; growing waits for the device
+        DevBuf *bufs[13] = {&ctx->q_in_locs, &ctx->q_in_z, &ctx->q_locs, &ctx->q_vec, &ctx->q_tiles,
+                            &ctx->q_linv, &ctx->q_parts, &ctx->q_flags, &ctx->q_ctrl, &ctx->q_insts,
+                            &ctx->q_tasks, &ctx->q_res, &ctx->q_info};
+        for (int q = 0; q < 13; ++q) {
+            MPGEO_TRY(bufs[q]->ensure(sz[q]));
+            ptr[q] = bufs[q]->ptr;
+        }
+    }
+    double *in_locs = static_cast<double *>(ptr[0]), *in_z = static_cast<double *>(ptr[1]);
+    double *q_locs = static_cast<double *>(ptr[2]), *q_vec = static_cast<double *>(ptr[3]);
+    int *q_flags = static_cast<int *>(ptr[7]), *q_ctrl = static_cast<int *>(ptr[8]);
+    BatchInst *q_insts = static_cast<BatchInst *>(ptr[9]);
+    BatchTask *q_tasks = static_cast<BatchTask *>(ptr[10]);
+    G.res = static_cast<double *>(ptr[11]);
+    G.info = static_cast<unsigned long long *>(ptr[12]);
+    G.ctrl = q_ctrl;
+    MPGEO_HIP(hipMemcpyAsync(in_locs, G.hl.data(), sz[0], hipMemcpyHostToDevice, s));
+    MPGEO_HIP(hipMemcpyAsync(in_z, G.hz.data(), sz[1], hipMemcpyHostToDevice, s));
+    MPGEO_HIP(hipMemcpyAsync(q_insts, G.bi.data(), sz[9], hipMemcpyHostToDevice, s));
+    MPGEO_HIP(hipMemcpyAsync(q_tasks, G.tasks.data(), sz[10], hipMemcpyHostToDevice, s));
+    if (fixed) {   // the array keeps the previous call's contents: clear flags, counter, info
+        launch_fill_u32(reinterpret_cast<uint32_t *>(q_flags), 0u, (size_t)tl, s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(q_ctrl), 0u, 2, s);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(G.info), ~0u, 2 * (size_t)gc, s);
+        MPGEO_HIP(hipGetLastError());
+    } else {
+        MPGEO_HIP(hipMemsetAsync(q_flags, 0, sz[7], s));
+        MPGEO_HIP(hipMemsetAsync(q_ctrl, 0, sz[8], s));
+        MPGEO_HIP(hipMemsetAsync(G.info, 0xFF, sz[12], s));
+    }
+    launch_batch_order(q_insts, gc, max_n, in_locs, in_z, q_locs, q_vec,
+                       true, (plan.flags & MPGEO_DIST_GCD) != 0, s);   // always ordered, as a lane would
+    MPGEO_HIP(hipGetLastError());
+    QueueArgs qa{};
+    qa.tasks = q_tasks;
+    qa.ntasks = (int64_t)G.tasks.size();
+    qa.insts = q_insts;
+    qa.locs = q_locs;
+    qa.z = q_vec;
+    qa.r = q_vec + vec;
+    qa.y = q_vec + 2 * vec;
+    qa.tiles = static_cast<float *>(ptr[4]);
+    qa.linv = static_cast<double *>(ptr[5]);
+    qa.parts = static_cast<double *>(ptr[6]);
+    qa.flags = q_flags;
+    qa.head = reinterpret_cast<unsigned *>(q_ctrl);
+    qa.abort_flag = q_ctrl + 1;
+    qa.info = G.info;
+    qa.result = G.res;
+    qa.profile = (plan.flags & MPGEO_PROFILE) ? 1 : 0;
+    qa.spin_limit = 8 << 20;   // about 2 s of sleeps per wait
+    const int cus = ctx->cus > 0 ? ctx->cus : 256;
+    const int cap = max_workgroups > 0 ? std::min(max_workgroups, cus) : cus;
+    const int wgs = (int)std::min<int64_t>((int64_t)G.tasks.size(), (int64_t)cap);
+    launch_batch_queue(qa, wgs, s);
+    MPGEO_HIP(hipGetLastError());
+    return MPGEO_OK;
+}
+
 static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
                        mpgeo_result *out, int32_t *tiles, char *arena, size_t arena_bytes,
                        const int32_t *bands) {
-    const int64_t te = (int64_t)kQueueTile * kQueueTile;
-    auto p_of = [&](int64_t q) { return (inst[q].n + kQueueTile - 1) / kQueueTile; };
-    auto tiles_of = [&](int64_t q) {
-        const int64_t p = p_of(q);
-        return p * (p + 1) / 2;
-    };
-    // FP64 band of problem q in tiles: the plan's (or the tuned one), capped at p (every tile)
-    auto band_of = [&](int64_t q) {
-        const int64_t p = p_of(q);
-        const int32_t b = bands ? bands[q] : plan.band64;
-        return (int32_t)((b < 0 || b > p) ? p : b);
-    };
-    // bytes of the tiles of problem q: FP64 tiles 8 bytes per entry, FP32 tiles 4
-    auto tile_bytes = [&](int64_t q) { return (size_t)queue_tile_units(p_of(q), 0, band_of(q)) * sizeof(float); };
-    // bytes of every work buffer problem q adds to a group (the fixed array's packing rule)
-    auto prob_bytes = [&](int64_t q) {
-        const int64_t n = inst[q].n, p = p_of(q), tl = tiles_of(q);
-        return (size_t)n * 5 * sizeof(double) +                    // packed inputs, ordered sites
-               (size_t)3 * p * kQueueTile * sizeof(double) +        // z, r, y (padded)
-               tile_bytes(q) + (size_t)p * te * sizeof(double) +     // tiles, diagonal inverses
-               (size_t)2 * p * sizeof(double) +                     // logdet / quad parts
-               (size_t)tl * (sizeof(int) + sizeof(BatchTask)) +     // done flags, tasks
-               sizeof(BatchInst) + 3 * sizeof(double) + sizeof(unsigned long long);
-    };
-    constexpr size_t kSlack = 13 * 256 + 2 * sizeof(int);            // alignment of 13 buffers, control
+    std::vector<int32_t> band((size_t)count);
+    for (int64_t q = 0; q < count; ++q) band[(size_t)q] = bands ? bands[q] : plan.band64;
     const bool fixed = arena != nullptr;
     size_t budget = 0;
     if (fixed) {
         for (int64_t q = 0; q < count; ++q)
-            if (prob_bytes(q) + kSlack > arena_bytes) return MPGEO_E_TOO_LARGE;   // beyond the array
+            if (queue_prob_bytes(inst[q].n, band[(size_t)q]) + kQueueSlack > arena_bytes)
+                return MPGEO_E_TOO_LARGE;   // beyond the array
     } else {
+        const int64_t te = (int64_t)kQueueTile * kQueueTile;
         size_t free_b = 0, total_b = 0;
         MPGEO_HIP(hipMemGetInfo(&free_b, &total_b));
         // tiles dominate: keep a group's tiles within half of the free memory (the buffers of an
@@ -2015,139 +2180,38 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         if (ctx->hbm_budget > 0) {   // the context's cap: every problem must fit in it alone
             budget = std::min(budget, ctx->hbm_budget);
             for (int64_t q = 0; q < count; ++q)
-                if (tile_bytes(q) > budget) return MPGEO_E_NOMEM;
+                if (queue_tile_bytes(inst[q].n, band[(size_t)q]) > budget) return MPGEO_E_NOMEM;
         }
     }
-    const int cus = ctx->cus > 0 ? ctx->cus : 256;
     hipStream_t s = ctx->stream;
     int status = MPGEO_OK;
     for (int64_t g0 = 0; g0 < count;) {
-        // ---- group [g0, g1) and its layout -------------------------------------------------------
+        // ---- group [g0, g1) ------------------------------------------------------------------------
         int64_t g1 = g0;
-        size_t gbytes = kSlack, tbytes = 0;
+        size_t gbytes = kQueueSlack, tbytes = 0;
         if (fixed) {
-            while (g1 < count && gbytes + prob_bytes(g1) <= arena_bytes) gbytes += prob_bytes(g1++);
+            while (g1 < count && gbytes + queue_prob_bytes(inst[g1].n, band[(size_t)g1]) <= arena_bytes) {
+                gbytes += queue_prob_bytes(inst[g1].n, band[(size_t)g1]);
+                ++g1;
+            }
         } else {
-            while (g1 < count && (g1 == g0 || tbytes + tile_bytes(g1) <= budget)) tbytes += tile_bytes(g1++);
+            while (g1 < count && (g1 == g0 || tbytes + queue_tile_bytes(inst[g1].n, band[(size_t)g1]) <= budget)) {
+                tbytes += queue_tile_bytes(inst[g1].n, band[(size_t)g1]);
+                ++g1;
+            }
         }
         const int64_t gc = g1 - g0;
-        std::vector<BatchInst> bi((size_t)gc);
-        int64_t pts = 0, tl = 0, lv = 0, vec = 0, prt = 0, units = 0;
-        int max_n = 1, max_p = 1;
-        for (int64_t q = 0; q < gc; ++q) {
-            const mpgeo_instance &x = inst[g0 + q];
-            BatchInst &b = bi[(size_t)q];
-            b.n = x.n;
-            b.p = (int32_t)((x.n + kQueueTile - 1) / kQueueTile);
-            b.band = band_of(g0 + q);
-            b.in0 = pts;
-            b.tile0 = units;
-            b.flag0 = tl;
-            b.linv0 = lv;
-            b.vec0 = vec;
-            b.part0 = prt;
-            b.mp = make_matern_params((plan.flags & MPGEO_PROFILE) ? 1.0 : x.theta.sigma2, x.theta.beta, x.theta.nu);
-            b.mp.gcd = (plan.flags & MPGEO_DIST_GCD) ? 1 : 0;
-            pts += x.n;
-            tl += (int64_t)b.p * (b.p + 1) / 2;
-            units += queue_tile_units(b.p, 0, b.band);
-            lv += b.p;
-            vec += (int64_t)b.p * kQueueTile;
-            prt += 2 * (int64_t)b.p;
-            max_n = std::max<int>(max_n, (int)x.n);
-            max_p = std::max<int>(max_p, b.p);
-        }
-        // tasks: column by column; in a column the diagonal tiles of every problem, then the rest
-        std::vector<BatchTask> tasks;
-        tasks.reserve((size_t)tl);
-        for (int j = 0; j < max_p; ++j) {
-            for (int64_t q = 0; q < gc; ++q)
-                if (j < bi[(size_t)q].p) tasks.push_back({(int32_t)q, j, j, 0});
-            for (int64_t q = 0; q < gc; ++q)
-                for (int i = j + 1; i < bi[(size_t)q].p; ++i) tasks.push_back({(int32_t)q, i, j, 0});
-        }
-        std::vector<double> hl((size_t)pts * 2), hz((size_t)pts);
-        for (int64_t q = 0; q < gc; ++q) {
-            const mpgeo_instance &x = inst[g0 + q];
-            std::memcpy(hl.data() + 2 * bi[(size_t)q].in0, x.locs, (size_t)x.n * 2 * sizeof(double));
-            std::memcpy(hz.data() + bi[(size_t)q].in0, x.z, (size_t)x.n * sizeof(double));
-        }
-        // ---- buffers -------------------------------------------------------------------------------
-        const size_t sz[13] = {hl.size() * sizeof(double), hz.size() * sizeof(double), hl.size() * sizeof(double),
-                               3 * (size_t)vec * sizeof(double), (size_t)units * sizeof(float),
-                               (size_t)lv * te * sizeof(double), (size_t)prt * sizeof(double),
-                               (size_t)tl * sizeof(int), 2 * sizeof(int), (size_t)gc * sizeof(BatchInst),
-                               tasks.size() * sizeof(BatchTask), (size_t)gc * 3 * sizeof(double),
-                               (size_t)gc * sizeof(unsigned long long)};
-        void *ptr[13];
-        if (fixed) {   // carved from the fixed array, 256-byte aligned
-            size_t off = 0;
-            for (int q = 0; q < 13; ++q) {
-                ptr[q] = arena + off;
-                off += align256(sz[q]);
-            }
-            if (off > arena_bytes) return MPGEO_E_TOO_LARGE;   // (the packing rule keeps it inside)
-        } else {   // grow only; growing waits for the device
-            DevBuf *bufs[13] = {&ctx->q_in_locs, &ctx->q_in_z, &ctx->q_locs, &ctx->q_vec, &ctx->q_tiles,
-                                &ctx->q_linv, &ctx->q_parts, &ctx->q_flags, &ctx->q_ctrl, &ctx->q_insts,
-                                &ctx->q_tasks, &ctx->q_res, &ctx->q_info};
-            for (int q = 0; q < 13; ++q) {
-                MPGEO_TRY(bufs[q]->ensure(sz[q]));
-                ptr[q] = bufs[q]->ptr;
-            }
-        }
-        double *in_locs = static_cast<double *>(ptr[0]), *in_z = static_cast<double *>(ptr[1]);
-        double *q_locs = static_cast<double *>(ptr[2]), *q_vec = static_cast<double *>(ptr[3]);
-        int *q_flags = static_cast<int *>(ptr[7]), *q_ctrl = static_cast<int *>(ptr[8]);
-        BatchInst *q_insts = static_cast<BatchInst *>(ptr[9]);
-        BatchTask *q_tasks = static_cast<BatchTask *>(ptr[10]);
-        double *q_res = static_cast<double *>(ptr[11]);
-        unsigned long long *q_info = static_cast<unsigned long long *>(ptr[12]);
-        MPGEO_HIP(hipMemcpyAsync(in_locs, hl.data(), sz[0], hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemcpyAsync(in_z, hz.data(), sz[1], hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemcpyAsync(q_insts, bi.data(), sz[9], hipMemcpyHostToDevice, s));
-        MPGEO_HIP(hipMemcpyAsync(q_tasks, tasks.data(), sz[10], hipMemcpyHostToDevice, s));
-        if (fixed) {   // the array keeps the previous call's contents: clear flags, counter, info
-            launch_fill_u32(reinterpret_cast<uint32_t *>(q_flags), 0u, (size_t)tl, s);
-            launch_fill_u32(reinterpret_cast<uint32_t *>(q_ctrl), 0u, 2, s);
-            launch_fill_u32(reinterpret_cast<uint32_t *>(q_info), ~0u, 2 * (size_t)gc, s);
-            MPGEO_HIP(hipGetLastError());
-        } else {
-            MPGEO_HIP(hipMemsetAsync(q_flags, 0, sz[7], s));
-            MPGEO_HIP(hipMemsetAsync(q_ctrl, 0, sz[8], s));
-            MPGEO_HIP(hipMemsetAsync(q_info, 0xFF, sz[12], s));
-        }
-        launch_batch_order(q_insts, gc, max_n, in_locs, in_z, q_locs, q_vec,
-                           true, (plan.flags & MPGEO_DIST_GCD) != 0, s);   // always ordered, as a lane would
-        MPGEO_HIP(hipGetLastError());
-        QueueArgs qa{};
-        qa.tasks = q_tasks;
-        qa.ntasks = (int64_t)tasks.size();
-        qa.insts = q_insts;
-        qa.locs = q_locs;
-        qa.z = q_vec;
-        qa.r = q_vec + vec;
-        qa.y = q_vec + 2 * vec;
-        qa.tiles = static_cast<float *>(ptr[4]);
-        qa.linv = static_cast<double *>(ptr[5]);
-        qa.parts = static_cast<double *>(ptr[6]);
-        qa.flags = q_flags;
-        qa.head = reinterpret_cast<unsigned *>(q_ctrl);
-        qa.abort_flag = q_ctrl + 1;
-        qa.info = q_info;
-        qa.result = q_res;
-        qa.profile = (plan.flags & MPGEO_PROFILE) ? 1 : 0;
-        qa.spin_limit = 8 << 20;   // about 2 s of sleeps per wait
-        const int wgs = (int)std::min<int64_t>((int64_t)tasks.size(), (int64_t)cus);
-        launch_batch_queue(qa, wgs, s);
-        MPGEO_HIP(hipGetLastError());
+        std::vector<const mpgeo_instance *> members((size_t)gc);
+        for (int64_t q = 0; q < gc; ++q) members[(size_t)q] = inst + g0 + q;
+        QueueGroup G;
+        MPGEO_TRY(queue_group_enqueue(ctx, s, members.data(), gc, band.data() + g0, plan, arena, arena_bytes, G));
         std::vector<double> res((size_t)gc * 3);
         std::vector<unsigned long long> info((size_t)gc);
         int ctrl[2] = {0, 0};
-        MPGEO_HIP(hipMemcpyAsync(res.data(), q_res, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        MPGEO_HIP(hipMemcpyAsync(info.data(), q_info, info.size() * sizeof(unsigned long long),
+        MPGEO_HIP(hipMemcpyAsync(res.data(), G.res, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipMemcpyAsync(info.data(), G.info, info.size() * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, s));
-        MPGEO_HIP(hipMemcpyAsync(ctrl, q_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, s));
+        MPGEO_HIP(hipMemcpyAsync(ctrl, G.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost, s));
         MPGEO_HIP(hipStreamSynchronize(s));
         if (ctrl[1] != 0) return MPGEO_E_DEVICE;   // a wait timed out
         for (int64_t q = 0; q < gc; ++q) {
@@ -2157,7 +2221,7 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
             o.logdet = res[(size_t)q * 3 + 1];
             o.quad = res[(size_t)q * 3 + 2];
             o.info = (info[(size_t)q] == ~0ull) ? -1 : (int64_t)info[(size_t)q];
-            o.band64 = bi[(size_t)q].band >= bi[(size_t)q].p - 1 ? -1 : bi[(size_t)q].band;
+            o.band64 = G.bi[(size_t)q].band >= G.bi[(size_t)q].p - 1 ? -1 : G.bi[(size_t)q].band;
             o.band32 = o.band0 = -1;
             if (o.info >= 0) status = MPGEO_E_NOT_SPD;
             if (tiles) tiles[g0 + q] = kQueueTile;
@@ -2307,6 +2371,7 @@ struct ServedDataset {
     int64_t n = 0;
     std::vector<double> locs, z;       // host copies (re-uploaded after an eviction)
     mpgeo_plan plan{};
+    bool queued = false;               // likelihood requests go through the persistent queue
     size_t footprint = 0;
     mpgeo_dataset *ds = nullptr;       // resident device state, or nullptr
     bool busy = false;
@@ -2353,6 +2418,12 @@ int mpgeo_server_add_dataset(mpgeo_server *srv, int64_t n, const double *locs, c
     if (!srv || !locs || !z || !id || n < 1 || n > (int64_t)0xFFFFFFFF) return MPGEO_E_ARG;
     if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
     if (plan.flags & MPGEO_ESCALATE) return MPGEO_E_UNSUPPORTED;
+    const bool queued = (plan.flags & MPGEO_BATCH_QUEUE) != 0;
+    if (queued) {   // likelihood requests through the persistent queue: its plans and sizes only
+        if (plan.tile == 0) plan.tile = kQueueTile;
+        MPGEO_TRY(queue_plan_ok(plan));
+        if (n > kQueueMaxN) return MPGEO_E_UNSUPPORTED;
+    }
     MPGEO_TRY(check_plan(plan));
     if (!all_finite(locs, 2 * (size_t)n) || !all_finite(z, (size_t)n)) return MPGEO_E_ARG;
     ServedDataset d;
@@ -2360,7 +2431,9 @@ int mpgeo_server_add_dataset(mpgeo_server *srv, int64_t n, const double *locs, c
     d.locs.assign(locs, locs + 2 * n);
     d.z.assign(z, z + n);
     d.plan = plan;
-    d.footprint = mpgeo_footprint_bytes(n, plan);
+    d.queued = queued;
+    d.plan.flags &= ~(uint32_t)MPGEO_BATCH_QUEUE;   // the lane plan (kriging requests)
+    d.footprint = mpgeo_footprint_bytes(n, d.plan);
     if (d.footprint > srv->budget) return MPGEO_E_NOMEM;   // could never be admitted
     srv->sets.push_back(std::move(d));
     *id = (int32_t)(srv->sets.size() - 1);
@@ -2461,6 +2534,22 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
             return MPGEO_E_DEVICE;
         }
     for (int64_t i = 0; i < nreq; ++i) out[i] = mpgeo_served{};
+    // the persistent queue: one batch of likelihood requests of queued datasets in flight at a
+    // time, on the context's own stream (the lanes are sub-contexts with streams of their own)
+    struct QueueState {
+        bool busy = false;
+        std::vector<int64_t> reqs;
+        QueueGroup group;
+        hipEvent_t done = nullptr;
+    } qs;
+    // the queue's persistent workgroups wait on dependencies between tasks: a quarter of the
+    // compute units at most, so that the lanes' factorizations beside it keep the rest
+    const int queue_wgs = std::max(8, (ctx->cus > 0 ? ctx->cus : 256) / 4);
+    if (hipEventCreateWithFlags(&qs.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        for (auto &l : lanes) (void)hipEventDestroy(l.done);
+        return MPGEO_E_DEVICE;
+    }
     std::deque<int64_t> ready;
     size_t next = 0;
     int64_t finished = 0;
@@ -2487,6 +2576,77 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
             ++finished;
             progressed = true;
         }
+        if (qs.busy && status == MPGEO_OK) {
+            const hipError_t q = hipEventQuery(qs.done);
+            if (q == hipSuccess) {
+                int ctrl[2] = {0, 0};
+                MPGEO_HIP(hipMemcpy(ctrl, qs.group.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost));
+                if (ctrl[1] != 0) status = MPGEO_E_DEVICE;   // a wait in the queue timed out
+                const double tf = now();
+                for (int64_t r : qs.reqs) out[r].finish_s = tf;
+                finished += (int64_t)qs.reqs.size();
+                qs.reqs.clear();
+                qs.busy = false;
+                progressed = true;
+            } else if (q != hipErrorNotReady) {
+                (void)hipGetLastError();
+                status = MPGEO_E_DEVICE;
+            }
+        }
+        // dispatch to the queue: every ready likelihood request of a queued dataset (with the
+        // first one's distance and likelihood form), up to a quarter of the budget in tiles,
+        // as one persistent launch
+        if (!qs.busy && status == MPGEO_OK) {
+            std::vector<mpgeo_instance> members;
+            std::vector<int32_t> bands;
+            uint32_t form = 0;
+            size_t bytes = 0;
+            for (auto it = ready.begin(); it != ready.end();) {
+                const ServedRequest &rq = srv->reqs[*it];
+                const ServedDataset &d = srv->sets[rq.dataset];
+                const uint32_t f = d.plan.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD);
+                const size_t b = queue_tile_bytes(d.n, d.plan.band64);
+                if (!d.queued || rq.m > 0 || (!members.empty() && (f != form || bytes + b > srv->budget / 4))) {
+                    ++it;
+                    continue;
+                }
+                form = f;
+                bytes += b;
+                mpgeo_theta th = rq.theta;
+                if (f & MPGEO_PROFILE) th.sigma2 = 1.0;
+                members.push_back(mpgeo_instance{d.n, d.locs.data(), d.z.data(), th});
+                bands.push_back(d.plan.band64);
+                qs.reqs.push_back(*it);
+                it = ready.erase(it);
+            }
+            if (!members.empty()) {
+                std::vector<const mpgeo_instance *> mp(members.size());
+                for (size_t q = 0; q < members.size(); ++q) mp[q] = &members[q];
+                mpgeo_plan qp{};
+                qp.tile = kQueueTile;
+                qp.flags = form;
+                const double ts = now();
+                for (int64_t r : qs.reqs) out[r].start_s = ts;
+                status = queue_group_enqueue(ctx, ctx->stream, mp.data(), (int64_t)mp.size(), bands.data(), qp,
+                                             nullptr, 0, qs.group, queue_wgs);
+                for (size_t q = 0; q < qs.reqs.size() && status == MPGEO_OK; ++q) {
+                    double *slot = res + 4 * qs.reqs[q];
+                    if (hipMemcpyAsync(slot, qs.group.res + 3 * q, 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                                       ctx->stream) != hipSuccess ||
+                        hipMemcpyAsync(slot + 3, qs.group.info + q, sizeof(double), hipMemcpyDeviceToDevice,
+                                       ctx->stream) != hipSuccess) {
+                        (void)hipGetLastError();
+                        status = MPGEO_E_DEVICE;
+                    }
+                }
+                if (status == MPGEO_OK && hipEventRecord(qs.done, ctx->stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    status = MPGEO_E_DEVICE;
+                }
+                qs.busy = status == MPGEO_OK;
+                progressed = true;
+            }
+        }
         // dispatch: oldest ready request whose dataset is idle (and resident or admissible)
         for (int li = 0; li < srv->nlanes && status == MPGEO_OK; ++li) {
             LaneState &l = lanes[(size_t)li];
@@ -2494,7 +2654,7 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
             auto it = ready.begin();
             for (; it != ready.end(); ++it) {
                 ServedDataset &d = srv->sets[srv->reqs[*it].dataset];
-                if (d.busy) continue;
+                if (d.busy || (d.queued && srv->reqs[*it].m == 0)) continue;
                 if (d.ds || server_admit(srv, d.footprint)) break;
             }
             if (it == ready.end()) break;
@@ -2551,7 +2711,9 @@ int mpgeo_server_run(mpgeo_server *srv, mpgeo_served *out) {
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamSynchronize(c->stream);
     }
+    (void)hipStreamSynchronize(ctx->stream);
     for (auto &l : lanes) (void)hipEventDestroy(l.done);
+    (void)hipEventDestroy(qs.done);
     if (status != MPGEO_OK) return status;
     std::vector<double> host((size_t)nreq * 4);
     MPGEO_HIP(hipMemcpy(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost));

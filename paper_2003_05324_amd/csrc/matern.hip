@@ -62,11 +62,15 @@ struct MaternSource {
     MaternParams mp;
     double xr, yr, cr;          // row site: x, y (great-circle: lon in degrees, lat in radians, cos lat)
     double *sx, *sy, *sc;       // shared column sites, same convention
+    const MaternTable *tab;     // smoothness-only factors of K_mu (read for general smoothness only)
     __device__ void prepare_cols(const TileIJ &, int, const int64_t *gcol) {
         __shared__ double cx[kCovCols], cy[kCovCols], ccs[kCovCols];
+        __shared__ MaternTable mtab;
         sx = cx;
         sy = cy;
         sc = ccs;
+        tab = &mtab;
+        if (mp.mode == 0 && mp.mu != -0.5) matern_table_build(mp.mu, mtab);
         if (threadIdx.x < kCovCols) {
             const int64_t g = gcol[threadIdx.x];
             const double x = g >= 0 ? locs[2 * g] : 0.0;
@@ -88,10 +92,10 @@ struct MaternSource {
     }
     __device__ double value(int64_t gr, int cc, int64_t gc) const {
         if (gr == gc) return mp.sigma2;
-        if (mp.gcd) return matern_cov(haversine(sx[cc] - xr, yr, cr, sy[cc], sc[cc]), mp);
+        if (mp.gcd) return matern_cov_tab(haversine(sx[cc] - xr, yr, cr, sy[cc], sc[cc]), mp, *tab);
         const double dx = xr - sx[cc];
         const double dy = yr - sy[cc];
-        return matern_cov(sqrt(dx * dx + dy * dy), mp);
+        return matern_cov_tab(sqrt(dx * dx + dy * dy), mp, *tab);
     }
 };
 

@@ -92,8 +92,101 @@ __device__ void bessel_k_large_scaled(double mu, double x, double &k0s, double &
     k1s = k0s / x * (x + mu + 0.5 + (m2 - 0.25) * up1 / u);
 }
 
-// C(r; theta) of eq. (1); C(0) = sigma2 (the r -> 0 limit).
-__device__ inline double matern_cov(double r, const MaternParams &mp) {
+// The quantities of the two K_mu evaluations above that depend on the smoothness only, formed
+// once per workgroup (in LDS) so that the per-entry loops multiply instead of divide:
+//   Miller:  C_k = prod_{t <= k} ((t - 1/2)^2 - mu^2) / t and 1 / ((k - 1/2)^2 - mu^2);
+//   Temme:   Gamma1, Gamma2, Gamma(1 + mu), Gamma(1 - mu), pi mu / sin(pi mu), and
+//            1 / (k^2 - mu^2), 1 / (k - mu), 1 / (k + mu), 1 / k.
+struct MaternTable {
+    static constexpr int kMiller = 91;   // k = 0 .. 90 (the largest start of the recurrence)
+    static constexpr int kSeries = 64;   // k = 1 .. 63 (the series' longest run)
+    double ck[kMiller], ia[kMiller];
+    double isq[kSeries], im[kSeries], ip[kSeries], ik[kSeries];
+    double g1, g2, gp, gm, fact;
+};
+
+// Built by all threads of the workgroup; the caller synchronises before use.
+__device__ inline void matern_table_build(double mu, MaternTable &t) {
+    const double m2 = mu * mu;
+    for (int k = threadIdx.x; k < MaternTable::kMiller; k += blockDim.x) {
+        const double h = k - 0.5;
+        t.ia[k] = (k == 0) ? 0.0 : 1.0 / (h * h - m2);
+        double c = 1.0;
+        for (int q = 1; q <= k; ++q) {
+            const double hq = q - 0.5;
+            c *= (hq * hq - m2) / q;
+        }
+        t.ck[k] = c;
+    }
+    for (int k = threadIdx.x; k < MaternTable::kSeries; k += blockDim.x) {
+        const double dk = (double)k;
+        t.isq[k] = (k == 0) ? 0.0 : 1.0 / (dk * dk - m2);
+        t.im[k] = (k == 0) ? 0.0 : 1.0 / (dk - mu);
+        t.ip[k] = (k == 0) ? 0.0 : 1.0 / (dk + mu);
+        t.ik[k] = (k == 0) ? 0.0 : 1.0 / dk;
+    }
+    if (threadIdx.x == 0) {
+        temme_gammas(mu, t.g1, t.g2);
+        t.gp = 1.0 / (t.g2 - mu * t.g1);
+        t.gm = 1.0 / (t.g2 + mu * t.g1);
+        t.fact = (mu == 0.0) ? 1.0 : (kPi * mu) / sinpi(mu);
+    }
+}
+
+// bessel_k_small with the smoothness-only quantities from the table.
+__device__ inline void bessel_k_small_tab(double mu, double x, const MaternTable &t, double &k0, double &k1) {
+    const double lg = log(2.0 / x);
+    const double sig = mu * lg;
+    const double fact2 = (sig == 0.0) ? 1.0 : sinh(sig) / sig;
+    double f = t.fact * (cosh(sig) * t.g1 + fact2 * lg * t.g2);
+    const double e = exp(sig);
+    double p = 0.5 * e * t.gp;
+    double q = 0.5 / e * t.gm;
+    double c = 1.0;
+    const double d = 0.25 * x * x;
+    double s0 = f, s1 = p;
+    for (int k = 1; k < MaternTable::kSeries; ++k) {
+        const double dk = (double)k;
+        f = (dk * f + p + q) * t.isq[k];
+        c *= d * t.ik[k];
+        p *= t.im[k];
+        q *= t.ip[k];
+        const double h = p - dk * f;
+        const double t0 = c * f, t1 = c * h;
+        s0 += t0;
+        s1 += t1;
+        if (fabs(t0) < 1e-17 * fabs(s0) && fabs(t1) < 1e-17 * fabs(s1)) break;
+    }
+    k0 = s0;
+    k1 = s1 * 2.0 / x;
+}
+
+// bessel_k_large_scaled with C_kmax and the recurrence's reciprocals from the table.
+__device__ inline void bessel_k_large_scaled_tab(double mu, double x, const MaternTable &t, double &k0s,
+                                                 double &k1s) {
+    const double m2 = mu * mu;
+    int kmax = 20 + (int)(130.0 / x);
+    if (kmax > 90) kmax = 90;
+    double ck = t.ck[kmax];
+    double up1 = 0.0, u = 1.0;
+    double s = ck * u;
+    for (int k = kmax; k >= 1; --k) {
+        const double kh = k + 0.5;
+        const double um1 = 2.0 * (k + x) * u - (kh * kh - m2) * up1;
+        up1 = u;
+        u = um1;
+        ck *= k * t.ia[k];   // C_{k-1}
+        s += ck * u;
+    }
+    k0s = sqrt(kPi / (2.0 * x)) / (s / u);
+    k1s = k0s / x * (x + mu + 0.5 + (m2 - 0.25) * up1 / u);
+}
+
+// C(r; theta) of eq. (1); C(0) = sigma2 (the r -> 0 limit).  With a table (general
+// smoothness; a table must be given then), the K_mu loops take their smoothness-only factors
+// from it.
+template <bool kTable>
+__device__ inline double matern_cov_impl(double r, const MaternParams &mp, const MaternTable *tab) {
     if (r == 0.0) return mp.sigma2;
     const double x = r / mp.beta;
     switch (mp.mode) {
@@ -111,10 +204,12 @@ __device__ inline double matern_cov(double r, const MaternParams &mp) {
         k1 = k0 * (1.0 + 1.0 / x);
         scaled = true;
     } else if (x <= 2.0) {
-        bessel_k_small(mu, x, k0, k1);
+        if constexpr (kTable) bessel_k_small_tab(mu, x, *tab, k0, k1);
+        else bessel_k_small(mu, x, k0, k1);
         scaled = false;
     } else {
-        bessel_k_large_scaled(mu, x, k0, k1);
+        if constexpr (kTable) bessel_k_large_scaled_tab(mu, x, *tab, k0, k1);
+        else bessel_k_large_scaled(mu, x, k0, k1);
         scaled = true;
     }
     for (int i = 1; i <= mp.nl; ++i) {
@@ -124,6 +219,13 @@ __device__ inline double matern_cov(double r, const MaternParams &mp) {
     }
     if (scaled) return mp.pref * exp(mp.nu * log(x) - x) * k0;
     return mp.pref * pow(x, mp.nu) * k0;
+}
+
+__device__ inline double matern_cov(double r, const MaternParams &mp) {
+    return matern_cov_impl<false>(r, mp, nullptr);
+}
+__device__ inline double matern_cov_tab(double r, const MaternParams &mp, const MaternTable &tab) {
+    return matern_cov_impl<true>(r, mp, &tab);
 }
 
 constexpr double kDegToRad = 3.14159265358979323846 / 180.0;

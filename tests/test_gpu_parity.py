@@ -68,7 +68,9 @@ def test_morton_permutation_is_bit_exact(small_ds):
 
 
 @pytest.mark.parametrize("theta,band", [((1.0, 0.1, 0.5), 2), ((1.3, 0.2, 0.73), 1),
-                                        ((0.9, 0.05, 1.0), 0), ((1.0, 0.1, 1.5), -1)])
+                                        ((0.9, 0.05, 1.0), 0), ((1.0, 0.1, 1.5), -1),
+                                        ((1.0, 0.1, 0.3), -1), ((0.8, 0.3, 2.2), -1),
+                                        ((1.1, 0.02, 0.49), 2)])
 def test_covariance_entries(small_ds, theta, band):
     locs, _ = small_case()
     tile = SMALL.tile
@@ -305,6 +307,26 @@ def test_mle_matches_oracle(lib, small_ds, band):
     fit = small_ds.mle(start, SMALL.tile, band)
     for got, want in zip(fit["theta"], gold["theta_hat"]):
         assert abs(got - want) / abs(want) <= 1e-3, (fit, gold)
+
+
+def test_mle_trace_is_the_search(lib, small_ds):
+    # the recorded trajectory is the search itself: same fit as mpgeo_dataset_mle, one entry per
+    # evaluation starting at the start point, the fit's log-likelihood its best entry, and each
+    # entry the log-likelihood a separate evaluation of that theta gives, bit for bit
+    start = [min(max(t * s, lo), hi) for t, s, lo, hi in
+             zip(SMALL.theta, oracle.mle.START_SCALE, oracle.mle.LOWER, oracle.mle.UPPER)]
+    fit = small_ds.mle(start, SMALL.tile, 2, xtol=1e-4)
+    tr = small_ds.mle_trace(start, SMALL.tile, 2, xtol=1e-4)
+    assert tr["theta"] == fit["theta"] and tr["loglik"] == fit["loglik"] and tr["evals"] == fit["evals"]
+    assert len(tr["trace"]) == tr["evals"] and tr["evals"] >= 4
+    assert np.allclose(tr["trace"][0], start, rtol=1e-14, atol=0)
+    best = int(np.argmax(tr["trace_loglik"]))
+    assert tr["trace_loglik"][best] == fit["loglik"]
+    assert np.allclose(tr["trace"][best], fit["theta"], rtol=1e-14, atol=0)
+    for e in (0, tr["evals"] // 2, tr["evals"] - 1):
+        assert small_ds.loglik(tr["trace"][e], SMALL.tile, 2)["loglik"] == tr["trace_loglik"][e]
+    with pytest.raises(lib.MpgeoError):
+        small_ds.mle_trace(start, SMALL.tile, 2, max_evals=3)
 
 
 # ---- third precision tier (16-bit operands for the farthest tiles) -------------------------

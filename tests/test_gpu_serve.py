@@ -117,3 +117,56 @@ def test_three_tier_served_results_equal_isolated_evaluations(lib):
         assert abs(r["loglik"] - want) / max(abs(want), sizes[d]) <= 20 * 2.0 ** -11
     srv.close()
     ctx.close()
+
+
+def test_queued_requests_batch_in_one_launch_and_equal_alone(lib):
+    # small datasets registered for the persistent queue: their ready likelihood requests are
+    # batched into queue launches beside the lanes' evaluations of the other datasets.  Every
+    # queued result equals the same problem queued alone (each problem's tasks have a fixed
+    # order whatever else is in the launch), bit for bit, and the oracle within the band bar;
+    # kriging requests on a queued dataset run on a lane (the factor stays resident there)
+    ctx = lib.Context(0)
+    sizes = [250, 600, 1000, 1400, 2600]
+    data = []
+    for q, n in enumerate(sizes):
+        locs = jittered_grid(int(np.ceil(np.sqrt(n))), 110 + q)[:n].copy()
+        data.append((locs, oracle.simulate_field(locs, (1.0, 0.1, 0.5), normals(n, 120 + q))))
+    srv = lib.Server(ctx, hbm_budget_bytes=1 << 34, lanes=2)
+    queued = [True, True, True, True, False]
+    bands = [1, -1, 2, 1, 1]
+    ids = [srv.add_dataset(locs, z, 128, b, queue=qd) for (locs, z), b, qd in zip(data, bands, queued)]
+    new = jittered_grid(6, 130) * 0.9 + 0.05
+    rng = np.random.default_rng(11)
+    reqs = []
+    for q in range(16):
+        d = int(rng.integers(0, len(sizes)))
+        theta = (float(np.exp(rng.normal(0, 0.15))), float(0.1 * np.exp(rng.normal(0, 0.15))), 0.5)
+        if q in (5, 11):
+            d = 1
+            reqs.append((srv.submit_krige(ids[d], theta, new, 0.002 * (q // 4)), d, theta, True))
+        else:
+            reqs.append((srv.submit(ids[d], theta, 0.002 * (q // 4)), d, theta, False))  # bursts of 4
+    st, out = srv.run()
+    assert st == 0
+    for t, d, theta, kriging in reqs:
+        r = out[t]
+        assert r["info"] == -1
+        if queued[d] and not kriging:
+            st1, alone, _ = ctx.batch_loglik([(data[d][0], data[d][1], theta)], tile=128, band64=bands[d],
+                                             queue=True)
+            assert st1 == 0
+            assert r["loglik"] == alone[0]["loglik"] and r["logdet"] == alone[0]["logdet"], (t, d)
+        else:
+            ds = lib.Dataset(ctx, *data[d])
+            alone = ds.loglik(theta, 128, bands[d])
+            assert r["loglik"] == alone["loglik"], (t, d)
+            if kriging:
+                assert np.array_equal(r["pred"], ds.krige(new)), t
+            ds.close()
+        want = oracle.loglik(data[d][0], data[d][1], theta)["loglik"]
+        assert abs(r["loglik"] - want) / abs(want) <= 1e-5
+    # plans the queue does not run are refused for a queued dataset
+    with pytest.raises(lib.MpgeoError):
+        srv.add_dataset(data[0][0], data[0][1], 128, 1, 2, "fp16", queue=True)
+    srv.close()
+    ctx.close()
