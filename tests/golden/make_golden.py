@@ -6,6 +6,8 @@ mle_small.json: maximum-likelihood fit (Nelder-Mead of the oracle) for the n = 1
 jittered-grid workload (theta_0 = (1, 0.1, 0.5)), with z = L eps drawn by the oracle.
 mle_profile_small.json: the same data fitted through the profile likelihood in
 (theta2, theta3) (two-dimensional Nelder-Mead; theta1 = q / n at the maximiser).
+small_z.txt: the data z = L eps of the n = 1,600 workload drawn by the oracle (one value per
+line, 17 significant digits), the input of the fits above, for the benchmark's fit beside them.
 sweep_n40000.json: for each of the six n = 40,000 band-sweep fields, eq. (2) at the true theta
 with z = L eps drawn by the oracle's FP64 factor (so y = L^-1 z is eps up to rounding): logdet,
 quad and l.  Sigma is filled in row blocks of the oracle's own eq. (1), one block at a time
@@ -73,6 +75,13 @@ def mle_profile_small():
     with open(os.path.join(HERE, "mle_profile_small.json"), "w") as f:
         json.dump(out, f, indent=2)
     print(json.dumps(out, indent=2))
+
+
+def small_z():
+    w = SMALL
+    z = oracle.simulate_field(w.locations(), w.theta, w.eps())
+    with open(os.path.join(HERE, "small_z.txt"), "w") as f:
+        f.write("".join(f"{float(v)!r}\n" for v in z))
 
 
 def _matern_matrix_blocked(locs, theta, blocks=256):
