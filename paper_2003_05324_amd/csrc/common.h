@@ -107,6 +107,7 @@ struct PotrfArgs {
     int64_t col_base;  // global logical column of the tile's first column
     int nb;            // logical tile size (columns >= nb are padding)
     int nbp;
+    int ld = 0;        // leading dimension of a, linv, linv32 (0: nbp)
 };
 void launch_potrf(const PotrfArgs &a, hipStream_t stream);
 

@@ -96,6 +96,7 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
     __shared__ int fail_col;
 
     const int nbp = args.nbp;
+    const int ld = args.ld > 0 ? args.ld : nbp;   // leading dimension of A, B and B32
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -111,7 +112,7 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
         // ---- 1. diagonal block: staged in LDS by all threads, factored by one wave ------
         for (int e = tid; e < kBlk * kBlk; e += kPotrfThreads) {
             const int r = e & (kBlk - 1), c = e / kBlk;
-            D[r][c] = (r >= c) ? A[(cb + r) + (int64_t)(cb + c) * nbp] : 0.0;
+            D[r][c] = (r >= c) ? A[(cb + r) + (int64_t)(cb + c) * ld] : 0.0;
         }
         __syncthreads();
         if (wave == 0) logdet += factor_diag_block(lane, cb, &fail_col);
@@ -119,7 +120,7 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
         // L block back to the tile (the diagonal block is not touched by steps 2 and 3)
         for (int e = tid; e < kBlk * kBlk; e += kPotrfThreads) {
             const int r = e & (kBlk - 1), c = e / kBlk;
-            if (r >= c) A[(cb + r) + (int64_t)(cb + c) * nbp] = D[r][c];
+            if (r >= c) A[(cb + r) + (int64_t)(cb + c) * ld] = D[r][c];
         }
         // ---- 2. block rows of B (columns t < split) and panel rows of A (t >= split) ------
         // Thread t solves D y = x: x[q] = B[cb + q][t] for t < cb, the unit vector e_(t - cb)
@@ -130,13 +131,13 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
             double y[kBlk];
             if (t < cb) {
 #pragma unroll
-                for (int q = 0; q < kBlk; ++q) y[q] = B[(cb + q) + (int64_t)t * nbp];
+                for (int q = 0; q < kBlk; ++q) y[q] = B[(cb + q) + (int64_t)t * ld];
             } else if (isB) {
 #pragma unroll
                 for (int q = 0; q < kBlk; ++q) y[q] = (q == t - cb) ? 1.0 : 0.0;
             } else {
 #pragma unroll
-                for (int q = 0; q < kBlk; ++q) y[q] = A[t + (int64_t)(cb + q) * nbp];
+                for (int q = 0; q < kBlk; ++q) y[q] = A[t + (int64_t)(cb + q) * ld];
             }
 #pragma unroll
             for (int l = 0; l < kBlk; ++l) {
@@ -153,15 +154,15 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
             if (isB) {
 #pragma unroll
                 for (int l = 0; l < kBlk; ++l) {
-                    B[(cb + l) + (int64_t)t * nbp] = y[l];
-                    if (B32) B32[(cb + l) + (int64_t)t * nbp] = (float)y[l];
+                    B[(cb + l) + (int64_t)t * ld] = y[l];
+                    if (B32) B32[(cb + l) + (int64_t)t * ld] = (float)y[l];
                 }
             } else {
 #pragma unroll
                 for (int l = 0; l < kBlk; ++l) {
-                    A[t + (int64_t)(cb + l) * nbp] = y[l];
-                    B[(cb + l) + (int64_t)t * nbp] = 0.0;
-                    if (B32) B32[(cb + l) + (int64_t)t * nbp] = 0.0f;
+                    A[t + (int64_t)(cb + l) * ld] = y[l];
+                    B[(cb + l) + (int64_t)t * ld] = 0.0;
+                    if (B32) B32[(cb + l) + (int64_t)t * ld] = 0.0f;
                 }
             }
         }
@@ -191,9 +192,9 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
 #pragma unroll
                     for (int st = 0; st < kBlk / 4; ++st) {
                         const int k = cb + 4 * st + lg;
-                        rv[h][st] = A[(i0 + 16 * h + lr) + (int64_t)k * nbp];
-                        qv[h][st] = inB ? B[k + (int64_t)(j0 + 16 * h + lr) * nbp]
-                                        : A[(j0 + 16 * h + lr) + (int64_t)k * nbp];
+                        rv[h][st] = A[(i0 + 16 * h + lr) + (int64_t)k * ld];
+                        qv[h][st] = inB ? B[k + (int64_t)(j0 + 16 * h + lr) * ld]
+                                        : A[(j0 + 16 * h + lr) + (int64_t)k * ld];
                     }
 #pragma unroll
                 for (int hi = 0; hi < 2; ++hi)
@@ -202,7 +203,7 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             cv[hi][hj][q] = ((diag && hj > hi) || fresh) ? 0.0
-                                : M[(i0 + 16 * hi + lr) + (int64_t)(j0 + 16 * hj + lg + 4 * q) * nbp];
+                                : M[(i0 + 16 * hi + lr) + (int64_t)(j0 + 16 * hj + lg + 4 * q) * ld];
                 f64x4 acc[2][2];
 #pragma unroll
                 for (int hi = 0; hi < 2; ++hi)
@@ -224,7 +225,7 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const int i = i0 + 16 * hi + lr, j = j0 + 16 * hj + lg + 4 * q;
-                            if (!diag || j <= i) M[i + (int64_t)j * nbp] = cv[hi][hj][q] - acc[hi][hj][q];
+                            if (!diag || j <= i) M[i + (int64_t)j * ld] = cv[hi][hj][q] - acc[hi][hj][q];
                         }
                     }
                 cbk += kWaves;
@@ -234,15 +235,17 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
         __syncthreads();
     }
 
-    // ---- forward-solve block, reductions ------------------------------------------------
-    for (int t = tid; t < nbp; t += kPotrfThreads) rs[t] = args.r[t];
-    __syncthreads();
+    // ---- forward-solve block, reductions (a block of a larger tile has no right-hand side) ----
     double quad = 0.0;
-    for (int i = tid; i < nbp; i += kPotrfThreads) {
-        double s = 0.0;
-        for (int j = 0; j <= i; ++j) s += B[i + (int64_t)j * nbp] * rs[j];
-        args.y[i] = s;
-        quad += s * s;
+    if (args.r) {
+        for (int t = tid; t < nbp; t += kPotrfThreads) rs[t] = args.r[t];
+        __syncthreads();
+        for (int i = tid; i < nbp; i += kPotrfThreads) {
+            double s = 0.0;
+            for (int j = 0; j <= i; ++j) s += B[i + (int64_t)j * ld] * rs[j];
+            args.y[i] = s;
+            quad += s * s;
+        }
     }
     // block reductions in a fixed order (deterministic)
     for (int off = 32; off > 0; off >>= 1) {
@@ -260,8 +263,8 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
             sl += red[0][w];
             sq += red[1][w];
         }
-        *args.logdet_part = sl;
-        *args.quad_part = sq;
+        if (args.logdet_part) *args.logdet_part = sl;
+        if (args.quad_part) *args.quad_part = sq;
         if (fail_col != INT_MAX && fail_col < args.nb)
             atomicMin(args.info, (unsigned long long)(args.col_base + fail_col));
     }

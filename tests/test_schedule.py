@@ -33,3 +33,21 @@ def test_schedule_is_consistent():
         run = subprocess.run([exe], capture_output=True, text=True, timeout=120)
         print(run.stdout)
         assert run.returncode == 0, run.stdout[-2000:]
+
+
+def test_blocked_diagonal_factorization_plan():
+    # the plan of the blocked 256/512-column diagonal-tile factorization (potrf_plan.h): bounds of
+    # every product and of the device kernel's indices, job counts per launch, independence of
+    # the products of a launch, and the plan replayed in FP64 against a plain Cholesky factor
+    # and inverse (tests/potrf_plan_check.cpp, host code only)
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ is not available")
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = os.path.join(tmp, "potrf_plan_check")
+        build = subprocess.run([gxx, "-O2", "-std=c++17", os.path.join(HERE, "potrf_plan_check.cpp"), "-o", exe],
+                               capture_output=True, text=True, timeout=300)
+        assert build.returncode == 0, build.stderr[-2000:]
+        run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+        print(run.stdout)
+        assert run.returncode == 0, run.stdout[-2000:]
