@@ -445,19 +445,27 @@ def band_sweep(args):
 
 
 def batch_bench(args):
-    """Batched evaluation: `args.batch` problems with their own sites, data and theta, all-FP64
-    plan, tiles from the autotuner (tuned on an untimed first batch), against evaluating the
-    same problems one after another through the one-shot entry point (tile 512)."""
+    """Batched evaluation: `args.batch` problems with their own sites, theta and data (a draw of
+    each problem's field), all-FP64 plan, tiles from the autotuner (tuned on an untimed first batch), against evaluating the
+    same problems one after another through the one-shot entry point (tile 512); then the
+    persistent task queue, all-FP64 and with FP64-band/FP32 tiles whose band the tuner picks per
+    class of n."""
     import numpy as np
     import torch
 
     import oracle
     import paper_2003_05324_amd as mp
     from synthetic import batch_instances
-    probs = batch_instances(args.batch, 11)
+    ctx = mp.Context(0)
+    # each problem's data: a draw of its own field by the library's FP64 sampler (its normal
+    # vector as eps), as the paper's synthetic data are drawn from the model
+    probs = []
+    for locs, eps, theta in batch_instances(args.batch, 11):
+        gen = mp.Dataset(ctx, locs, None)
+        probs.append((locs, np.asarray(gen.simulate(theta, eps, 128, -1)), theta))
+        gen.close()
     ns = np.array([len(z) for _, z, _ in probs])
     flops = float(np.sum(ns.astype(np.float64) ** 3 / 3.0))
-    ctx = mp.Context(0)
     print(f"[batch] {len(probs)} problems, n in [{ns.min()}, {ns.max()}], sum n^3/3 = {flops:.3e}",
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -481,6 +489,22 @@ def batch_bench(args):
         walls_q.append(time.perf_counter() - t0)
     wall_q = statistics.median(walls_q)
     print(f"[batch] task queue: {wall_q:.3f} s", file=sys.stderr, flush=True)
+    # the same queue with FP64-band/FP32 tiles, the band of each class chosen by the tuner
+    # (MPGEO_TUNE_BAND; the first call probes, untimed), problems that are not positive definite
+    # at their band widened (MPGEO_ESCALATE)
+    ctx.batch_loglik(probs, tile=0, queue=True, tune_band=True, escalate=True)
+    walls_b = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_b, res_b, _ = ctx.batch_loglik(probs, tile=0, queue=True, tune_band=True, escalate=True)
+        walls_b.append(time.perf_counter() - t0)
+    wall_b = statistics.median(walls_b)
+    bands = {}
+    for r in res_b:
+        key = "all" if r["band64"] < 0 else str(r["band64"])
+        bands[key] = bands.get(key, 0) + 1
+    print(f"[batch] task queue, tuned bands {bands}: {wall_b:.3f} s", file=sys.stderr, flush=True)
     for locs, z, theta in probs[:2]:
         ctx.loglik(locs, z, theta, 512, -1)                              # warm-up
     torch.cuda.synchronize()
@@ -492,11 +516,14 @@ def batch_bench(args):
               for a, b, p in zip(res, seq, probs))
     dev_q = max(abs(a["loglik"] - b["loglik"]) / max(abs(b["loglik"]), len(p[1]))
                 for a, b, p in zip(res_q, seq, probs))
+    errs_b = [abs(a["loglik"] - b["loglik"]) / abs(b["loglik"]) for a, b in zip(res_b, seq)]
+    dev_b = max(errs_b)
     # oracle spot check on the three smallest problems
     small = np.argsort(ns)[:3]
     want = {q: oracle.loglik(*probs[q])["loglik"] for q in small}
     orc = max(abs(res[q]["loglik"] - want[q]) / abs(want[q]) for q in small)
     orc_q = max(abs(res_q[q]["loglik"] - want[q]) / abs(want[q]) for q in small)
+    orc_b = max(abs(res_b[q]["loglik"] - want[q]) / abs(want[q]) for q in small)
     hist = {}
     for t in tiles:
         hist[str(t)] = hist.get(str(t), 0) + 1
@@ -514,7 +541,15 @@ def batch_bench(args):
                   "tflops": flops / wall_q / 1e12, "speedup_vs_lanes": wall / wall_q,
                   "speedup_vs_sequential": t_seq / wall_q, "tile": 128,
                   "max_dloglik_vs_sequential": dev_q,
-                  "max_rel_dloglik_vs_oracle_3_smallest": orc_q}}), flush=True)
+                  "max_rel_dloglik_vs_oracle_3_smallest": orc_q},
+        "queue_tuned_band": {"status": st_b, "seconds": wall_b, "evals_per_s": len(probs) / wall_b,
+                             "escalated": int(sum(1 for r in res_b if r["escalations"] > 0)),
+                             "tflops_cholesky_equivalent": flops / wall_b / 1e12,
+                             "speedup_vs_fp64_queue": wall_q / wall_b, "bands": bands, "tile": 128,
+                             "max_rel_dloglik_vs_sequential_fp64": dev_b,
+                             "median_rel_dloglik_vs_sequential_fp64": float(np.median(errs_b)),
+                             "problems_over_1e-5": int(sum(e > 1e-5 for e in errs_b)),
+                             "max_rel_dloglik_vs_oracle_3_smallest": orc_b}}), flush=True)
 
 
 def serve_bench(args):

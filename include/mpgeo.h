@@ -114,12 +114,15 @@ typedef enum {
  * first success or after the all-FP64 plan.  mpgeo_result.escalations counts the repetitions
  * and .band64 / .band32 / .band0 give the bands of the reported result.  Honoured by
  * mpgeo_loglik, mpgeo_dataset_loglik, mpgeo_dataset_mle (every evaluation of the search),
- * mpgeo_dataset_simulate and mpgeo_factor_dense; mpgeo_batch_loglik and the serving loop
- * return MPGEO_E_UNSUPPORTED with it. */
+ * mpgeo_dataset_simulate, mpgeo_factor_dense, and the persistent-queue batch
+ * (mpgeo_batch_loglik with MPGEO_BATCH_QUEUE, mpgeo_batch_loglik_noalloc), where the problems
+ * that failed run again in a launch of their own at the widened FP64 band; the batched lanes and
+ * the serving loop return MPGEO_E_UNSUPPORTED with it. */
 #define MPGEO_ESCALATE    64u
 /* Band tuning for batched evaluation (mpgeo_batch_loglik; the choice of the precision map that
  * Section VIII-C-1 makes by hand for each size).  plan.band64 is then ignored: for each class
- * of problems (half-octave of n, tile, path) the first problem is evaluated all-FP64 and with
+ * of problems (half-octave of n, smoothness to a quarter, half-octave of the range: the last
+ * two set Sigma's conditioning; tile, path) the first problem is evaluated all-FP64 and with
  * FP64 bands 0, 1, 2, 4, 8 tiles (FP32 beyond), and the narrowest band whose log-likelihood
  * is within 1e-6 (relative) of the all-FP64 one is used for the whole class (all-FP64 when
  * none is).  The choice depends only on that problem's deterministic results and is kept in

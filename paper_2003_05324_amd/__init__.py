@@ -271,7 +271,7 @@ class Context:
 
     def batch_loglik(self, problems, tile: int = 0, band64: int = -1, band32: int = -1, lowp=None,
                      profile: bool = False, gcd: bool = False, band0: int = -1,
-                     queue: bool = False, tune_band: bool = False) -> tuple:
+                     queue: bool = False, tune_band: bool = False, escalate: bool = False) -> tuple:
         """eq. (2) for many independent (locs, z, theta) problems in one call (host arrays).
         tile = 0: tile size chosen per instance by the autotuner; tune_band: the FP64 band too
         (MPGEO_TUNE_BAND; the chosen band is each result's "band64").  queue=True: one
@@ -286,7 +286,8 @@ class Context:
         res = (Result * max(1, len(problems)))()
         tiles = (ctypes.c_int32 * max(1, len(problems)))()
         flags = ((MPGEO_PROFILE if profile else 0) | (MPGEO_DIST_GCD if gcd else 0) |
-                 (MPGEO_BATCH_QUEUE if queue else 0) | (MPGEO_TUNE_BAND if tune_band else 0))
+                 (MPGEO_BATCH_QUEUE if queue else 0) | (MPGEO_TUNE_BAND if tune_band else 0) |
+                 (MPGEO_ESCALATE if escalate else 0))
         st = LIB.mpgeo_batch_loglik(self.handle, len(problems), arr,
                                     make_plan(tile, band64, flags, band32, lowp, band0), res, tiles)
         if st not in (MPGEO_OK, MPGEO_E_NOT_SPD):

@@ -1932,14 +1932,20 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
                        const int32_t *bands);
 
 // FP64 band (MPGEO_TUNE_BAND) for an instance evaluated with tile `tile`: the narrowest
-// candidate whose log-likelihood on the first instance of its class (half-octave of n, tile,
-// plan flags) is within kTuneBandBar of the all-FP64 one, else all-FP64 (-1).  The choice
+// candidate whose log-likelihood on the first instance of its class (half-octave of n,
+// smoothness, half-octave of the range, tile, plan flags) is within kTuneBandBar of the
+// all-FP64 one, else all-FP64 (-1).  The choice
 // depends only on that instance's results, which the kernels make deterministic; it is kept in
 // the context for later batches.  Probes run through the queue (queue) or a lane.
 static int batch_band(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, int tile, bool queue,
                       double *probe_out, int *band_out) {
+    // a class: half-octave of n, smoothness to a quarter, range to a half-octave (the two decide
+    // Sigma's conditioning, hence how narrow a band stays within the bar), tile and path
     const int bucket = (int)std::floor(2.0 * std::log2((double)in.n));
-    const std::string key = std::to_string(bucket) + "/" + std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
+    const int nu_q = (int)std::lround(4.0 * in.theta.nu);
+    const int beta_h = (int)std::lround(2.0 * std::log2(in.theta.beta));
+    const std::string key = std::to_string(bucket) + "/" + std::to_string(nu_q) + "/" + std::to_string(beta_h) + "/" +
+                            std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
                             std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
     auto it = ctx->tuned_band.find(key);
     if (it != ctx->tuned_band.end()) {
@@ -2231,6 +2237,49 @@ static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
     return status;
 }
 
+// The queued batch with MPGEO_ESCALATE: problems that were not positive definite at their band
+// run again, their bands widened b -> 2b + 1 (the step of escalate_plan) until they are or the
+// band covers the matrix; each result then reports the band it was computed at and the number
+// of widenings.
+static int batch_queue_escalating(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
+                                  mpgeo_result *out, int32_t *tiles, char *arena, size_t arena_bytes,
+                                  const int32_t *bands) {
+    int st = batch_queue(ctx, count, inst, plan, out, tiles, arena, arena_bytes, bands);
+    if (st != MPGEO_E_NOT_SPD || !(plan.flags & MPGEO_ESCALATE)) return st;
+    std::vector<int32_t> band((size_t)count);
+    std::vector<int32_t> esc((size_t)count, 0);
+    for (int64_t q = 0; q < count; ++q) band[(size_t)q] = bands ? bands[q] : plan.band64;
+    for (;;) {
+        std::vector<int64_t> redo;
+        for (int64_t q = 0; q < count; ++q) {
+            const int64_t p = (inst[q].n + kQueueTile - 1) / kQueueTile;
+            int32_t &b = band[(size_t)q];
+            if (out[q].info < 0 || b < 0 || (int64_t)b >= p - 1) continue;   // done, or all-FP64 already
+            b = ((int64_t)2 * b + 1 >= p - 1) ? -1 : 2 * b + 1;
+            ++esc[(size_t)q];
+            redo.push_back(q);
+        }
+        if (redo.empty()) break;
+        std::vector<mpgeo_instance> sub(redo.size());
+        std::vector<int32_t> sub_band(redo.size());
+        std::vector<mpgeo_result> sub_out(redo.size());
+        for (size_t r = 0; r < redo.size(); ++r) {
+            sub[r] = inst[redo[r]];
+            sub_band[r] = band[(size_t)redo[r]];
+        }
+        st = batch_queue(ctx, (int64_t)redo.size(), sub.data(), plan, sub_out.data(), nullptr, arena, arena_bytes,
+                         sub_band.data());
+        if (st != MPGEO_OK && st != MPGEO_E_NOT_SPD) return st;
+        for (size_t r = 0; r < redo.size(); ++r) out[redo[r]] = sub_out[r];
+    }
+    st = MPGEO_OK;
+    for (int64_t q = 0; q < count; ++q) {
+        out[q].escalations = esc[(size_t)q];
+        if (out[q].info >= 0) st = MPGEO_E_NOT_SPD;
+    }
+    return st;
+}
+
 // Arguments of the queued batch: a two-tier plan (FP64 band, FP32 beyond; or all FP64) at
 // tile 128, each problem at most kQueueMaxN sites.
 static int queue_plan_ok(const mpgeo_plan &plan) {
@@ -2249,7 +2298,7 @@ static int check_batch_args(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance 
                             mpgeo_result *out) {
     if (!ctx || count < 0 || (count > 0 && (!inst || !out))) return MPGEO_E_ARG;
     if (plan.flags & (MPGEO_INPUT_DEVICE | MPGEO_TIMING)) return MPGEO_E_ARG;
-    if (plan.flags & MPGEO_ESCALATE) return MPGEO_E_UNSUPPORTED;
+    if ((plan.flags & MPGEO_ESCALATE) && !(plan.flags & MPGEO_BATCH_QUEUE)) return MPGEO_E_UNSUPPORTED;
     mpgeo_plan chk = plan;
     if (chk.tile == 0) chk.tile = 1;
     MPGEO_TRY(check_plan(chk));
@@ -2283,7 +2332,8 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
                 bands[(size_t)i] = b;
             }
         }
-        return batch_queue(ctx, count, inst, plan, out, tiles, nullptr, 0, tune_band ? bands.data() : nullptr);
+        return batch_queue_escalating(ctx, count, inst, plan, out, tiles, nullptr, 0,
+                                      tune_band ? bands.data() : nullptr);
     }
     if (count == 0) return MPGEO_OK;
     Device dev(ctx->device);
@@ -2348,6 +2398,7 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
 // zero, since the array keeps the previous call's contents.
 int mpgeo_batch_loglik_noalloc(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, mpgeo_plan plan,
                                mpgeo_result *out) {
+    plan.flags |= MPGEO_BATCH_QUEUE;
     MPGEO_TRY(check_batch_args(ctx, count, inst, plan, out));
     if (plan.flags & MPGEO_TUNE_BAND) return MPGEO_E_UNSUPPORTED;   // its probes would allocate
     MPGEO_TRY(queue_plan_ok(plan));
@@ -2357,7 +2408,7 @@ int mpgeo_batch_loglik_noalloc(mpgeo_ctx *ctx, int64_t count, const mpgeo_instan
     if (!dev.ok) return MPGEO_E_DEVICE;
     char *ptr = scratch_ptr(ctx->device);
     if (!ptr) return MPGEO_E_DEVICE;
-    return batch_queue(ctx, count, inst, plan, out, nullptr, ptr, kScratchBytes, nullptr);
+    return batch_queue_escalating(ctx, count, inst, plan, out, nullptr, ptr, kScratchBytes, nullptr);
 }
 
 // ---- serving loop ---------------------------------------------------------------------------

@@ -188,10 +188,15 @@ def test_queue_two_tier_plans(lib, ctx, problems, band):
     assert [r["loglik"] for r in res2] == [r["loglik"] for r in res]
 
 
+def _tune_class(n, theta):
+    # the tuner's class: half-octave of n, smoothness to a quarter, half-octave of the range
+    return (int(np.floor(2 * np.log2(n))), int(round(4 * theta[2])), int(round(2 * np.log2(theta[1]))))
+
+
 def test_band_tuner(lib, problems):
-    # MPGEO_TUNE_BAND: one band per class of n (narrowest within 1e-6 of all-FP64 on the class's
-    # first problem), the same for the queue and the lanes at tile 128, deterministic across
-    # contexts, every result within the band path's bar of the oracle
+    # MPGEO_TUNE_BAND: one band per class (narrowest within 1e-6 of all-FP64 on the class's first
+    # problem), deterministic across contexts, every result within the band path's bar of the
+    # oracle
     c1, c2 = lib.Context(0), lib.Context(0)
     try:
         st, res, _ = c1.batch_loglik(problems, tile=128, queue=True, tune_band=True)
@@ -201,7 +206,7 @@ def test_band_tuner(lib, problems):
         assert [r["loglik"] for r in res2] == [r["loglik"] for r in res]
         classes = {}
         for (locs, z, theta), r in zip(problems, res):
-            classes.setdefault(int(np.floor(2 * np.log2(len(z)))), set()).add(r["band64"])
+            classes.setdefault(_tune_class(len(z), theta), set()).add(r["band64"])
             want = oracle.loglik(locs, z, theta)["loglik"]
             assert abs(r["loglik"] - want) / abs(want) <= 1e-5
         assert all(len(b) == 1 for b in classes.values())
@@ -212,13 +217,43 @@ def test_band_tuner(lib, problems):
         assert st == 0 and tiles == [128] * len(problems)
         lane_classes = {}
         for (locs, z, theta), r in zip(problems, lanes):
-            lane_classes.setdefault(int(np.floor(2 * np.log2(len(z)))), set()).add(r["band64"])
+            lane_classes.setdefault(_tune_class(len(z), theta), set()).add(r["band64"])
             want = oracle.loglik(locs, z, theta)["loglik"]
             assert abs(r["loglik"] - want) / abs(want) <= 1e-5
         assert all(len(b) == 1 for b in lane_classes.values())
     finally:
         c1.close()
         c2.close()
+
+
+def test_queue_escalation(lib, ctx):
+    # a problem positive definite in FP64 but not with FP32 tiles (nu = 5/2, beta = 0.3 on 900
+    # sites: condition number 3e10) beside an easy one: with MPGEO_ESCALATE the failed problem
+    # runs again at the widened FP64 band until it factors, the easy one is untouched; the
+    # escalated result equals the queue at the final band, bit for bit, and the oracle
+    hard_locs = jittered_grid(30, 3)
+    hard_theta = (1.0, 0.3, 2.5)
+    hard = (hard_locs, oracle.simulate_field(hard_locs, hard_theta, normals(900, 4)), hard_theta)
+    easy_locs = jittered_grid(20, 5)
+    easy = (easy_locs, oracle.simulate_field(easy_locs, (1.0, 0.05, 0.5), normals(400, 6)), (1.0, 0.05, 0.5))
+    st, res, _ = ctx.batch_loglik([hard, easy], tile=128, band64=0, queue=True)
+    assert st == lib.MPGEO_E_NOT_SPD and res[0]["info"] >= 0 and res[1]["info"] == -1
+    st, res, _ = ctx.batch_loglik([hard, easy], tile=128, band64=0, queue=True, escalate=True)
+    assert st == lib.MPGEO_OK
+    assert res[0]["escalations"] >= 1 and res[1]["escalations"] == 0 and res[1]["band64"] == 0
+    ladder = [0, 1, 3, -1]                                  # b -> 2b + 1, p = 8 tile rows
+    assert res[0]["band64"] == ladder[res[0]["escalations"]]
+    st1, alone, _ = ctx.batch_loglik([hard], tile=128, band64=res[0]["band64"], queue=True)
+    assert st1 == lib.MPGEO_OK and alone[0]["loglik"] == res[0]["loglik"]
+    # against the oracle: two FP64 factorizations of a matrix of condition number 3e10 differ by
+    # their roundings amplified by it (9e-10 measured for the all-FP64 plan), hence 1e-8 here
+    want = oracle.loglik(*hard)["loglik"]
+    bar = 1e-8 if res[0]["band64"] < 0 else 1e-5
+    assert abs(res[0]["loglik"] - want) / abs(want) <= bar
+    print(f"escalated to band {res[0]['band64']} after {res[0]['escalations']} widenings")
+    # the lanes do not escalate
+    with pytest.raises(lib.MpgeoError):
+        ctx.batch_loglik([easy], tile=128, band64=0, escalate=True)
 
 
 def test_queue_rejects_what_it_does_not_cover(lib, ctx, problems):
