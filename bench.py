@@ -518,6 +518,11 @@ def batch_bench(args):
                 for a, b, p in zip(res_q, seq, probs))
     errs_b = [abs(a["loglik"] - b["loglik"]) / abs(b["loglik"]) for a, b in zip(res_b, seq)]
     dev_b = max(errs_b)
+    # the same errors against the size of eq. (2)'s terms, the tuner's scale (l itself passes
+    # through zero for the smoothest fields)
+    terms_b = [abs(a["loglik"] - b["loglik"]) /
+               (0.5 * (len(p[1]) * np.log(2 * np.pi) + abs(b["logdet"]) + abs(b["quad"])))
+               for a, b, p in zip(res_b, seq, probs)]
     # oracle spot check on the three smallest problems
     small = np.argsort(ns)[:3]
     want = {q: oracle.loglik(*probs[q])["loglik"] for q in small}
@@ -549,6 +554,7 @@ def batch_bench(args):
                              "max_rel_dloglik_vs_sequential_fp64": dev_b,
                              "median_rel_dloglik_vs_sequential_fp64": float(np.median(errs_b)),
                              "problems_over_1e-5": int(sum(e > 1e-5 for e in errs_b)),
+                             "max_dloglik_over_terms_vs_sequential_fp64": max(terms_b),
                              "max_rel_dloglik_vs_oracle_3_smallest": orc_b}}), flush=True)
 
 

@@ -122,13 +122,19 @@ typedef enum {
 /* Band tuning for batched evaluation (mpgeo_batch_loglik; the choice of the precision map that
  * Section VIII-C-1 makes by hand for each size).  plan.band64 is then ignored: for each class
  * of problems (half-octave of n, smoothness to a quarter, half-octave of the range: the last
- * two set Sigma's conditioning; tile, path) the first problem is evaluated all-FP64 and with
- * FP64 bands 0, 1, 2, 4, 8 tiles (FP32 beyond), and the narrowest band whose log-likelihood
- * is within 1e-6 (relative) of the all-FP64 one is used for the whole class (all-FP64 when
- * none is).  The choice depends only on that problem's deterministic results and is kept in
- * the context for later batches; mpgeo_result.band64 reports it per problem.  With plan.tile
- * = 0 the tile is tuned first, on the all-FP64 plan.  Works with and without
- * MPGEO_BATCH_QUEUE; other entry points ignore the flag. */
+ * two set Sigma's conditioning; tile, path) the first two problems of the class are evaluated
+ * all-FP64 and with FP64 bands 0, 1, 2, 4, 8 tiles (FP32 beyond), and the narrowest band at
+ * which both factor and stay within 1e-7 of their all-FP64 log-likelihood is used for the
+ * whole class (all-FP64 when none is).  The 1e-7 is relative to the size of the terms that
+ * eq. (2) sums, S = (n log 2 pi + |log|Sigma|| + z^T Sigma^-1 z) / 2 (of the profiled form with
+ * MPGEO_PROFILE), not to l, which passes through zero where they cancel.  To keep l within
+ * 1e-5 of itself, a problem whose result at the class's band has |l| < 3 e S / 1e-5 (e: the
+ * larger error of the two probes, at least 1e-9) is evaluated again all-FP64
+ * (mpgeo_result.escalations counts it, band64 is then -1).  The choice depends only on the
+ * probes' deterministic results and is kept in the context for later batches;
+ * mpgeo_result.band64 reports the band each problem was computed at.  With plan.tile = 0 the
+ * tile is tuned first, on the all-FP64 plan.  Works with and without MPGEO_BATCH_QUEUE; other
+ * entry points ignore the flag. */
 #define MPGEO_TUNE_BAND  128u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
@@ -188,7 +194,7 @@ typedef struct {
     int32_t band64;        /* bands of the plan the result was computed with: the plan's own, */
     int32_t band32;        /* or the widened ones after MPGEO_ESCALATE */
     int32_t band0;
-    int32_t escalations;   /* repetitions with wider bands (MPGEO_ESCALATE), else 0 */
+    int32_t escalations;   /* repetitions with wider bands (MPGEO_ESCALATE) or all-FP64 (MPGEO_TUNE_BAND) */
 } mpgeo_result;
 
 /* Per-kernel-class launch statistics accumulated while MPGEO_TIMING is set. */

@@ -383,6 +383,13 @@ const char *kStatNames[kStatCount] = {"covgen", "morton_order", "potrf_tile", "t
                                       "trsm_fp32", "panel_solve", "update_fp64", "update_fp32",
                                       "finalize", "quantize", "update_lowp", "update_lowp_col"};
 
+// A class's tuned FP64 band (-1: all-FP64) and the largest error of its probes at that band,
+// relative to the size of eq. (2)'s terms.
+struct TunedBand {
+    int band;
+    double err;
+};
+
 }  // namespace
 
 struct mpgeo_ctx {
@@ -431,7 +438,7 @@ struct mpgeo_ctx {
     std::vector<mpgeo_ctx *> lanes;
     std::vector<mpgeo_dataset *> lane_ds;
     std::map<std::string, int> tuned_tile;
-    std::map<std::string, int> tuned_band;    // MPGEO_TUNE_BAND: FP64 band per class of n and tile
+    std::map<std::string, TunedBand> tuned_band;   // MPGEO_TUNE_BAND: band and error per class
     DevBuf batch_res;                         // per-instance {loglik, logdet, quad, info}
     // the persistent task-queue batch: inputs, tiles, vectors and control words
     DevBuf q_in_locs, q_in_z, q_locs, q_vec, q_tiles, q_linv, q_parts, q_flags, q_ctrl,
@@ -1921,79 +1928,155 @@ static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, d
     return MPGEO_OK;
 }
 
-// Candidate FP64 bands of the band tuner (in tiles), narrowest first, and its bar: the relative
-// log-likelihood difference to the all-FP64 evaluation of the class's first problem (a tenth of
-// the mixed paths' 1e-5, a margin for the other problems of the class).
+// The band tuner (MPGEO_TUNE_BAND).  Its candidate FP64 bands (in tiles), narrowest first; its
+// bar on a candidate's error, relative to the size of the terms that eq. (2) sums (the sizes
+// of n log 2 pi, log|Sigma| and z^T Sigma^-1 z, halved), not to l itself, which passes through
+// zero where those terms cancel (smooth fields of large range), while the rounding error of the
+// factorization does not; the problems of a class it probes; and the relative accuracy of l
+// that it keeps: a problem whose l comes out too small against its terms for the class's error
+// (kTuneMargin * err * terms > kTuneTarget * |l|) is evaluated again all-FP64.
 static const int kTuneBands[] = {0, 1, 2, 4, 8};
-constexpr double kTuneBandBar = 1e-6;
+constexpr double kTuneBandBar = 1e-7;
+constexpr int kTuneProbes = 2;
+constexpr double kTuneTarget = 1e-5;
+constexpr double kTuneMargin = 3.0;
+constexpr double kTuneErrFloor = 1e-9;   // a class error measured as zero still counts this much
+
+// Half the summed sizes of eq. (2)'s terms (of the profiled form with MPGEO_PROFILE).
+static double loglik_terms(int64_t n, double logdet, double quad, bool profile) {
+    const double dn = (double)n, l2pi = 1.8378770664093454836;   // log 2 pi
+    if (profile) return 0.5 * (dn * (l2pi + 1.0) + dn * std::fabs(std::log(quad / dn)) + std::fabs(logdet));
+    return 0.5 * (dn * l2pi + std::fabs(logdet) + std::fabs(quad));
+}
 
 static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
                        mpgeo_result *out, int32_t *tiles, char *arena, size_t arena_bytes,
                        const int32_t *bands);
 
-// FP64 band (MPGEO_TUNE_BAND) for an instance evaluated with tile `tile`: the narrowest
-// candidate whose log-likelihood on the first instance of its class (half-octave of n,
-// smoothness, half-octave of the range, tile, plan flags) is within kTuneBandBar of the
-// all-FP64 one, else all-FP64 (-1).  The choice
-// depends only on that instance's results, which the kernels make deterministic; it is kept in
-// the context for later batches.  Probes run through the queue (queue) or a lane.
-static int batch_band(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, int tile, bool queue,
-                      double *probe_out, int *band_out) {
-    // a class: half-octave of n, smoothness to a quarter, range to a half-octave (the two decide
-    // Sigma's conditioning, hence how narrow a band stays within the bar), tile and path
+// A class of the band tuner: half-octave of n, smoothness to a quarter, range to a half-octave
+// (the two set Sigma's conditioning, hence how narrow a band stays within the bar), tile, path.
+static std::string band_class(const mpgeo_instance &in, const mpgeo_plan &pl, int tile, bool queue) {
     const int bucket = (int)std::floor(2.0 * std::log2((double)in.n));
     const int nu_q = (int)std::lround(4.0 * in.theta.nu);
     const int beta_h = (int)std::lround(2.0 * std::log2(in.theta.beta));
-    const std::string key = std::to_string(bucket) + "/" + std::to_string(nu_q) + "/" + std::to_string(beta_h) + "/" +
-                            std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
-                            std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
-    auto it = ctx->tuned_band.find(key);
-    if (it != ctx->tuned_band.end()) {
-        *band_out = it->second;
-        return MPGEO_OK;
-    }
-    const int64_t p = (in.n + tile - 1) / tile;
+    return std::to_string(bucket) + "/" + std::to_string(nu_q) + "/" + std::to_string(beta_h) + "/" +
+           std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
+           std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
+}
+
+// Tunes one class on its probe problems: each is evaluated all-FP64 and at every candidate band
+// below its last tile row (one queue launch for all of them, or one lane evaluation each); the
+// narrowest candidate at which every probe factors and stays within kTuneBandBar of its
+// all-FP64 result (relative to its terms) is the class's band, the largest such error its
+// error; all-FP64 (-1) when no candidate is.  Depends only on the probes' deterministic results.
+static int band_probe(mpgeo_ctx *ctx, const std::vector<const mpgeo_instance *> &probes, mpgeo_plan pl, int tile,
+                      bool queue, double *probe_out, TunedBand *tb) {
+    int64_t pmax = 0;
+    for (const mpgeo_instance *in : probes) pmax = std::max<int64_t>(pmax, (in->n + tile - 1) / tile);
     std::vector<int> cand{-1};
     for (int b : kTuneBands)
-        if (b < p - 1) cand.push_back(b);
-    std::vector<double> ll(cand.size(), 0.0);
-    std::vector<int> ok(cand.size(), 0);
-    for (size_t c = 0; c < cand.size(); ++c) {
-        mpgeo_plan q = pl;
-        q.tile = tile;
-        q.band64 = cand[c];
-        q.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
-        mpgeo_result r{};
-        int st;
-        if (queue) {
-            const int32_t b = cand[c];
-            st = batch_queue(ctx, 1, &in, q, &r, nullptr, nullptr, 0, &b);
-        } else {
-            st = batch_enqueue(ctx->lane_ds[0], in, q, probe_out);
-            batch_sync(ctx);
-            if (st == MPGEO_OK) {
+        if (b < pmax - 1) cand.push_back(b);
+    const size_t np = probes.size(), nc = cand.size();
+    std::vector<mpgeo_result> r(np * nc);   // [candidate][probe]
+    pl.tile = tile;
+    pl.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
+    if (queue) {
+        std::vector<mpgeo_instance> all(np * nc);
+        std::vector<int32_t> bands(np * nc);
+        for (size_t c = 0; c < nc; ++c)
+            for (size_t k = 0; k < np; ++k) {
+                all[c * np + k] = *probes[k];
+                bands[c * np + k] = cand[c];
+            }
+        const int st = batch_queue(ctx, (int64_t)all.size(), all.data(), pl, r.data(), nullptr, nullptr, 0, bands.data());
+        if (st != MPGEO_OK && st != MPGEO_E_NOT_SPD) return st;
+    } else {
+        for (size_t c = 0; c < nc; ++c)
+            for (size_t k = 0; k < np; ++k) {
+                mpgeo_plan q = pl;
+                q.band64 = cand[c];
+                const int st = batch_enqueue(ctx->lane_ds[0], *probes[k], q, probe_out);
+                batch_sync(ctx);
+                if (st != MPGEO_OK) return st;
                 double host[4];
                 MPGEO_HIP(hipMemcpy(host, probe_out, sizeof(host), hipMemcpyDeviceToHost));
                 unsigned long long info;
                 std::memcpy(&info, host + 3, sizeof(info));
-                r.loglik = host[0];
-                st = info == ~0ull ? MPGEO_OK : MPGEO_E_NOT_SPD;
+                mpgeo_result &o = r[c * np + k];
+                o.loglik = host[0];
+                o.logdet = host[1];
+                o.quad = host[2];
+                o.info = info == ~0ull ? -1 : (int64_t)info;
             }
-        }
-        if (st != MPGEO_OK && st != MPGEO_E_NOT_SPD) return st;
-        ok[c] = st == MPGEO_OK;
-        ll[c] = r.loglik;
     }
-    int best = -1;
-    if (ok[0])
-        for (size_t c = 1; c < cand.size(); ++c)
-            if (ok[c] && std::fabs(ll[c] - ll[0]) <= kTuneBandBar * std::fabs(ll[0])) {
-                best = cand[c];
-                break;
-            }
-    ctx->tuned_band[key] = best;
-    *band_out = best;
+    *tb = TunedBand{-1, 0.0};
+    const bool profile = (pl.flags & MPGEO_PROFILE) != 0;
+    for (size_t k = 0; k < np; ++k)
+        if (r[k].info >= 0) return MPGEO_OK;   // a probe is not positive definite even all-FP64
+    for (size_t c = 1; c < nc; ++c) {
+        double worst = 0.0;
+        bool ok = true;
+        for (size_t k = 0; k < np && ok; ++k) {
+            const mpgeo_result &f = r[k], &m = r[c * np + k];
+            ok = m.info < 0;
+            worst = std::max(worst, std::fabs(m.loglik - f.loglik) / loglik_terms(probes[k]->n, f.logdet, f.quad, profile));
+        }
+        if (ok && worst <= kTuneBandBar) {
+            *tb = TunedBand{cand[c], std::max(worst, kTuneErrFloor)};
+            break;
+        }
+    }
     return MPGEO_OK;
+}
+
+// The tuned band and class error of each instance (tile[i] its tile): classes not yet in the
+// context are probed on their first kTuneProbes problems of this call, then kept for later
+// batches.
+static int tune_bands(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &pl,
+                      const std::vector<int> &tile, bool queue, double *probe_out, std::vector<int32_t> &band,
+                      std::vector<double> &err) {
+    std::vector<std::string> key((size_t)count);
+    std::vector<std::string> order;   // new classes in order of first appearance
+    std::map<std::string, std::vector<const mpgeo_instance *>> probes;
+    std::map<std::string, int> probe_tile;
+    for (int64_t i = 0; i < count; ++i) {
+        key[(size_t)i] = band_class(inst[i], pl, tile[(size_t)i], queue);
+        if (ctx->tuned_band.count(key[(size_t)i])) continue;
+        auto &v = probes[key[(size_t)i]];
+        if (v.empty()) {
+            order.push_back(key[(size_t)i]);
+            probe_tile[key[(size_t)i]] = tile[(size_t)i];
+        }
+        if ((int)v.size() < kTuneProbes) v.push_back(inst + i);
+    }
+    for (const std::string &k : order) {
+        TunedBand tb;
+        MPGEO_TRY(band_probe(ctx, probes[k], pl, probe_tile[k], queue, probe_out, &tb));
+        ctx->tuned_band[k] = tb;
+    }
+    band.resize((size_t)count);
+    err.resize((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        const TunedBand &tb = ctx->tuned_band[key[(size_t)i]];
+        band[(size_t)i] = tb.band;
+        err[(size_t)i] = tb.err;
+    }
+    return MPGEO_OK;
+}
+
+// The problems of a tuned batch to evaluate again all-FP64 for accuracy: factored at a band
+// (not all-FP64) with an l too small against its terms for the class error err[i].
+static std::vector<int64_t> accuracy_reruns(int64_t count, const mpgeo_instance *inst, const mpgeo_result *out,
+                                            const std::vector<double> &err, bool profile) {
+    std::vector<int64_t> redo;
+    for (int64_t i = 0; i < count; ++i) {
+        const mpgeo_result &o = out[i];
+        if (o.info >= 0 || o.band64 < 0 || err[(size_t)i] <= 0.0) continue;
+        if (kTuneMargin * err[(size_t)i] * loglik_terms(inst[i].n, o.logdet, o.quad, profile) >
+            kTuneTarget * std::fabs(o.loglik))
+            redo.push_back(i);
+    }
+    return redo;
 }
 
 // The persistent task-queue batch (MPGEO_BATCH_QUEUE): problems are packed into shared buffers
@@ -2323,17 +2406,33 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         if (count == 0) return MPGEO_OK;
         Device dev(ctx->device);
         if (!dev.ok) return MPGEO_E_DEVICE;
+        if (!tune_band) return batch_queue_escalating(ctx, count, inst, plan, out, tiles, nullptr, 0, nullptr);
         std::vector<int32_t> bands;
-        if (tune_band) {
-            bands.resize((size_t)count);
-            for (int64_t i = 0; i < count; ++i) {
-                int b = -1;
-                MPGEO_TRY(batch_band(ctx, inst[i], plan, kQueueTile, true, nullptr, &b));
-                bands[(size_t)i] = b;
+        std::vector<double> err;
+        MPGEO_TRY(tune_bands(ctx, count, inst, plan, std::vector<int>((size_t)count, kQueueTile), true, nullptr,
+                             bands, err));
+        int st = batch_queue_escalating(ctx, count, inst, plan, out, tiles, nullptr, 0, bands.data());
+        if (st != MPGEO_OK && st != MPGEO_E_NOT_SPD) return st;
+        const std::vector<int64_t> redo = accuracy_reruns(count, inst, out, err, (plan.flags & MPGEO_PROFILE) != 0);
+        if (!redo.empty()) {
+            std::vector<mpgeo_instance> sub(redo.size());
+            std::vector<mpgeo_result> sub_out(redo.size());
+            for (size_t r = 0; r < redo.size(); ++r) sub[r] = inst[redo[r]];
+            mpgeo_plan fp64 = plan;
+            fp64.band64 = -1;
+            const int st2 = batch_queue(ctx, (int64_t)redo.size(), sub.data(), fp64, sub_out.data(), nullptr, nullptr,
+                                        0, nullptr);
+            if (st2 != MPGEO_OK && st2 != MPGEO_E_NOT_SPD) return st2;
+            for (size_t r = 0; r < redo.size(); ++r) {
+                const int esc = out[redo[r]].escalations;
+                out[redo[r]] = sub_out[r];
+                out[redo[r]].escalations = esc + 1;
             }
+            st = MPGEO_OK;
+            for (int64_t q = 0; q < count; ++q)
+                if (out[q].info >= 0) st = MPGEO_E_NOT_SPD;
         }
-        return batch_queue_escalating(ctx, count, inst, plan, out, tiles, nullptr, 0,
-                                      tune_band ? bands.data() : nullptr);
+        return st;
     }
     if (count == 0) return MPGEO_OK;
     Device dev(ctx->device);
@@ -2344,16 +2443,23 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
     MPGEO_TRY(batch_lanes(ctx, nlanes));
     MPGEO_TRY(ctx->batch_res.ensure((size_t)(count + 1) * 4 * sizeof(double)));
     double *res = ctx->batch_res.as<double>();
-    std::vector<int> tile((size_t)count), band((size_t)count, plan.band64);
+    std::vector<int> tile((size_t)count);
+    std::vector<int32_t> band((size_t)count, plan.band64);
+    std::vector<double> err((size_t)count, 0.0);
     for (int64_t i = 0; i < count; ++i) {
         mpgeo_plan tp = plan;
         if (tune_band) {   // the tile is timed on the all-FP64 plan, the band then chosen for it
             tp.band64 = -1;
             tp.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
         }
-        int st = batch_tile(ctx, inst[i], tp, res + 4 * count, &tile[(size_t)i]);
-        if (st == MPGEO_OK && tune_band)
-            st = batch_band(ctx, inst[i], plan, tile[(size_t)i], false, res + 4 * count, &band[(size_t)i]);
+        const int st = batch_tile(ctx, inst[i], tp, res + 4 * count, &tile[(size_t)i]);
+        if (st != MPGEO_OK) {
+            batch_sync(ctx);
+            return st;
+        }
+    }
+    if (tune_band) {
+        const int st = tune_bands(ctx, count, inst, plan, tile, false, res + 4 * count, band, err);
         if (st != MPGEO_OK) {
             batch_sync(ctx);
             return st;
@@ -2384,11 +2490,44 @@ int mpgeo_batch_loglik(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst
         out[i].logdet = r[1];
         out[i].quad = r[2];
         out[i].info = (info == ~0ull) ? -1 : (int64_t)info;
-        out[i].band64 = band[(size_t)i];
+        const int64_t p = (inst[i].n + tile[(size_t)i] - 1) / tile[(size_t)i];
+        out[i].band64 = band[(size_t)i] >= p - 1 ? -1 : band[(size_t)i];   // a band covering the matrix is all-FP64
         out[i].band32 = plan.band32;
         out[i].band0 = plan.band0;
         if (out[i].info >= 0) status = MPGEO_E_NOT_SPD;
         if (tiles) tiles[i] = tile[(size_t)i];
+    }
+    if (!tune_band) return status;
+    const std::vector<int64_t> redo = accuracy_reruns(count, inst, out, err, (plan.flags & MPGEO_PROFILE) != 0);
+    if (redo.empty()) return status;
+    int est = MPGEO_OK;
+    std::vector<char> again((size_t)count, 0);
+    for (size_t q = 0; q < redo.size() && est == MPGEO_OK; ++q) {
+        const int64_t i = redo[q];
+        mpgeo_plan pl = plan;
+        pl.tile = tile[(size_t)i];
+        pl.band64 = -1;
+        pl.flags &= ~(uint32_t)MPGEO_TUNE_BAND;
+        again[(size_t)i] = 1;
+        est = batch_enqueue(ctx->lane_ds[q % (size_t)nlanes], inst[i], pl, res + 4 * i);
+    }
+    batch_sync(ctx);
+    if (est != MPGEO_OK) return est;
+    MPGEO_HIP(hipMemcpy(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+    status = MPGEO_OK;
+    for (int64_t i = 0; i < count; ++i) {
+        if (again[(size_t)i]) {
+            const double *r = host.data() + 4 * i;
+            unsigned long long info;
+            std::memcpy(&info, r + 3, sizeof(info));
+            out[i].loglik = r[0];
+            out[i].logdet = r[1];
+            out[i].quad = r[2];
+            out[i].info = (info == ~0ull) ? -1 : (int64_t)info;
+            out[i].band64 = -1;
+            out[i].escalations += 1;
+        }
+        if (out[i].info >= 0) status = MPGEO_E_NOT_SPD;
     }
     return status;
 }

@@ -193,10 +193,30 @@ def _tune_class(n, theta):
     return (int(np.floor(2 * np.log2(n))), int(round(4 * theta[2])), int(round(2 * np.log2(theta[1]))))
 
 
+def _terms(n, logdet, quad):
+    # half the summed sizes of eq. (2)'s terms: the scale the tuner measures its error on
+    return 0.5 * (n * np.log(2 * np.pi) + abs(logdet) + abs(quad))
+
+
+def _check_tuned(lib, problems, res, fp64):
+    # one band per class among the problems left at their tuned band; the others all-FP64,
+    # either re-evaluated for accuracy (one escalation, the all-FP64 result bit for bit) or with
+    # a band that covers their matrix; every result within the band path's 1e-5 of the oracle
+    classes = {}
+    for (locs, z, theta), r, f in zip(problems, res, fp64):
+        want = oracle.loglik(locs, z, theta)["loglik"]
+        assert abs(r["loglik"] - want) / abs(want) <= 1e-5
+        if r["escalations"] > 0:
+            assert r["band64"] == -1 and r["loglik"] == f["loglik"]
+        elif r["band64"] >= 0:
+            classes.setdefault(_tune_class(len(z), theta), set()).add(r["band64"])
+    assert all(len(b) == 1 for b in classes.values())
+    return classes
+
+
 def test_band_tuner(lib, problems):
-    # MPGEO_TUNE_BAND: one band per class (narrowest within 1e-6 of all-FP64 on the class's first
-    # problem), deterministic across contexts, every result within the band path's bar of the
-    # oracle
+    # MPGEO_TUNE_BAND: one band per class (narrowest within 1e-7 of all-FP64, relative to the
+    # size of eq. (2)'s terms, on the class's first two problems), deterministic across contexts
     c1, c2 = lib.Context(0), lib.Context(0)
     try:
         st, res, _ = c1.batch_loglik(problems, tile=128, queue=True, tune_band=True)
@@ -204,26 +224,56 @@ def test_band_tuner(lib, problems):
         st2, res2, _ = c2.batch_loglik(problems, tile=128, queue=True, tune_band=True)
         assert [r["band64"] for r in res2] == [r["band64"] for r in res]
         assert [r["loglik"] for r in res2] == [r["loglik"] for r in res]
-        classes = {}
-        for (locs, z, theta), r in zip(problems, res):
-            classes.setdefault(_tune_class(len(z), theta), set()).add(r["band64"])
-            want = oracle.loglik(locs, z, theta)["loglik"]
-            assert abs(r["loglik"] - want) / abs(want) <= 1e-5
-        assert all(len(b) == 1 for b in classes.values())
-        print("tuned bands per class:", {k: sorted(v) for k, v in classes.items()})
+        _, fp64, _ = c1.batch_loglik(problems, tile=128, band64=-1, queue=True)
+        classes = _check_tuned(lib, problems, res, fp64)
+        print("tuned bands per class:", {k: sorted(v) for k, v in classes.items()},
+              "re-evaluated:", sum(r["escalations"] for r in res))
         # the lanes probe their classes themselves (their products are summed in another order,
         # so a band at the edge of the bar may come out differently)
         st, lanes, tiles = c1.batch_loglik(problems, tile=128, tune_band=True)
         assert st == 0 and tiles == [128] * len(problems)
-        lane_classes = {}
-        for (locs, z, theta), r in zip(problems, lanes):
-            lane_classes.setdefault(_tune_class(len(z), theta), set()).add(r["band64"])
-            want = oracle.loglik(locs, z, theta)["loglik"]
-            assert abs(r["loglik"] - want) / abs(want) <= 1e-5
-        assert all(len(b) == 1 for b in lane_classes.values())
+        _, fp64l, _ = c1.batch_loglik(problems, tile=128, band64=-1)
+        _check_tuned(lib, problems, lanes, fp64l)
     finally:
         c1.close()
         c2.close()
+
+
+@pytest.mark.parametrize("queue", [True, False])
+def test_band_tuner_reevaluates_cancelling_loglik(lib, queue):
+    # l passes through zero where its terms cancel, and a mixed band's rounding error, a small
+    # fraction of those terms, is then no longer small against l: such a problem is evaluated
+    # again all-FP64.  Two probes of one class (same sites, smoothness and range) fix a mixed
+    # band; the third problem is the first scaled so that l = 0 (z -> c z, sigma2 -> c^2 sigma2
+    # shifts l by -n log c, with c = exp(l / n)), which leaves its class and its relative
+    # rounding unchanged
+    locs = jittered_grid(40, 21)
+    theta = (1.0, 0.02, 0.5)
+    z = oracle.simulate_field(locs, theta, normals(1600, 22))
+    l0 = oracle.loglik(locs, z, theta)["loglik"]
+    c = np.exp(l0 / len(z))
+    zero = (locs, c * z, (c * c, theta[1], theta[2]))
+    probs = [(locs, z, theta), (locs, 1.5 * z, (2.25, theta[1], theta[2])), zero]
+    want = oracle.loglik(*zero)
+    terms = _terms(len(z), want["logdet"], want["quad"])
+    assert abs(want["loglik"]) < 1e-9 * terms
+    ctx = lib.Context(0)
+    try:
+        st, res, _ = ctx.batch_loglik(probs, tile=128, queue=queue, tune_band=True)
+        assert st == 0
+        print("bands", [r["band64"] for r in res], "escalations", [r["escalations"] for r in res])
+        assert res[0]["band64"] >= 0 and res[1]["band64"] == res[0]["band64"]
+        assert res[0]["escalations"] == res[1]["escalations"] == 0
+        assert res[2]["band64"] == -1 and res[2]["escalations"] == 1
+        _, fp64, _ = ctx.batch_loglik([zero], tile=128, band64=-1, queue=queue)
+        assert res[2]["loglik"] == fp64[0]["loglik"]
+        assert abs(res[2]["loglik"] - want["loglik"]) <= 1e-10 * terms
+        # the same problem at the class's band, without the tuner: its error against l
+        _, mixed, _ = ctx.batch_loglik([zero], tile=128, band64=res[0]["band64"], queue=queue)
+        print(f"at band {res[0]['band64']}: |dl| = {abs(mixed[0]['loglik'] - want['loglik']):.2e}, "
+              f"terms {terms:.3e}, l {want['loglik']:.2e}")
+    finally:
+        ctx.close()
 
 
 def test_queue_escalation(lib, ctx):
