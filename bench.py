@@ -41,7 +41,7 @@ PEAK_HBM_GBS = 8000.0      # GB/s, MI355X HBM3E
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries, one per update kernel, each naming
 # the kernel source it was measured on (the figure is void once that source changed)
 TRAFFIC_PROFILES = {
-    "update_lowp": ("update_lowp_hbm_traffic_matern-n99856-nb512-band2-band32_8-fp16.md", "lowp.hip"),
+    "update_lowp": ("update_lowp_hbm_traffic_matern-n99856-nb512-band2-band32_10-fp16.md", "lowp.hip"),
     "update_fp32": ("update_fp32_hbm_traffic_matern-n99856-nb512-band2.md", "gemm.hip"),
 }
 
@@ -114,12 +114,12 @@ def parse():
                     help="comma list of the paths to time: two_tier (the headline: --steps/--warmup), "
                          "three_tier (--three-tier-steps), fp64 (--fp64-steps); profiling runs may "
                          "leave out the headline, and then print no value")
-    ap.add_argument("--band32", type=int, default=8)
+    ap.add_argument("--band32", type=int, default=10)
     ap.add_argument("--lowp", default="fp16", choices=["fp16", "bf16", "none"])
     ap.add_argument("--m", type=int, default=316, help="grid side (n = m*m)")
     ap.add_argument("--tile", type=int, default=512)
     ap.add_argument("--band", type=int, default=2)
-    ap.add_argument("--cpu-sample-m", type=int, default=130)
+    ap.add_argument("--cpu-sample-m", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--heldout", type=int, default=2000, help="kriging sites (0: skip)")
     ap.add_argument("--batch", type=int, default=0,
@@ -760,7 +760,7 @@ def main():
     summaries = {name: leg_summary(w, r, st, n, ll64 if name != "fp64" else None, stats, wl, dt)
                  for name, (w, r, st, stats, wl, dt) in runs.items()}
     if "two_tier" not in summaries:   # a profiling run of the other legs: no headline
-        print(json.dumps({"legs": summaries}), flush=True)
+        print(json.dumps({"legs": summaries, "kriging": kriging}), flush=True)
         return
     head = summaries["two_tier"]
     value = head["evals_per_s"]
