@@ -328,9 +328,12 @@ typedef struct {
  * mpgeo_loglik would; the evaluations are spread over private lanes of the context (each its
  * own pair of streams and workspace; MPGEO_BATCH_LANES, default 4) and enqueued without host
  * synchronisation, largest first.  plan.tile = 0 selects the tile size per instance by an
- * autotuner: for each half-octave of n (and precision plan) the first instance is timed with a
- * tile covering it and with 128, 256, 384, 512 below n, and the fastest is kept in the context
- * for later batches.  out[i] receives loglik, logdet, quad and info (times are 0); tiles, if
+ * autotuner: for each half-octave of n (and precision plan) the first instance is timed (the
+ * faster of two runs) with a tile covering it and with 128, 256, 384, 512 below n, and the
+ * largest tile within 5% of the fastest is kept in the context for later batches.  The bands
+ * of a mixed plan count tiles, so its results follow the tile chosen, which the timing decides:
+ * pass a tile, or MPGEO_TUNE_BAND (whose band is probed for the tuned tile and keeps l within
+ * its bar), where results must not depend on timing.  out[i] receives loglik, logdet, quad and info (times are 0); tiles, if
  * not NULL, the tile size used.  Inputs are host memory (MPGEO_INPUT_DEVICE and MPGEO_TIMING
  * are rejected).  With MPGEO_BATCH_QUEUE the batch runs as one persistent kernel instead
  * (see the flag); a wait in it that exceeds about two seconds aborts the kernel and returns
