@@ -41,8 +41,9 @@ PEAK_HBM_GBS = 8000.0      # GB/s, MI355X HBM3E
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries, one per update kernel, each naming
 # the kernel source it was measured on (the figure is void once that source changed)
 TRAFFIC_PROFILES = {
-    "update_lowp": ("update_lowp_hbm_traffic_matern-n99856-nb512-band2-band32_10-fp16.md", "lowp.hip"),
-    "update_fp32": ("update_fp32_hbm_traffic_matern-n99856-nb512-band2.md", "gemm.hip"),
+    "update_lowp": (["update_lowp_hbm_traffic_matern-n99856-nb512-band2-band32_8-fp16.md",
+                     "update_lowp_hbm_traffic_matern-n99856-nb512-band2-band32_10-fp16.md"], "lowp.hip"),
+    "update_fp32": (["update_fp32_hbm_traffic_matern-n99856-nb512-band2.md"], "gemm.hip"),
 }
 
 
@@ -53,20 +54,20 @@ def measured_traffic(kernel, workload):
     import re
     if kernel not in TRAFFIC_PROFILES:
         return None
-    fname, src = TRAFFIC_PROFILES[kernel]
-    path = os.path.join(ROOT, "profiles", fname)
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    wl = re.search(r"workload: (\S+)", text)
-    sha = re.search(r"sha256 at measurement: ([0-9a-f]+)", text)
-    val = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
-    if not wl or wl.group(1) != workload or not sha or not val:
-        return None
+    fnames, src = TRAFFIC_PROFILES[kernel]
     source = os.path.join(ROOT, "paper_2003_05324_amd", "csrc", src)
-    if hashlib.sha256(open(source, "rb").read()).hexdigest() != sha.group(1):
-        return None
-    return float(val.group(1))
+    digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    for fname in fnames:
+        path = os.path.join(ROOT, "profiles", fname)
+        if not os.path.exists(path):
+            continue
+        text = open(path).read()
+        wl = re.search(r"workload: (\S+)", text)
+        sha = re.search(r"sha256 at measurement: ([0-9a-f]+)", text)
+        val = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", text)
+        if wl and wl.group(1) == workload and sha and sha.group(1) == digest and val:
+            return float(val.group(1))
+    return None
 
 
 def roofline(stats, workload):
@@ -110,11 +111,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--three-tier-steps", type=int, default=3)
-    ap.add_argument("--legs", default="two_tier,three_tier,fp64",
+    ap.add_argument("--legs", default="two_tier,three_tier,three_tier_wide,fp64",
                     help="comma list of the paths to time: two_tier (the headline: --steps/--warmup), "
-                         "three_tier (--three-tier-steps), fp64 (--fp64-steps); profiling runs may "
+                         "three_tier and three_tier_wide (--three-tier-steps), fp64 (--fp64-steps); profiling runs may "
                          "leave out the headline, and then print no value")
-    ap.add_argument("--band32", type=int, default=10)
+    ap.add_argument("--band32", type=int, default=8,
+                    help="FP32 tiles beyond the FP64 band in the three-tier leg")
+    ap.add_argument("--band32-wide", type=int, default=10,
+                    help="FP32 width of a second three-tier leg (three_tier_wide; 0: none)")
     ap.add_argument("--lowp", default="fp16", choices=["fp16", "bf16", "none"])
     ap.add_argument("--m", type=int, default=316, help="grid side (n = m*m)")
     ap.add_argument("--tile", type=int, default=512)
@@ -725,6 +729,9 @@ def main():
     if "three_tier" in want and lowp and args.three_tier_steps > 0:
         legs.append(("three_tier", args.band, band32, lowp, args.three_tier_steps, 1,
                      "f64+f32+" + lowp.replace("fp", "f")))
+    if "three_tier_wide" in want and lowp and args.three_tier_steps > 0 and args.band32_wide > 0:
+        legs.append(("three_tier_wide", args.band, args.band32_wide, lowp, args.three_tier_steps, 1,
+                     "f64+f32+" + lowp.replace("fp", "f")))
     if "fp64" in want and args.fp64_steps > 0:
         legs.append(("fp64", -1, -1, None, args.fp64_steps, 1, "f64"))
     runs = {}
@@ -741,8 +748,9 @@ def main():
         ds = mp.Dataset(ctx, locs, z)
         kriging = {"sites": m_h}
         for name, b64, b32, fmt in (("two_tier", args.band, -1, None), ("three_tier", args.band, band32, lowp),
+                                    ("three_tier_wide", args.band, args.band32_wide, lowp),
                                     ("fp64", -1, -1, None)):
-            if name == "three_tier" and fmt is None:
+            if name.startswith("three_tier") and (fmt is None or b32 <= 0 or name not in runs):
                 continue
             ds.loglik(theta, args.tile, b64, band32=b32, lowp=fmt)
             t0 = time.perf_counter()
@@ -789,7 +797,7 @@ def main():
     }
     if ll64 is not None:
         out["dloglik_rel_vs_fp64"] = head["dloglik_rel_vs_fp64"]
-    for name in ("three_tier", "fp64"):
+    for name in ("three_tier", "three_tier_wide", "fp64"):
         if name in summaries:
             out[name] = summaries[name]
             out["speedup_" + name + "_vs_two_tier"] = summaries[name]["evals_per_s"] / value
