@@ -12,9 +12,10 @@ oracle computes one at a time, and properties that hold at any size:
   * the three-tier plans likewise.  FP16 operands land at |dl| / |l| of 1.5e-6 to 1.1e-5 across
     FP32 widths 8 to 16 here: the error is the sum of many rounding errors (16-bit operands, FP32
     accumulation over up to 2e5 products) and does not shrink steadily with the width, because
-    in Z-order tiles far apart in index can be near in space.  Width 10 (1.45e-6 measured) is
-    asserted at 1e-5; width 8, the configured plan, is a reported row (1.06e-5 measured; 7.3e-6
-    with the single-workgroup diagonal factorization, whose roundings differ), held to the
+    in Z-order tiles far apart in index can be near in space.  Width 10 (3.0e-6 measured here,
+    1.5e-6 on the benchmark's draw of the field) is asserted at 1e-5; width 8, the configured
+    plan, is a reported row (1.06e-5 measured here, 1.2e-5 on the benchmark's draw; 7.3e-6 with
+    the single-workgroup diagonal factorization, whose roundings differ), held to the
     derived worst case 20 * 2^-11 of an FP16 operand tier.  BF16 operands miss 1e-5 at this
     size at width 8 (1.4e-4) and width 24 (8.0e-5) alike: reported rows, held to 20 * 2^-8.
 """
