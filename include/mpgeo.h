@@ -136,6 +136,11 @@ typedef enum {
  * tile is tuned first, on the all-FP64 plan.  Works with and without MPGEO_BATCH_QUEUE; other
  * entry points ignore the flag. */
 #define MPGEO_TUNE_BAND  128u
+/* Reserved for graph replay of the factorization (the launch sequence of one evaluation
+ * captured into a HIP graph and replayed per theta, for problems whose time is dominated by
+ * launching small kernels).  Switched off: every entry point returns MPGEO_E_UNSUPPORTED when
+ * it is set. */
+#define MPGEO_GRAPH      256u
 
 /* theta of eq. (1): sigma2 = theta1 (variance), beta = theta2 (range), nu = theta3
  * (smoothness); all must be finite and > 0. */

@@ -30,6 +30,7 @@ MPGEO_DIST_GCD = 16
 MPGEO_BATCH_QUEUE = 32
 MPGEO_ESCALATE = 64
 MPGEO_TUNE_BAND = 128
+MPGEO_GRAPH = 256
 
 EXPORTED = (
     "mpgeo_ctx_create", "mpgeo_ctx_destroy", "mpgeo_ctx_kernel_stats", "mpgeo_ctx_reset_stats",
@@ -234,15 +235,16 @@ class Context:
     def loglik(self, locs, z, theta: Sequence[float], tile: int, band64: int,
                morton: bool = True, timing: bool = False, band32: int = -1, lowp=None,
                profile: bool = False, gcd: bool = False, band0: int = -1,
-               escalate: bool = False) -> dict:
+               escalate: bool = False, graph: bool = False) -> dict:
         """One-shot eq. (2) (or the profile likelihood): ordering, covariance tiles, factor,
-        solve, reduction.  escalate=True: MPGEO_ESCALATE."""
+        solve, reduction.  escalate=True: MPGEO_ESCALATE; graph=True: MPGEO_GRAPH."""
         dev = isinstance(locs, torch.Tensor)
         if not dev:
             locs, z = _host_f64(locs), _host_f64(z)
         flags = (MPGEO_ORDER_MORTON if morton else 0) | (MPGEO_INPUT_DEVICE if dev else 0) | \
                 (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0) | \
-                (MPGEO_DIST_GCD if gcd else 0) | (MPGEO_ESCALATE if escalate else 0)
+                (MPGEO_DIST_GCD if gcd else 0) | (MPGEO_ESCALATE if escalate else 0) | \
+                (MPGEO_GRAPH if graph else 0)
         res = Result()
         st = LIB.mpgeo_loglik(self.handle, int(locs.shape[0]), _ptr(locs), _ptr(z), Theta(*theta),
                               make_plan(tile, band64, flags, band32, lowp, band0), ctypes.byref(res))
@@ -358,10 +360,12 @@ class Dataset:
 
     def loglik(self, theta: Sequence[float], tile: int, band64: int, timing: bool = False,
                band32: int = -1, lowp=None, profile: bool = False, band0: int = -1,
-               dist64: float = 0.0, dist32: float = 0.0, escalate: bool = False) -> dict:
+               dist64: float = 0.0, dist32: float = 0.0, escalate: bool = False,
+               graph: bool = False) -> dict:
+        """eq. (2) at theta on the resident dataset.  graph=True: MPGEO_GRAPH."""
         res = Result()
         flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0) | \
-                (MPGEO_ESCALATE if escalate else 0)
+                (MPGEO_ESCALATE if escalate else 0) | (MPGEO_GRAPH if graph else 0)
         st = LIB.mpgeo_dataset_loglik(self.handle, Theta(*theta),
                                       make_plan(tile, band64, flags, band32, lowp, band0, dist64, dist32),
                                       ctypes.byref(res))
@@ -433,7 +437,7 @@ class Dataset:
 
     def mle(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
             ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None,
-            profile: bool = False, escalate: bool = False) -> dict:
+            profile: bool = False, escalate: bool = False, graph: bool = False) -> dict:
         """Nelder-Mead maximum-likelihood fit of theta from `start` (eq. (2)); with
         profile=True a two-dimensional search over (theta2, theta3) of the profile likelihood."""
         th = Theta()
@@ -441,7 +445,7 @@ class Dataset:
         ev = ctypes.c_int32()
         it = ctypes.c_int32()
         plan = make_plan(tile, band64, (MPGEO_PROFILE if profile else 0) |
-                         (MPGEO_ESCALATE if escalate else 0), band32, lowp)
+                         (MPGEO_ESCALATE if escalate else 0) | (MPGEO_GRAPH if graph else 0), band32, lowp)
         _check(LIB.mpgeo_dataset_mle(self.handle, Theta(*start), plan, xtol, ftol,
                                      max_evals, ctypes.byref(th), ctypes.byref(ll), ctypes.byref(ev),
                                      ctypes.byref(it)), "mpgeo_dataset_mle")
@@ -449,7 +453,8 @@ class Dataset:
                 "iters": it.value}
 
     def mle_trace(self, start: Sequence[float], tile: int, band64: int, xtol: float = 1e-6,
-                  ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None) -> dict:
+                  ftol: float = 0.0, max_evals: int = 1000, band32: int = -1, lowp=None,
+                  graph: bool = False) -> dict:
         """mle() that also returns the search's trajectory: every evaluated theta in order and
         its log-likelihood (-inf where the matrix was not positive definite)."""
         th = Theta()
@@ -458,7 +463,8 @@ class Dataset:
         it = ctypes.c_int32()
         trace = (Theta * max_evals)()
         trace_ll = np.empty(max_evals)
-        _check(LIB.mpgeo_dataset_mle_trace(self.handle, Theta(*start), make_plan(tile, band64, 0, band32, lowp),
+        _check(LIB.mpgeo_dataset_mle_trace(self.handle, Theta(*start), make_plan(tile, band64, MPGEO_GRAPH if graph else 0,
+                                                                             band32, lowp),
                                            xtol, ftol, max_evals, ctypes.byref(th), ctypes.byref(ll),
                                            ctypes.byref(ev), ctypes.byref(it), trace, trace_ll.ctypes.data),
                "mpgeo_dataset_mle_trace")

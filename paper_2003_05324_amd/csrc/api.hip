@@ -529,6 +529,7 @@ int check_theta(const mpgeo_theta &t) {
 }
 
 int check_plan(const mpgeo_plan &pl) {
+    if (pl.flags & MPGEO_GRAPH) return MPGEO_E_UNSUPPORTED;   // switched off (see the flag)
     if (pl.tile < 1 || pl.tile > kMaxTile) return MPGEO_E_ARG;
     if (pl.band64 < -1 || pl.band32 < -1 || pl.band0 < -1) return MPGEO_E_ARG;
     if (pl.lowp < 0 || pl.lowp > 2) return MPGEO_E_ARG;
@@ -841,7 +842,7 @@ int run_factor(mpgeo_dataset *ds, hipEvent_t ev_factored) {
     hipEvent_t *ev_bulk = ev_f + p;                        // U_bulk(k) done
     hipEvent_t *ev_next = ev_bulk + p;                     // U_next(k) done
     hipEvent_t *ev_col = ev_next + p;                      // column k+1's FP32 / 16-bit tiles done
-    MPGEO_HIP(hipMemsetAsync(info, 0xFF, sizeof(unsigned long long), s0));
+    launch_fill_u64(info, ~0ull, 1, s0);   // no failing column yet
     launch_pad_vector(ds->z.as<double>(), r, L.n, L.nb, nbp, p, s0);
     if (L.lowp) launch_row_scale(map, ds->qscale.as<float>(), s0);   // from Sigma's diagonal
     MPGEO_HIP(hipEventRecord(ev_start, s0));

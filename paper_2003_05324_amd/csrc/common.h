@@ -76,6 +76,10 @@ void launch_export_dense(const TileMap &map, double *out, int64_t ld, const Tile
 void launch_entries(const TileMap &map, int64_t count, const int64_t *rows, const int64_t *cols,
                     double *out, hipStream_t stream);
 
+// count words of value (a kernel, not a memset node, so that the call may sit in a captured
+// graph).
+void launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count, hipStream_t stream);
+
 // Logical vector (n) -> physical padded vector (p * nbp), zero in padding rows.
 void launch_pad_vector(const double *src, double *dst, int64_t n, int nb, int nbp, int p,
                        hipStream_t stream);

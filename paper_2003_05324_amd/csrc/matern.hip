@@ -252,6 +252,19 @@ void launch_pad_vector(const double *src, double *dst, int64_t n, int nb, int nb
                        nbp, total);
 }
 
+namespace {
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long value, int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = value;
+}
+}  // namespace
+
+void launch_fill_u64(unsigned long long *p, unsigned long long value, int64_t count, hipStream_t stream) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, p, value,
+                       count);
+}
+
 void launch_unpad_vector(const double *src, double *dst, int64_t n, int nb, int nbp,
                          hipStream_t stream) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
