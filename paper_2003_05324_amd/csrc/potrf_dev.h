@@ -11,7 +11,8 @@
 //      of L^-1 (right-hand side B[cb + q][t], or the identity inside the diagonal block),
 //      for t >= split the panel rows of L (right-hand side A[t][cb + q], solved against
 //      D^T).  These block rows of B are final, so their FP32 copy is written here too
-//      (when one is asked for);
+//      (when one is asked for); B's entries above the diagonal blocks are zeroed once, at the
+//      start;
 //   3. for rows i >= split and columns j <= i:  M_ij -= sum_l V_il V_jl, with M = B and
 //      V_j = (new B block rows)(:, j) for j < split, M = A and V_j = L(j, block c) otherwise.
 //      This rank-32 update runs on v_mfma_f64_16x16x4_f64, each wave taking 32 x 32 regions,
@@ -30,6 +31,8 @@ namespace {
 constexpr int kBlk = 32;
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // value of v in lane l (l uniform), through the scalar registers
 __device__ inline double readlane(double v, int l) {
@@ -105,6 +108,15 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
     float *B32 = args.linv32;
     if (tid == 0) fail_col = INT_MAX;
     double logdet = 0.0;
+    // the strictly upper part of B (and B32) outside the diagonal blocks is zero: written once
+    // here, column by column, rather than by the panel rows of every block
+    for (int j = kBlk; j < nbp; ++j) {
+        const int top = j / kBlk * kBlk;   // rows 0 .. top-1 lie above column j's diagonal block
+        for (int i = tid; i < top; i += kPotrfThreads) {
+            B[i + (int64_t)j * ld] = 0.0;
+            if (B32) B32[i + (int64_t)j * ld] = 0.0f;
+        }
+    }
     __syncthreads();
 
     for (int cb = 0; cb < nbp; cb += kBlk) {
@@ -126,12 +138,19 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
         // Thread t solves D y = x: x[q] = B[cb + q][t] for t < cb, the unit vector e_(t - cb)
         // inside the diagonal block, A[t][cb + q] for t >= split.  The compiler barrier per
         // column keeps the broadcast reads of D from being issued all at once.
+        // (a thread's 32 entries of B are contiguous in column t: read and written 16 bytes at a
+        // time; cb and ld are multiples of 32, so the vectors are aligned)
         for (int t = tid; t < nbp; t += kPotrfThreads) {
             const bool isB = t < split;
             double y[kBlk];
             if (t < cb) {
+                const d2v *src = reinterpret_cast<const d2v *>(B + cb + (int64_t)t * ld);
 #pragma unroll
-                for (int q = 0; q < kBlk; ++q) y[q] = B[(cb + q) + (int64_t)t * ld];
+                for (int q = 0; q < kBlk / 2; ++q) {
+                    const d2v v = src[q];
+                    y[2 * q] = v.x;
+                    y[2 * q + 1] = v.y;
+                }
             } else if (isB) {
 #pragma unroll
                 for (int q = 0; q < kBlk; ++q) y[q] = (q == t - cb) ? 1.0 : 0.0;
@@ -152,18 +171,18 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
                 asm volatile("" ::: "memory");
             }
             if (isB) {
+                d2v *dst = reinterpret_cast<d2v *>(B + cb + (int64_t)t * ld);
 #pragma unroll
-                for (int l = 0; l < kBlk; ++l) {
-                    B[(cb + l) + (int64_t)t * ld] = y[l];
-                    if (B32) B32[(cb + l) + (int64_t)t * ld] = (float)y[l];
+                for (int l = 0; l < kBlk / 2; ++l) dst[l] = (d2v){y[2 * l], y[2 * l + 1]};
+                if (B32) {
+                    f4v *dst32 = reinterpret_cast<f4v *>(B32 + cb + (int64_t)t * ld);
+#pragma unroll
+                    for (int l = 0; l < kBlk / 4; ++l)
+                        dst32[l] = (f4v){(float)y[4 * l], (float)y[4 * l + 1], (float)y[4 * l + 2], (float)y[4 * l + 3]};
                 }
             } else {
 #pragma unroll
-                for (int l = 0; l < kBlk; ++l) {
-                    A[t + (int64_t)(cb + l) * ld] = y[l];
-                    B[(cb + l) + (int64_t)t * ld] = 0.0;
-                    if (B32) B32[(cb + l) + (int64_t)t * ld] = 0.0f;
-                }
+                for (int l = 0; l < kBlk; ++l) A[t + (int64_t)(cb + l) * ld] = y[l];
             }
         }
         __syncthreads();
