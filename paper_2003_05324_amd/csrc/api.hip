@@ -12,6 +12,7 @@
 // Tiles are kept resident in HBM; no host transfer happens inside the loop.
 #include "common.h"
 #include "../../include/mpgeo.h"
+#include "tune_policy.h"
 
 #include <hip/hip_ext.h>
 
@@ -1935,40 +1936,15 @@ static int batch_tile(mpgeo_ctx *ctx, const mpgeo_instance &in, mpgeo_plan pl, d
     return MPGEO_OK;
 }
 
-// The band tuner (MPGEO_TUNE_BAND).  Its candidate FP64 bands (in tiles), narrowest first; its
-// bar on a candidate's error, relative to the size of the terms that eq. (2) sums (the sizes
-// of n log 2 pi, log|Sigma| and z^T Sigma^-1 z, halved), not to l itself, which passes through
-// zero where those terms cancel (smooth fields of large range), while the rounding error of the
-// factorization does not; the problems of a class it probes; and the relative accuracy of l
-// that it keeps: a problem whose l comes out too small against its terms for the class's error
-// (kTuneMargin * err * terms > kTuneTarget * |l|) is evaluated again all-FP64.
-static const int kTuneBands[] = {0, 1, 2, 4, 8};
-constexpr double kTuneBandBar = 1e-7;
-constexpr int kTuneProbes = 2;
-constexpr double kTuneTarget = 1e-5;
-constexpr double kTuneMargin = 3.0;
-constexpr double kTuneErrFloor = 1e-9;   // a class error measured as zero still counts this much
-
-// Half the summed sizes of eq. (2)'s terms (of the profiled form with MPGEO_PROFILE).
-static double loglik_terms(int64_t n, double logdet, double quad, bool profile) {
-    const double dn = (double)n, l2pi = 1.8378770664093454836;   // log 2 pi
-    if (profile) return 0.5 * (dn * (l2pi + 1.0) + dn * std::fabs(std::log(quad / dn)) + std::fabs(logdet));
-    return 0.5 * (dn * l2pi + std::fabs(logdet) + std::fabs(quad));
-}
-
+// The band tuner (MPGEO_TUNE_BAND): its policy is in tune_policy.h.
 static int batch_queue(mpgeo_ctx *ctx, int64_t count, const mpgeo_instance *inst, const mpgeo_plan &plan,
                        mpgeo_result *out, int32_t *tiles, char *arena, size_t arena_bytes,
                        const int32_t *bands);
 
-// A class of the band tuner: half-octave of n, smoothness to a quarter, range to a half-octave
-// (the two set Sigma's conditioning, hence how narrow a band stays within the bar), tile, path.
+// A class of the band tuner: band_class_key (n, smoothness, range), tile, path, flags.
 static std::string band_class(const mpgeo_instance &in, const mpgeo_plan &pl, int tile, bool queue) {
-    const int bucket = (int)std::floor(2.0 * std::log2((double)in.n));
-    const int nu_q = (int)std::lround(4.0 * in.theta.nu);
-    const int beta_h = (int)std::lround(2.0 * std::log2(in.theta.beta));
-    return std::to_string(bucket) + "/" + std::to_string(nu_q) + "/" + std::to_string(beta_h) + "/" +
-           std::to_string(tile) + "/" + (queue ? "q" : "l") + "/" +
-           std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
+    return band_class_key(in.n, in.theta.beta, in.theta.nu) + "/" + std::to_string(tile) + "/" +
+           (queue ? "q" : "l") + "/" + std::to_string(pl.flags & (MPGEO_PROFILE | MPGEO_DIST_GCD));
 }
 
 // Tunes one class on its probe problems: each is evaluated all-FP64 and at every candidate band
@@ -1980,9 +1956,7 @@ static int band_probe(mpgeo_ctx *ctx, const std::vector<const mpgeo_instance *> 
                       bool queue, double *probe_out, TunedBand *tb) {
     int64_t pmax = 0;
     for (const mpgeo_instance *in : probes) pmax = std::max<int64_t>(pmax, (in->n + tile - 1) / tile);
-    std::vector<int> cand{-1};
-    for (int b : kTuneBands)
-        if (b < pmax - 1) cand.push_back(b);
+    const std::vector<int> cand = band_candidates(pmax);
     const size_t np = probes.size(), nc = cand.size();
     std::vector<mpgeo_result> r(np * nc);   // [candidate][probe]
     pl.tile = tile;
@@ -2016,23 +1990,11 @@ static int band_probe(mpgeo_ctx *ctx, const std::vector<const mpgeo_instance *> 
                 o.info = info == ~0ull ? -1 : (int64_t)info;
             }
     }
-    *tb = TunedBand{-1, 0.0};
-    const bool profile = (pl.flags & MPGEO_PROFILE) != 0;
-    for (size_t k = 0; k < np; ++k)
-        if (r[k].info >= 0) return MPGEO_OK;   // a probe is not positive definite even all-FP64
-    for (size_t c = 1; c < nc; ++c) {
-        double worst = 0.0;
-        bool ok = true;
-        for (size_t k = 0; k < np && ok; ++k) {
-            const mpgeo_result &f = r[k], &m = r[c * np + k];
-            ok = m.info < 0;
-            worst = std::max(worst, std::fabs(m.loglik - f.loglik) / loglik_terms(probes[k]->n, f.logdet, f.quad, profile));
-        }
-        if (ok && worst <= kTuneBandBar) {
-            *tb = TunedBand{cand[c], std::max(worst, kTuneErrFloor)};
-            break;
-        }
-    }
+    std::vector<ProbeResult> pr(r.size());
+    for (size_t e = 0; e < r.size(); ++e) pr[e] = ProbeResult{r[e].loglik, r[e].logdet, r[e].quad, r[e].info < 0};
+    std::vector<int64_t> sizes(np);
+    for (size_t k = 0; k < np; ++k) sizes[k] = probes[k]->n;
+    choose_band(cand, sizes, pr, (pl.flags & MPGEO_PROFILE) != 0, &tb->band, &tb->err);
     return MPGEO_OK;
 }
 
@@ -2078,9 +2040,7 @@ static std::vector<int64_t> accuracy_reruns(int64_t count, const mpgeo_instance 
     std::vector<int64_t> redo;
     for (int64_t i = 0; i < count; ++i) {
         const mpgeo_result &o = out[i];
-        if (o.info >= 0 || o.band64 < 0 || err[(size_t)i] <= 0.0) continue;
-        if (kTuneMargin * err[(size_t)i] * loglik_terms(inst[i].n, o.logdet, o.quad, profile) >
-            kTuneTarget * std::fabs(o.loglik))
+        if (needs_fp64_rerun(inst[i].n, o.loglik, o.logdet, o.quad, o.info < 0, o.band64, err[(size_t)i], profile))
             redo.push_back(i);
     }
     return redo;

@@ -51,3 +51,20 @@ def test_blocked_diagonal_factorization_plan():
         run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
         print(run.stdout)
         assert run.returncode == 0, run.stdout[-2000:]
+
+
+def test_band_tuner_policy():
+    # the FP64-band tuner's policy (tune_policy.h): the terms scale of eq. (2), the class key, the
+    # candidate bands, the choice from the probes' results and the all-FP64 re-evaluation of a
+    # problem whose l cancels (tests/tune_policy_check.cpp, host code only)
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ is not available")
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = os.path.join(tmp, "tune_policy_check")
+        build = subprocess.run([gxx, "-O2", "-std=c++17", "-Wall", os.path.join(HERE, "tune_policy_check.cpp"),
+                                "-o", exe], capture_output=True, text=True, timeout=300)
+        assert build.returncode == 0, build.stderr[-2000:]
+        run = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        print(run.stdout)
+        assert run.returncode == 0, run.stdout[-2000:]
