@@ -237,7 +237,7 @@ class Context:
                profile: bool = False, gcd: bool = False, band0: int = -1,
                escalate: bool = False, graph: bool = False) -> dict:
         """One-shot eq. (2) (or the profile likelihood): ordering, covariance tiles, factor,
-        solve, reduction.  escalate=True: MPGEO_ESCALATE; graph=True: MPGEO_GRAPH."""
+        solve, reduction.  escalate=True: MPGEO_ESCALATE; graph=True: MPGEO_GRAPH (reserved, rejected)."""
         dev = isinstance(locs, torch.Tensor)
         if not dev:
             locs, z = _host_f64(locs), _host_f64(z)
@@ -362,7 +362,7 @@ class Dataset:
                band32: int = -1, lowp=None, profile: bool = False, band0: int = -1,
                dist64: float = 0.0, dist32: float = 0.0, escalate: bool = False,
                graph: bool = False) -> dict:
-        """eq. (2) at theta on the resident dataset.  graph=True: MPGEO_GRAPH."""
+        """eq. (2) at theta on the resident dataset.  graph=True: MPGEO_GRAPH (reserved, rejected)."""
         res = Result()
         flags = (MPGEO_TIMING if timing else 0) | (MPGEO_PROFILE if profile else 0) | \
                 (MPGEO_ESCALATE if escalate else 0) | (MPGEO_GRAPH if graph else 0)
