@@ -260,8 +260,17 @@ __device__ void potrf_tile_body(const PotrfArgs &args) {
         for (int t = tid; t < nbp; t += kPotrfThreads) rs[t] = args.r[t];
         __syncthreads();
         for (int i = tid; i < nbp; i += kPotrfThreads) {
+            // the row of L^-1 read eight entries ahead of the (in-order) accumulation
             double s = 0.0;
-            for (int j = 0; j <= i; ++j) s += B[i + (int64_t)j * ld] * rs[j];
+            int j = 0;
+            for (; j + 8 <= i + 1; j += 8) {
+                double b[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) b[u] = B[i + (int64_t)(j + u) * ld];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += b[u] * rs[j + u];
+            }
+            for (; j <= i; ++j) s += B[i + (int64_t)j * ld] * rs[j];
             args.y[i] = s;
             quad += s * s;
         }
